@@ -1,0 +1,225 @@
+"""Oracle fit: limited-memory BFGS on -Phi with a strong-Wolfe line search, and a
+dense damped Newton solve for tiny non-separable problems.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 5.2 fixes the protocol: start from theta = 0 (the fully ambiguous
+diagram), maximise Phi with L-BFGS [Liu and Nocedal 1989], gauge fixed by
+theta_N = 0 (Remark 4.3), a fixed iteration budget.  The paper names no memory
+size, line search or tolerance; this oracle takes memory m = 10, initial inverse
+Hessian gamma*I with gamma = s.y / y.y, a first trial step 1/||g||_2 when the
+memory is empty and 1 otherwise, and the strong-Wolfe bracketing/zoom line search
+of Nocedal and Wright (Algorithms 3.5 and 3.6) with c1 = 1e-4, c2 = 0.9, cubic
+interpolation, doubling extrapolation and at most 20 evaluations per search.
+A pair (s, y) is stored only when s.y > 1e-10 ||s|| ||y||.  A failed search
+clears the memory and retries once from steepest descent.  The fit stops at the
+first accepted iterate whose hard-assignment accuracy reaches the target, at the
+iteration budget, or when ||g||_inf <= gtol.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C1 = 1e-4
+C2 = 0.9
+MAX_LS_EVALS = 20
+CURV_EPS = 1e-10
+
+
+def _cubic_min(a, fa, da, b, fb, db):
+    """Minimiser of the cubic interpolating (a, fa, da), (b, fb, db)
+    (Nocedal and Wright eq. 3.59), kept inside the middle 80% of [a, b];
+    bisection when the cubic has no admissible minimiser."""
+    lo, hi = min(a, b), max(a, b)
+    width = hi - lo
+    mid = 0.5 * (a + b)
+    d1 = da + db - 3.0 * (fa - fb) / (a - b)
+    disc = d1 * d1 - da * db
+    if not (disc >= 0.0):
+        return mid
+    d2 = math.copysign(math.sqrt(disc), b - a)
+    den = db - da + 2.0 * d2
+    if den == 0.0:
+        return mid
+    t = b - (b - a) * ((db + d2 - d1) / den)
+    if not (lo + 0.1 * width <= t <= hi - 0.1 * width):
+        return mid
+    return t
+
+
+def _line_search(evalf, x, f0, g0, d, t1):
+    """Strong-Wolfe search along d from x.  evalf(x) -> (f, g).  Returns
+    (ok, t, x_t, f_t, g_t, n_evals)."""
+    dphi0 = float(g0.ravel() @ d.ravel())
+    evals = 0
+    best = None  # (t, x, f, g, dphi) with sufficient decrease, lowest f
+
+    def trial(t):
+        xt = x + t * d
+        ft, gt = evalf(xt)
+        return xt, ft, gt, float(gt.ravel() @ d.ravel())
+
+    def zoom(lo, hi):
+        nonlocal evals
+        while evals < MAX_LS_EVALS:
+            t = _cubic_min(lo[0], lo[2], lo[4], hi[0], hi[2], hi[4])
+            xt, ft, gt, dt = trial(t)
+            evals += 1
+            if ft > f0 + C1 * t * dphi0 or ft >= lo[2]:
+                hi = (t, xt, ft, gt, dt)
+            else:
+                if abs(dt) <= -C2 * dphi0:
+                    return True, (t, xt, ft, gt, dt)
+                if dt * (hi[0] - lo[0]) >= 0.0:
+                    hi = lo
+                lo = (t, xt, ft, gt, dt)
+        return False, lo
+
+    prev = (0.0, x, f0, g0, dphi0)
+    t = t1
+    while evals < MAX_LS_EVALS:
+        xt, ft, gt, dt = trial(t)
+        evals += 1
+        cur = (t, xt, ft, gt, dt)
+        if ft > f0 + C1 * t * dphi0 or (evals > 1 and ft >= prev[2]):
+            ok, res = zoom(prev, cur)
+            break
+        if abs(dt) <= -C2 * dphi0:
+            ok, res = True, cur
+            break
+        if dt >= 0.0:
+            ok, res = zoom(cur, prev)
+            break
+        prev = cur
+        t = 2.0 * t
+    else:
+        ok, res = False, prev
+    if not ok:
+        # fall back to the lowest point that still has sufficient decrease
+        if res[0] > 0.0:
+            ok = True
+        best = res
+    else:
+        best = res
+    t, xt, ft, gt, _ = best
+    return ok, t, xt, ft, gt, evals
+
+
+def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=2000,
+              history=10, gauge="last", gtol=0.0, callback=None):
+    """Maximise Phi (minimise f = -Phi) from theta0.
+
+    objective(theta) -> (Phi, grad Phi);  accuracy(theta) -> Acc in [0, 1] or None.
+    Returns a dict with theta, phi, acc, iters, evals, status and per-iteration
+    records (phi, acc, evals, t) for trajectory comparisons.
+    """
+    from . import gauge_project
+
+    x = gauge_project(theta0, gauge) if gauge == "centered" else np.array(theta0, np.float64)
+    if gauge == "last":
+        x[-1, :] = 0.0
+
+    n_evals = 0
+
+    def evalf(xx):
+        nonlocal n_evals
+        n_evals += 1
+        phi, g = objective(xx)
+        return -phi, gauge_project(-g, gauge)
+
+    f, g = evalf(x)
+    S, Y, R = [], [], []
+    gamma = 1.0
+    it = 0
+    records = []
+    acc = accuracy(x) if accuracy is not None else None
+    status = "budget"
+    if acc is not None and acc >= target_acc:
+        status = "target"
+        return dict(theta=x, phi=-f, acc=acc, iters=0, evals=n_evals, status=status,
+                    records=records)
+    d = -g
+    reset_tried = False
+    while it < max_iter:
+        gnorm = float(np.sqrt(np.sum(g * g)))
+        if gnorm == 0.0 or float(np.max(np.abs(g))) <= gtol:
+            status = "gtol"
+            break
+        t1 = 1.0 / gnorm if not S else 1.0
+        dphi0 = float(g.ravel() @ d.ravel())
+        if not (dphi0 < 0.0):
+            S, Y, R = [], [], []
+            d = -g
+            t1 = 1.0 / gnorm
+        ok, t, xt, ft, gt, ev = _line_search(evalf, x, f, g, d, t1)
+        if not ok:
+            if S and not reset_tried:
+                S, Y, R = [], [], []
+                d = -g
+                reset_tried = True
+                continue
+            status = "linesearch"
+            break
+        reset_tried = False
+        s = t * d
+        y = gt - g
+        sy = float(s.ravel() @ y.ravel())
+        if sy > CURV_EPS * math.sqrt(float(s.ravel() @ s.ravel())) * math.sqrt(float(y.ravel() @ y.ravel())):
+            if len(S) == history:
+                S.pop(0), Y.pop(0), R.pop(0)
+            S.append(s)
+            Y.append(y)
+            R.append(1.0 / sy)
+            gamma = sy / float(y.ravel() @ y.ravel())
+        x, f, g = xt, ft, gt
+        it += 1
+        acc = accuracy(x) if accuracy is not None else None
+        records.append(dict(phi=-f, acc=acc, evals=ev, t=t))
+        if callback is not None:
+            callback(it, x, -f, acc)
+        if acc is not None and acc >= target_acc:
+            status = "target"
+            break
+        # two-loop recursion: d = -H g
+        q = g.copy()
+        alphas = []
+        for sj, yj, rj in zip(reversed(S), reversed(Y), reversed(R)):
+            a = rj * float(sj.ravel() @ q.ravel())
+            alphas.append(a)
+            q = q - a * yj
+        r = (gamma if S else 1.0) * q
+        for (sj, yj, rj), a in zip(zip(S, Y, R), reversed(alphas)):
+            b = rj * float(yj.ravel() @ r.ravel())
+            r = r + (a - b) * sj
+        d = -r
+    return dict(theta=x, phi=-f, acc=acc, iters=it, evals=n_evals, status=status,
+                records=records)
+
+
+def newton_fit(theta0, objective, hessian, *, gauge_last=True, tol=1e-12, max_iter=100):
+    """Damped Newton ascent of Phi on the gauge-fixed subspace theta_N = 0
+    (Proposition 4.11 gives a unique maximiser there when no exact reconstruction
+    exists).  objective(theta) -> (Phi, grad); hessian(theta) -> (NK x NK)."""
+    x = np.array(theta0, np.float64)
+    N, K = x.shape
+    if gauge_last:
+        x[-1, :] = 0.0
+    free = np.arange((N - 1) * K) if gauge_last else np.arange(N * K)
+    for _ in range(max_iter):
+        phi, g = objective(x)
+        gv = g.reshape(-1)[free]
+        if np.max(np.abs(gv)) <= tol:
+            break
+        Hm = hessian(x)[np.ix_(free, free)]
+        step = np.linalg.solve(Hm, -gv)  # ascent direction for concave Phi
+        t = 1.0
+        while t > 1e-12:
+            xn = x.copy()
+            xn.reshape(-1)[free] += t * step
+            if objective(xn)[0] >= phi + 1e-4 * t * float(gv @ step):
+                break
+            t *= 0.5
+        x = xn
+    return x
