@@ -1,0 +1,169 @@
+/*
+ * pd.h -- C ABI of the MI355X (gfx950) polynomial-diagram library (libpd.so).
+ *
+ * Paper: Bourne, Buze, Gallouet, Merigot, "Polynomial diagrams for
+ * microstructure modelling" (arXiv 2605.20816).
+ *
+ * The library fits Legendre polynomial diagrams to labelled pixel grain maps.
+ * For a grain map G : Omega -> {0..N-1} on an H x W pixel grid, degree d and
+ * eps > 0, with K = (d+1)(d+2)/2 features per grain and parameters
+ * theta in R^{N x K}, it evaluates
+ *   Phi(theta) = (1/n) sum_x log p_{G(x)}(x),
+ *   p_i(x)     = exp(-h_i(x)/eps) / sum_j exp(-h_j(x)/eps),
+ *   h_i(x)     = theta_i . psi(x),   psi_(a,b)(x) = P_a(x1) P_b(x2)
+ * (Section 2.2 eq. log-res, Section 3.3 eq. h-degree-d-legendre), its gradient
+ * (Proposition 4.4, eq. grad), the hard assignment F_theta (Section 2.1) and
+ * maximises Phi with L-BFGS (Section 5.2).  The sum form L = n * Phi.
+ *
+ * Conventions (fixed here where the paper leaves a choice):
+ *   - pixel (r, c) has row-major index r*W + c and centre
+ *     x1 = (2c + 1 - W)/W, x2 = (2r + 1 - H)/H (Section 2.1, axes rescaled
+ *     independently for rectangles, Section 3.3);
+ *   - grains and labels are 0-based; ties in F_theta go to the smallest index;
+ *   - feature alpha = (a, b) of total degree k sits at index k(k+1)/2 + b
+ *     (degree-graded, then b ascending: d = 1 gives 1, x, y);
+ *   - theta is N x K row-major FP64 (grain i's K coefficients contiguous).
+ *
+ * Memory: every pointer is a DEVICE pointer unless marked (host).  The caller
+ * owns all buffers; the library never returns memory for the caller to free
+ * (other than the context itself).  A context owns its device workspace, which
+ * it grows on demand and frees in pd_destroy.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * pd_features, pd_objective_grad, pd_assign and the warm-start calls are
+ * stream-ordered and asynchronous; pd_fit returns when every map has stopped.
+ *
+ * Errors: arguments that can be checked on the host are checked before any
+ * launch (PD_ERR_INVALID_ARG, message in pd_last_error).  HIP failures return
+ * PD_ERR_HIP with hipGetErrorString's text.  A context is not thread-safe.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PD_OK = 0,
+  PD_ERR_INVALID_ARG = 1,
+  PD_ERR_UNSUPPORTED = 2,
+  PD_ERR_OOM = 3,
+  PD_ERR_HIP = 4,
+  PD_ERR_NONFINITE = 5,
+  PD_ERR_NOT_CONVERGED = 6
+} pd_status;
+
+/* Arithmetic of the logit/exp/gradient contractions.  Global reductions of Phi
+ * and grad Phi are FP64 in every mode.
+ *   PD_FP64: everything FP64 (the paper's precision, Section 5.1).
+ *   PD_FP32: FP32 logits, FP32 exp/log-sum-exp, FP64 reductions.
+ *   PD_BF16: logit and gradient contractions on BF16 matrix cores (hi/lo split
+ *            operands, FP32 accumulation), FP32 log-sum-exp, FP64 reductions. */
+typedef enum { PD_FP64 = 0, PD_FP32 = 1, PD_BF16 = 2 } pd_precision;
+
+/* Gauge of the fit (Lemma 4.2, Remark 4.3).  LAST_ZERO keeps theta_{N-1} = 0
+ * (the paper's choice, Section 5.1); CENTERED keeps sum_i theta_i = 0. */
+typedef enum { PD_GAUGE_LAST_ZERO = 0, PD_GAUGE_CENTERED = 1, PD_GAUGE_NONE = 2 } pd_gauge;
+
+/* Start of the fit: the caller's theta, theta = 0 (Section 5.2), or the learned
+ * warm start (per-grain descriptors -> MLP -> scaled theta). */
+typedef enum { PD_INIT_GIVEN = 0, PD_INIT_ZERO = 1, PD_INIT_MLP = 2 } pd_init;
+
+#define PD_MAX_DEGREE 8
+
+/* One grain map.  labels: DEVICE int32[height*width], values in [0, n_grains)
+ * (precondition of the hot calls; pd_validate checks it).  n_grains >= 2
+ * (Section 2.1 takes N > 1), 1 <= degree <= PD_MAX_DEGREE, eps > 0 finite. */
+typedef struct {
+  int32_t height, width;
+  const int32_t *labels;
+  int32_t n_grains, degree;
+  double eps;
+} pd_problem;
+
+typedef struct pd_ctx pd_ctx;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+pd_status pd_create(int device, pd_ctx **out);
+/* Free the context and its workspace.  NULL is ignored. */
+void pd_destroy(pd_ctx *ctx);
+/* Text of the last non-OK status of this context ("" if none). */
+const char *pd_last_error(const pd_ctx *ctx);
+/* K_d = (d+1)(d+2)/2 (Section 3.1); 0 for d outside [0, PD_MAX_DEGREE]. */
+int32_t pd_num_features(int32_t degree);
+
+/* Design matrix eta_L(Omega) of Section 3.3: out[alpha*n + j] = psi_alpha(x_j),
+ * n = height*width, alpha in the order above.  out_prec PD_FP64 writes doubles
+ * (bit-identical to the canonical recurrence (m+1)P_{m+1} = fma((2m+1)t, P_m,
+ * -m P_{m-1}) followed by one correctly rounded division, and one rounded product
+ * P_a(x1)*P_b(x2)); PD_FP32 writes floats (the FP64 values rounded); PD_BF16
+ * writes two bf16 planes, hi = bf16(psi) then lo = bf16(psi - hi), each K x n. */
+pd_status pd_features(pd_ctx *ctx, int32_t height, int32_t width, int32_t degree,
+                      pd_precision out_prec, void *out, void *stream);
+
+/* Check that every label of each map lies in [0, n_grains).  Synchronous;
+ * returns PD_ERR_INVALID_ARG naming the first bad map. */
+pd_status pd_validate(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                      void *stream);
+
+/* Objective Phi (eq. Phi) and gradient (eq. grad) of n_probs maps in one call.
+ *   theta    (host array of n_probs DEVICE pointers) N_p x K_p FP64 each;
+ *   phi_out  DEVICE double[n_probs]: Phi of each map (mean, <= 0);
+ *   grad_out (host array; NULL, or entries NULL, to skip the gradient) DEVICE
+ *            N_p x K_p FP64 each: grad Phi, not gauge-projected.
+ * Non-finite theta yields NaN outputs.  Labels outside [0, N) yield NaN Phi. */
+pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                            const double *const *theta /*host*/, double *phi_out,
+                            double *const *grad_out /*host*/, pd_precision prec,
+                            void *stream);
+
+/* Hard assignment F_theta (Section 2.1, smallest index on ties) in FP64 with the
+ * canonical score order f = theta_i0, f = fma(theta_ik, psi_k, f), k = 1..K-1,
+ * so labels are bit-reproducible.  labels_out (host array; entries may be NULL)
+ * DEVICE int32[n] each (-1 where a score is NaN); n_correct_out DEVICE
+ * int64[n_probs]: #{x : F(x) = G(x)} (Acc = n_correct / n, Section 2.2). */
+pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                    const double *const *theta /*host*/, int32_t *const *labels_out /*host*/,
+                    int64_t *n_correct_out, void *stream);
+
+/* L-BFGS fit (Section 5.2) of n_probs maps at once, on the device.
+ * Minimises -Phi with memory `history`, strong-Wolfe line search (c1 = 1e-4,
+ * c2 = 0.9, cubic zoom, <= 20 evaluations per search), first trial step
+ * 1/||g||_2 when the memory is empty and 1 otherwise; stops a map at the first
+ * accepted iterate with FP64 accuracy >= target_acc, at max_iter iterations, or
+ * when ||g||_inf <= gtol.  Accuracy is checked every check_every iterations. */
+typedef struct {
+  pd_precision prec;      /* arithmetic of the objective/gradient evaluations   */
+  pd_gauge gauge;         /* PD_GAUGE_LAST_ZERO (paper) or PD_GAUGE_CENTERED     */
+  pd_init init;           /* PD_INIT_GIVEN uses theta_inout as the start         */
+  int32_t history;        /* L-BFGS memory, 1..64 (default 10)                   */
+  int32_t max_iter;       /* iteration budget (paper: 1000 or 2000)              */
+  double target_acc;      /* stop at Acc >= target_acc (e.g. 0.99); > 1 disables */
+  double gtol;            /* stop at ||grad||_inf <= gtol (0 disables)           */
+  int32_t check_every;    /* accuracy / stop-flag poll period in iterations      */
+  const void *mlp;        /* PD_INIT_MLP: a pd_mlp (see below), else NULL        */
+} pd_fit_opts;
+
+typedef struct {
+  int32_t status;         /* 0 target reached, 1 budget, 2 gtol, 3 line search failed,
+                             4 non-finite                                          */
+  int32_t iters, evals;   /* accepted iterations, objective+gradient evaluations  */
+  double phi, acc;        /* final Phi and accuracy                               */
+  double seconds_total;   /* wall time of this pd_fit call                        */
+  double seconds_to_target; /* wall time until Acc >= target_acc (-1 if never)    */
+} pd_fit_report;
+
+/* theta_inout: host array of DEVICE N_p x K_p FP64 pointers (start if
+ * PD_INIT_GIVEN; result on return).  reports: host array of n_probs. */
+pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                 double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
+                 pd_fit_report *reports /*host*/, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PD_H */

@@ -1,0 +1,241 @@
+"""Python binding of libpd, the MI355X (gfx950) polynomial-diagram library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libpd.so`` (built by ``paper_2605_20816_amd.build``).  Torch tensors
+provide device memory and the current stream.  If the library is missing this
+module raises on import of any entry point; there is no fallback path.
+
+Paper: Bourne, Buze, Gallouet, Merigot, "Polynomial diagrams for microstructure
+modelling" (arXiv 2605.20816).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpd.so")
+
+PD_OK = 0
+STATUS = {0: "PD_OK", 1: "PD_ERR_INVALID_ARG", 2: "PD_ERR_UNSUPPORTED", 3: "PD_ERR_OOM",
+          4: "PD_ERR_HIP", 5: "PD_ERR_NONFINITE", 6: "PD_ERR_NOT_CONVERGED"}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+GAUGE = {"last": 0, "centered": 1, "none": 2}
+INIT = {"given": 0, "zero": 1, "mlp": 2}
+FIT_STATUS = {0: "target", 1: "budget", 2: "gtol", 3: "linesearch", 4: "nonfinite"}
+MAX_DEGREE = 8
+
+
+class PdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("labels", ctypes.c_void_p), ("n_grains", ctypes.c_int32),
+                ("degree", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+class _FitOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("gauge", ctypes.c_int), ("init", ctypes.c_int),
+                ("history", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("target_acc", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+
+
+class _FitReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("phi", ctypes.c_double), ("acc", ctypes.c_double),
+                ("seconds_total", ctypes.c_double), ("seconds_to_target", ctypes.c_double)]
+
+
+_lib = None
+
+# Every symbol the C ABI declares, with its ctypes signature.
+_SIGS = {
+    "pd_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "pd_destroy": (None, [ctypes.c_void_p]),
+    "pd_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pd_num_features": (ctypes.c_int32, [ctypes.c_int32]),
+    "pd_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_validate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                   ctypes.c_void_p]),
+    "pd_objective_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                         ctypes.c_void_p]),
+    "pd_assign": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_fit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_FitOpts),
+                              ctypes.POINTER(_FitReport), ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libpd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_20816_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def num_features(d: int) -> int:
+    """Section 3.1: K_d = (d+1)(d+2)/2."""
+    return int(lib().pd_num_features(int(d)))
+
+
+@dataclass
+class Problem:
+    """One grain map on the device: labels int32 (H*W,) values in [0, N)."""
+    labels: torch.Tensor
+    H: int
+    W: int
+    N: int
+    d: int
+    eps: float
+
+    def c(self) -> _Problem:
+        lab = self.labels
+        if not (lab.is_cuda and lab.dtype == torch.int32 and lab.is_contiguous()):
+            raise ValueError("labels must be a contiguous int32 CUDA tensor")
+        if lab.numel() != self.H * self.W:
+            raise ValueError("labels must have H*W entries")
+        return _Problem(self.H, self.W, lab.data_ptr(), self.N, self.d, float(self.eps))
+
+
+def _check_thetas(probs, thetas):
+    if len(probs) != len(thetas):
+        raise ValueError("one theta per map")
+    for p, t in zip(probs, thetas):
+        K = num_features(p.d)   # 0 for an invalid degree: the library reports it
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("theta must be a contiguous float64 CUDA tensor")
+        if K and tuple(t.shape) != (p.N, K):
+            raise ValueError(f"theta must have shape (N, K) = ({p.N}, {K})")
+
+
+def _ptrs(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for k, t in enumerate(ts):
+        arr[k] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """A libpd context on one device (owns the library's workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        st = lib().pd_create(int(device), ctypes.byref(self._h))
+        if st != PD_OK:
+            raise PdError(st, "pd_create failed")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().pd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != PD_OK:
+            raise PdError(st, lib().pd_last_error(self._h).decode())
+
+    def features(self, H, W, d, prec="fp64", stream=None):
+        """Design matrix eta_L(Omega) (K x n); 'bf16' returns (2, K, n) raw bf16 bits."""
+        K = num_features(d)
+        n = H * W
+        dev = torch.device("cuda", self.device)
+        if prec == "fp64":
+            out = torch.empty((K, n), dtype=torch.float64, device=dev)
+        elif prec == "fp32":
+            out = torch.empty((K, n), dtype=torch.float32, device=dev)
+        else:
+            out = torch.empty((2, K, n), dtype=torch.int16, device=dev)
+        self._check(lib().pd_features(self._h, H, W, d, PREC[prec], ctypes.c_void_p(out.data_ptr()),
+                                      _stream(stream)))
+        return out
+
+    def validate(self, probs, stream=None):
+        arr = (_Problem * len(probs))(*[p.c() for p in probs])
+        self._check(lib().pd_validate(self._h, arr, len(probs), _stream(stream)))
+
+    def objective_grad(self, probs, thetas, prec="fp64", grad=True, phi_out=None,
+                       grad_out=None, stream=None):
+        """Phi and grad Phi for each map.  Returns (phi (n,) float64, [grad N x K])."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = thetas[0].device
+        _check_thetas(probs, thetas)
+        phi = phi_out if phi_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+        if grad:
+            grads = grad_out if grad_out is not None else [torch.empty_like(t) for t in thetas]
+            gp = _ptrs(grads)
+        else:
+            grads, gp = None, None
+        self._check(lib().pd_objective_grad(self._h, arr, n, _ptrs(thetas),
+                                            ctypes.c_void_p(phi.data_ptr()), gp, PREC[prec],
+                                            _stream(stream)))
+        return phi, grads
+
+    def assign(self, probs, thetas, labels_out=True, stream=None):
+        """F_theta per map and #correct.  Returns ([labels int32 (n,)] or None, counts int64)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = thetas[0].device
+        _check_thetas(probs, thetas)
+        cnt = torch.empty(n, dtype=torch.int64, device=dev)
+        outs = None
+        lp = None
+        if labels_out:
+            outs = [torch.empty(p.H * p.W, dtype=torch.int32, device=dev) for p in probs]
+            lp = _ptrs(outs)
+        self._check(lib().pd_assign(self._h, arr, n, _ptrs(thetas), lp,
+                                    ctypes.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return outs, cnt
+
+    def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
+            max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, stream=None):
+        """Device L-BFGS fit of every map; thetas are updated in place.
+        Returns a list of report dicts."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
+                        check_every, None if mlp is None else mlp.handle())
+        reps = (_FitReport * n)()
+        self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
+                                 _stream(stream)))
+        return [dict(status=FIT_STATUS.get(r.status, r.status), iters=r.iters, evals=r.evals,
+                     phi=r.phi, acc=r.acc, seconds_total=r.seconds_total,
+                     seconds_to_target=r.seconds_to_target) for r in reps]

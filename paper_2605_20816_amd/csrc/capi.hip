@@ -1,0 +1,390 @@
+// capi.hip -- C ABI of libpd: context, argument checks, workspace planning and
+// the launches of pd_features, pd_validate, pd_objective_grad and pd_assign.
+#include "pd.h"
+#include "pd_host.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+pd_status pd_fail(pd_ctx *c, pd_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+pd_status pd_check_problem(pd_ctx *ctx, const pd_problem &p, int idx) {
+  char buf[256];
+  if (p.height < 1 || p.width < 1) {
+    snprintf(buf, sizeof buf, "map %d: height and width must be >= 1 (got %d x %d)", idx,
+             p.height, p.width);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  if ((long long)p.height * p.width > (1LL << 31) - 1) {
+    snprintf(buf, sizeof buf, "map %d: more than 2^31-1 pixels", idx);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  if (p.n_grains < 2) {
+    snprintf(buf, sizeof buf, "map %d: n_grains must be >= 2 (got %d)", idx, p.n_grains);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  if (p.n_grains > (1 << 20)) {
+    snprintf(buf, sizeof buf, "map %d: n_grains above 2^20 is not supported", idx);
+    return pd_fail(ctx, PD_ERR_UNSUPPORTED, buf);
+  }
+  if (p.degree < 1 || p.degree > PD_MAX_DEGREE) {
+    snprintf(buf, sizeof buf, "map %d: degree must be in [1, %d] (got %d)", idx, PD_MAX_DEGREE,
+             p.degree);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  if (!finite_pos(p.eps)) {
+    snprintf(buf, sizeof buf, "map %d: eps must be finite and > 0", idx);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  if (p.labels == nullptr) {
+    snprintf(buf, sizeof buf, "map %d: labels is NULL", idx);
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, buf);
+  }
+  return PD_OK;
+}
+
+pd_status pd_reserve(pd_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return PD_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+  if (ctx->ws) hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_cap = 0;
+  const size_t want = bytes + bytes / 4 + (1 << 20);
+  e = hipMalloc((void **)&ctx->ws, want);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return pd_fail(ctx, PD_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  ctx->ws_cap = want;
+  return PD_OK;
+}
+
+// Tile of the gradient kernel: aim for about `target_waves` waves per map, each
+// over at least 64 pixels, tiles at most 256 columns wide.
+static void choose_tiles(int H, int W, int Npad, int target_waves, int &tr, int &tc) {
+  const long long groups = Npad / PD_WAVE;
+  long long px = (long long)H * W * groups / target_waves;
+  if (px < 64) px = 64;
+  tc = std::min(W, 256);
+  long long rows = px / tc;
+  if (rows < 1) rows = 1;
+  if (rows > H) rows = H;
+  tr = (int)rows;
+}
+
+void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec) {
+  P.n = n;
+  P.prec = prec;
+  P.maps.assign(n, MapDev{});
+  P.reg.assign(n, MapRegions{});
+  P.offA.assign(n + 1, 0);
+  P.offB.assign(n + 1, 0);
+  P.offP.assign(n + 1, 0);
+  P.offR.assign(n + 1, 0);
+  P.max_hw = 0;
+  P.max_k = 0;
+  const size_t tsz = prec == 0 ? 8 : 4;
+  for (int p = 0; p < n; ++p) {
+    const pd_problem &q = probs[p];
+    MapDev &M = P.maps[p];
+    MapRegions &R = P.reg[p];
+    M.H = q.height;
+    M.W = q.width;
+    M.N = q.n_grains;
+    M.d = q.degree;
+    M.K = (q.degree + 1) * (q.degree + 2) / 2;
+    M.DP = q.degree + 1;
+    M.Npad = (q.n_grains + PD_WAVE - 1) / PD_WAVE * PD_WAVE;
+    M.segs = (q.width + PD_WAVE - 1) / PD_WAVE;
+    M.eps = q.eps;
+    M.grad_scale = 1.0 / (q.eps * (double)q.height * (double)q.width);
+    M.labels = q.labels;
+    choose_tiles(M.H, M.W, M.Npad, P.target_waves, M.tile_rows, M.tile_cols);
+    M.tiles_r = (M.H + M.tile_rows - 1) / M.tile_rows;
+    M.tiles_c = (M.W + M.tile_cols - 1) / M.tile_cols;
+    M.a_items = M.H * M.segs;
+    M.b_items = M.tiles_r * M.tiles_c * (M.Npad / PD_WAVE);
+    M.r_items = (M.N * M.K + PD_BLOCK - 1) / PD_BLOCK;
+    const long long n_px = (long long)M.H * M.W;
+    R.tx64 = L.take(sizeof(double) * M.W * M.DP);
+    R.ty64 = L.take(sizeof(double) * M.H * M.DP);
+    R.txT = L.take(tsz * M.W * M.DP);
+    R.thc = L.take(sizeof(double) * M.N * M.K);
+    R.C = L.take(tsz * (size_t)M.H * M.Npad * M.DP);
+    R.lse = L.take(tsz * n_px);
+    R.part_l = L.take(sizeof(double) * M.a_items);
+    R.part_g = L.take(sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
+    R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    P.offA[p + 1] = P.offA[p] + M.a_items;
+    P.offB[p + 1] = P.offB[p] + M.b_items;
+    P.offP[p + 1] = P.offP[p] + (int)(((long long)M.H * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
+    P.offR[p + 1] = P.offR[p] + M.r_items;
+    M.a_off = P.offA[p];
+    M.b_off = P.offB[p];
+    M.r_off = P.offR[p];
+    P.max_hw = std::max(P.max_hw, std::max(M.H, M.W));
+    P.max_k = std::max(P.max_k, M.K);
+  }
+  P.o_maps = L.take(sizeof(MapDev) * n);
+  P.o_off = L.take(sizeof(int32_t) * 4 * (n + 1));
+}
+
+void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
+                  double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct) {
+  P.any_grad = false;
+  for (int p = 0; p < P.n; ++p) {
+    MapDev &M = P.maps[p];
+    const MapRegions &R = P.reg[p];
+    M.tx64 = (double *)(base + R.tx64);
+    M.ty64 = (double *)(base + R.ty64);
+    M.txT = base + R.txT;
+    M.thc = (double *)(base + R.thc);
+    M.C = base + R.C;
+    M.lse = base + R.lse;
+    M.part_l = (double *)(base + R.part_l);
+    M.part_g = (double *)(base + R.part_g);
+    M.part_c = (int64_t *)(base + R.part_c);
+    M.theta = theta ? theta[p] : nullptr;
+    M.phi = phi_out ? phi_out + p : nullptr;
+    M.grad = grad_out ? grad_out[p] : nullptr;
+    M.labels_out = labels_out ? labels_out[p] : nullptr;
+    M.n_correct = n_correct ? n_correct + p : nullptr;
+    if (M.grad) P.any_grad = true;
+  }
+  P.d_maps = (MapDev *)(base + P.o_maps);
+  int32_t *off = (int32_t *)(base + P.o_off);
+  P.d_offA = off;
+  P.d_offB = off + (P.n + 1);
+  P.d_offP = off + 2 * (P.n + 1);
+  P.d_offR = off + 3 * (P.n + 1);
+}
+
+hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
+  // maps and the four offset arrays are contiguous in the arena (o_maps, o_off)
+  const size_t maps_bytes = sizeof(MapDev) * P.n;
+  const size_t gap = P.o_off - P.o_maps;
+  const size_t total = gap + sizeof(int32_t) * 4 * (P.n + 1);
+  hipError_t e;
+  if (ctx->staged) {
+    e = hipEventSynchronize(ctx->staged);
+    if (e != hipSuccess) return e;
+  } else {
+    e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (total > ctx->stage_cap) {
+    if (ctx->stage) hipHostFree(ctx->stage);
+    ctx->stage = nullptr;
+    ctx->stage_cap = 0;
+    e = hipHostMalloc((void **)&ctx->stage, total * 2, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    ctx->stage_cap = total * 2;
+  }
+  memcpy(ctx->stage, P.maps.data(), maps_bytes);
+  int32_t *o = (int32_t *)(ctx->stage + gap);
+  for (int k = 0; k <= P.n; ++k) {
+    o[k] = P.offA[k];
+    o[(P.n + 1) + k] = P.offB[k];
+    o[2 * (P.n + 1) + k] = P.offP[k];
+    o[3 * (P.n + 1) + k] = P.offR[k];
+  }
+  e = hipMemcpyAsync(P.d_maps, ctx->stage, total, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(ctx->staged, s);
+}
+
+void pd_plan_tables(const EvalPlan &P, hipStream_t s) {
+  pd_launch_tables(P.prec, P.d_maps, P.n, P.max_hw, s);
+}
+
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s) {
+  pd_launch_center(P.d_maps, P.n, P.max_k, s);
+  pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
+  pd_launch_lse(P.prec, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  if (with_grad) pd_launch_grad(P.prec, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
+  pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, s);
+}
+
+void pd_plan_assign(const EvalPlan &P, hipStream_t s) {
+  pd_launch_assign(P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+}
+
+#define PD_HIP(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return pd_fail(ctx, PD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static pd_status precision_code(pd_ctx *ctx, pd_precision prec, int &code) {
+  if (prec == PD_FP64) code = 0;
+  else if (prec == PD_FP32) code = 1;
+  else if (prec == PD_BF16) code = 2;
+  else return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown precision");
+  return PD_OK;
+}
+
+extern "C" {
+
+pd_status pd_create(int device, pd_ctx **out) {
+  if (out == nullptr) return PD_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    hipGetLastError();
+    return PD_ERR_HIP;
+  }
+  if (device < 0 || device >= count) return PD_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PD_ERR_HIP;
+  pd_ctx *c = new pd_ctx();
+  c->device = device;
+  *out = c;
+  return PD_OK;
+}
+
+void pd_destroy(pd_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->stage) hipHostFree(ctx->stage);
+  if (ctx->staged) hipEventDestroy(ctx->staged);
+  pd_fit_release(ctx);
+  delete ctx;
+}
+
+const char *pd_last_error(const pd_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t pd_num_features(int32_t degree) {
+  if (degree < 0 || degree > PD_MAX_DEGREE) return 0;
+  return (degree + 1) * (degree + 2) / 2;
+}
+
+pd_status pd_features(pd_ctx *ctx, int32_t height, int32_t width, int32_t degree,
+                      pd_precision out_prec, void *out, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, out_prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (out == nullptr) return pd_fail(ctx, PD_ERR_INVALID_ARG, "out is NULL");
+  pd_problem q{height, width, (const int32_t *)out, 2, degree, 1.0};
+  pd_status st = pd_check_problem(ctx, q, 0);
+  if (st != PD_OK) return st;
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, &q, 1, 0);
+  st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, nullptr, nullptr, nullptr, nullptr, nullptr);
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  pd_plan_tables(P, s);
+  pd_launch_features_out(P.d_maps, code, out, (long long)height * width, s);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_validate(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n_probs, 0);
+  const size_t o_bad = L.take(sizeof(int32_t) * n_probs);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, nullptr, nullptr, nullptr, nullptr, nullptr);
+  int32_t *bad = (int32_t *)(ctx->ws + o_bad);
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  PD_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t) * n_probs, s));
+  pd_launch_validate(P.d_maps, n_probs, bad, s);
+  PD_HIP(ctx, hipGetLastError());
+  std::vector<int32_t> hb(n_probs);
+  PD_HIP(ctx, hipMemcpyAsync(hb.data(), bad, sizeof(int32_t) * n_probs, hipMemcpyDeviceToHost, s));
+  PD_HIP(ctx, hipStreamSynchronize(s));
+  for (int p = 0; p < n_probs; ++p)
+    if (hb[p])
+      return pd_fail(ctx, PD_ERR_INVALID_ARG,
+                     "map " + std::to_string(p) + ": a label lies outside [0, n_grains)");
+  return PD_OK;
+}
+
+pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                            const double *const *theta, double *phi_out,
+                            double *const *grad_out, pd_precision prec, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta is NULL");
+  if (!phi_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "phi_out is NULL");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta[" + std::to_string(p) + "] is NULL");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (code == 2) return pd_bf16_objective_grad(ctx, probs, n_probs, theta, phi_out, grad_out, s);
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n_probs, code);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  pd_plan_tables(P, s);
+  pd_plan_eval(P, P.any_grad, s);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                    const double *const *theta, int32_t *const *labels_out,
+                    int64_t *n_correct_out, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta is NULL");
+  if (!n_correct_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "n_correct_out is NULL");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta[" + std::to_string(p) + "] is NULL");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n_probs, 0);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, theta, nullptr, nullptr, labels_out, n_correct_out);
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  pd_plan_tables(P, s);
+  pd_plan_assign(P, s);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
+}  // extern "C"

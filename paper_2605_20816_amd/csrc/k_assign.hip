@@ -1,0 +1,105 @@
+// k_assign.hip -- hard arg-min assignment F_theta and accuracy (Section 2.1, 2.2).
+//
+// Lanes = pixels of a 64-pixel row segment, loop over grains with theta read as
+// wave-uniform scalar loads.  Scores use one canonical FP64 operation order,
+//   psi_(a,b) = P_a(x1) * P_b(x2)           (one rounded product)
+//   f_i = theta_i0;  f_i = fma(theta_ik, psi_k, f_i), k = 1..K-1
+// and the scan keeps the first strict minimum (smallest index on ties), so the
+// labels are bit-reproducible.  A NaN score marks the pixel -1.
+#include "pd_internal.h"
+
+template <int D>
+__device__ inline void assign_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  const int r = local / M.segs;
+  const int c = (local - r * M.segs) * PD_WAVE + lane;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  const auto px = pd_glb(M.tx64 + (size_t)cc * DP);
+  const auto py = pd_uni(M.ty64 + (size_t)r * DP);
+  double psi[K];
+#pragma unroll
+  for (int deg = 0; deg <= D; ++deg)
+#pragma unroll
+    for (int b = 0; b <= deg; ++b) psi[pd_alpha_index(deg - b, b)] = px[deg - b] * py[b];
+  const auto th = pd_uni(M.theta);
+  double fbest = th[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) fbest = __builtin_fma(th[k], psi[k], fbest);
+  bool bad = __builtin_isnan(fbest);
+  int best = 0;
+  for (int i = 1; i < M.N; ++i) {
+    const auto ti = th + (size_t)i * K;
+    double f = ti[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) f = __builtin_fma(ti[k], psi[k], f);
+    bad |= __builtin_isnan(f);
+    if (f < fbest) {
+      fbest = f;
+      best = i;
+    }
+  }
+  long long correct = 0;
+  if (valid) {
+    const int lab = bad ? -1 : best;
+    const size_t j = (size_t)r * M.W + c;
+    if (M.labels_out) pd_glb(M.labels_out)[j] = lab;
+    correct = (lab == pd_glb(M.labels)[j]) ? 1 : 0;
+  }
+  const long long tot = pd_wave_sum_i64(correct);
+  if (lane == 0) pd_glb(M.part_c)[local] = tot;
+}
+
+__global__ __launch_bounds__(PD_BLOCK) void k_assign(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps,
+                                                     int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  PD_DISPATCH_D(M.d, (assign_item<D>(M, item - off[m], lane)));
+}
+
+// One block per map: fixed-order sum of the per-wave correct counts.
+__global__ __launch_bounds__(PD_BLOCK) void k_reduce_count(const MapDev *__restrict__ maps) {
+  const MapDev &M = maps[blockIdx.x];
+  if (M.n_correct == nullptr) return;
+  __shared__ long long red[PD_BLOCK];
+  long long s = 0;
+  for (int t = threadIdx.x; t < M.a_items; t += PD_BLOCK) s += M.part_c[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *M.n_correct = red[0];
+}
+
+// bad[m] = 1 if some label of map m lies outside [0, N).  grid: (blocks, n_maps).
+__global__ __launch_bounds__(PD_BLOCK) void k_validate(const MapDev *__restrict__ maps,
+                                                       int32_t *bad) {
+  const MapDev &M = maps[blockIdx.y];
+  const long long n = (long long)M.H * M.W;
+  int b = 0;
+  for (long long j = (long long)blockIdx.x * PD_BLOCK + threadIdx.x; j < n;
+       j += (long long)gridDim.x * PD_BLOCK) {
+    const int g = M.labels[j];
+    b |= (g < 0 || g >= M.N);
+  }
+  if (b) bad[blockIdx.y] = 1;
+}
+
+void pd_launch_assign(const MapDev *maps, const int32_t *off, int n_maps, int total,
+                      hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  k_assign<<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  k_reduce_count<<<n_maps, PD_BLOCK, 0, s>>>(maps);
+}
+
+void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s) {
+  k_validate<<<dim3(64, n_maps), PD_BLOCK, 0, s>>>(maps, bad);
+}

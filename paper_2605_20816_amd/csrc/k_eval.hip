@@ -1,0 +1,384 @@
+// k_eval.hip -- Legendre tables, objective and gradient kernels (FP64 / FP32 VALU).
+//
+// Phi(theta) = (1/n) sum_x [ s_G(x) - lse(x) ],  s_i = -h_i/eps   (eq. log-res-2)
+// grad_i Phi = (1/(eps n)) sum_x (p_i(x) - delta_{i,G(x)}) psi(x)   (eq. grad)
+//
+// The Legendre design is separable, psi_(a,b)(x) = P_a(x1) P_b(x2), so for a
+// fixed row the logit is a degree-d polynomial in x1 with row coefficients
+//   C_{r,i,a} = -(log2 e / eps) sum_b thc_{i,(a,b)} P_b(x2_r),
+// costing d FMAs per (pixel, grain) instead of K.  Logits are kept in base 2
+// (exp2 is the hardware instruction), thc is theta minus its grain mean (a
+// common shift, which changes neither p nor Phi by Lemma 4.2, and keeps FP32
+// logits small).
+//
+// Kernel A (k_lse): one wave per 64-pixel row segment, lanes = pixels, loop over
+//   grains in chunks of 8 with an online max / sum of exp2 (one exp2 per pair
+//   plus one per chunk); writes lse(x) and a per-wave partial of log2 p_G.
+// Kernel B (k_grad): one wave per (pixel tile, 64 grains), lanes = grains, loop
+//   over the tile's pixels with the pixel data (P_a(x1), lse, label) as
+//   wave-uniform scalar loads; per-lane accumulators of (p - delta) P_a(x1) are
+//   folded into the K moments at the end of each row.  No cross-lane reduction
+//   and no atomics: partials per tile are summed in a fixed order by k_reduce_grad,
+//   so results are bitwise reproducible.
+#include "pd_internal.h"
+
+#include <math.h>
+
+template <typename T> __device__ inline T pd_exp2(T x);
+template <> __device__ inline float pd_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ inline double pd_exp2<double>(double x) { return exp2(x); }
+template <typename T> __device__ inline T pd_log2(T x);
+template <> __device__ inline float pd_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ inline double pd_log2<double>(double x) { return log2(x); }
+__device__ inline float pd_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double pd_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float pd_max(float a, float b) { return fmaxf(a, b); }
+__device__ inline double pd_max(double a, double b) { return fmax(a, b); }
+
+// ---------------------------------------------------------------------------
+// Canonical 1-D Legendre tables (Section 3.3 recurrence), bit-identical to the
+// definition: t = (2i+1-len)/len (one correctly rounded division), P_0 = 1,
+// P_1 = t, P_{m+1} = fma((2m+1) t, P_m, -(m P_{m-1})) / (m+1).
+__device__ inline void pd_legendre_canonical(int idx, int len, int d, double *P) {
+  const double t = (double)(2 * idx + 1 - len) / (double)len;
+  P[0] = 1.0;
+  if (d >= 1) P[1] = t;
+  for (int m = 1; m < d; ++m) {
+    const double a = (double)(2 * m + 1) * t;
+    const double b = (double)m * P[m - 1];
+    P[m + 1] = __builtin_fma(a, P[m], -b) / (double)(m + 1);
+  }
+}
+
+// grid: (ceil(max(H,W)/256), n_maps).  Writes tx64/ty64 and the typed copy txT.
+template <typename T>
+__global__ __launch_bounds__(PD_BLOCK) void k_tables(const MapDev *__restrict__ maps) {
+  const MapDev &M = maps[blockIdx.y];
+  const int idx = blockIdx.x * PD_BLOCK + threadIdx.x;
+  double P[PD_DMAX + 1];
+  if (idx < M.W) {
+    pd_legendre_canonical(idx, M.W, M.d, P);
+    for (int a = 0; a <= M.d; ++a) {
+      M.tx64[(size_t)idx * M.DP + a] = P[a];
+      ((T *)M.txT)[(size_t)idx * M.DP + a] = (T)P[a];
+    }
+  }
+  if (idx < M.H) {
+    pd_legendre_canonical(idx, M.H, M.d, P);
+    for (int a = 0; a <= M.d; ++a) M.ty64[(size_t)idx * M.DP + a] = P[a];
+  }
+}
+
+// grid: (K, n_maps), 256 threads: mean over grains of column k of theta, then
+// thc = -(log2 e / eps) * (theta - mean).  Fixed-order block reduction.
+__global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ maps) {
+  const MapDev &M = maps[blockIdx.y];
+  const int k = blockIdx.x;
+  if (k >= M.K) return;
+  __shared__ double red[PD_BLOCK];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < M.N; i += PD_BLOCK) s += M.theta[(size_t)i * M.K + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)M.N;
+  const double scale = -PD_LOG2E / M.eps;
+  for (int i = threadIdx.x; i < M.N; i += PD_BLOCK)
+    M.thc[(size_t)i * M.K + k] = scale * (M.theta[(size_t)i * M.K + k] - mean);
+}
+
+// Row coefficients C[r][i][a] = sum_b thc[i][(a,b)] P_b(x2_r).  Padded grains
+// i in [N, Npad) get C = (-inf, 0, ..., 0): exp2 of their logit is 0.
+// grid: blocks over the flattened (map, r, i), offsets in off (n_maps + 1).
+template <typename T, int D>
+__device__ inline void prep_one(const MapDev &M, int r, int i) {
+  constexpr int DP = D + 1;
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  T *out = (T *)M.C + ((size_t)r * M.Npad + i) * DP;
+  if (i >= M.N) {
+    out[0] = (T)-INFINITY;
+#pragma unroll
+    for (int a = 1; a < DP; ++a) out[a] = (T)0;
+    return;
+  }
+  const double *th = M.thc + (size_t)i * K;
+  const double *ty = M.ty64 + (size_t)r * DP;
+#pragma unroll
+  for (int a = 0; a <= D; ++a) {
+    double v = th[pd_alpha_index(a, 0)];
+#pragma unroll
+    for (int b = 1; a + b <= D; ++b) v = __builtin_fma(th[pd_alpha_index(a, b)], ty[b], v);
+    out[a] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ maps,
+                                                   const int32_t *__restrict__ off, int n_maps) {
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
+  if (flat >= (long long)M.H * M.Npad) return;
+  const int r = (int)(flat / M.Npad), i = (int)(flat - (long long)r * M.Npad);
+  PD_DISPATCH_D(M.d, (prep_one<T, D>(M, r, i)));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel A: per-pixel base-2 log-sum-exp over grains and partial sums of log2 p_G.
+template <typename T, int D>
+__device__ inline void lse_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  const int r = local / M.segs;
+  const int c = (local - r * M.segs) * PD_WAVE + lane;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  const auto tx = pd_glb((const T *)M.txT + (size_t)cc * DP);
+  T px[DP];
+#pragma unroll
+  for (int a = 0; a < DP; ++a) px[a] = tx[a];
+  const auto Crow = pd_uni((const T *)M.C + (size_t)r * M.Npad * DP);
+  const auto Cvec = pd_glb((const T *)M.C + (size_t)r * M.Npad * DP);
+  const int N = M.N;
+  T mrun = (T)-INFINITY, S = (T)0;
+  for (int i0 = 0; i0 < N; i0 += 8) {
+    T s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const auto cp = Crow + (size_t)(i0 + j) * DP;
+      T v = cp[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
+      s[j] = (i0 + j < N) ? v : (T)-INFINITY;
+    }
+    T cm = s[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) cm = pd_max(cm, s[j]);
+    const T mnew = pd_max(mrun, cm);
+    S *= pd_exp2<T>(mrun - mnew);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) S += pd_exp2<T>(s[j] - mnew);
+    mrun = mnew;
+  }
+  const T lse = mrun + pd_log2<T>(S);
+  double ell = 0.0;
+  if (valid) {
+    const size_t j = (size_t)r * M.W + c;
+    pd_glb((T *)M.lse)[j] = lse;
+    const int g = pd_glb(M.labels)[j];
+    if (g >= 0 && g < N) {
+      const auto cg = Cvec + (size_t)g * DP;
+      T v = cg[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) v = pd_fma(cg[a], px[a], v);
+      ell = (double)v - (double)lse;
+    } else {
+      ell = NAN;
+    }
+  }
+  const double tot = pd_wave_sum(ell);
+  if (lane == 0) pd_glb(M.part_l)[local] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ maps,
+                                                  const int32_t *__restrict__ off, int n_maps,
+                                                  int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  PD_DISPATCH_D(M.d, (lse_item<T, D>(M, item - off[m], lane)));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel B: partial gradient moments per (pixel tile, 64-grain group).
+template <typename T, int D>
+__device__ inline void grad_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  const int groups = M.Npad / PD_WAVE;
+  const int tile = local / groups;
+  const int grp = local - tile * groups;
+  const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
+  const int r0 = tr * M.tile_rows, r1 = min(r0 + M.tile_rows, M.H);
+  const int c0 = tcol * M.tile_cols, c1 = min(c0 + M.tile_cols, M.W);
+  const int gbase = grp * PD_WAVE;
+  const int i = gbase + lane;
+  double q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q[k] = 0.0;
+  const auto txT = pd_uni((const T *)M.txT);
+  for (int r = r0; r < r1; ++r) {
+    const auto cp = pd_glb((const T *)M.C + ((size_t)r * M.Npad + i) * DP);
+    T cf[DP];
+#pragma unroll
+    for (int a = 0; a < DP; ++a) cf[a] = cp[a];
+    T racc[DP];
+#pragma unroll
+    for (int a = 0; a < DP; ++a) racc[a] = (T)0;
+    const auto lrow = pd_uni((const T *)M.lse + (size_t)r * M.W);
+    const auto grow = pd_uni(M.labels + (size_t)r * M.W);
+    for (int c = c0; c < c1; ++c) {
+      const auto pxp = txT + (size_t)c * DP;
+      T px[DP];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) px[a] = pxp[a];
+      const T l = lrow[c];
+      const int g = grow[c];
+      T s = cf[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], px[a], s);
+      const T p = pd_exp2<T>(s - l);
+      racc[0] += p;
+#pragma unroll
+      for (int a = 1; a < DP; ++a) racc[a] = pd_fma(p, px[a], racc[a]);
+      const int gl = g - gbase;
+      if ((unsigned)gl < (unsigned)PD_WAVE) {
+        if (lane == gl) {
+          racc[0] -= (T)1;
+#pragma unroll
+          for (int a = 1; a < DP; ++a) racc[a] -= px[a];
+        }
+      }
+    }
+    const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+      const double ra = (double)racc[a];
+#pragma unroll
+      for (int b = 0; a + b <= D; ++b) {
+        const int k = pd_alpha_index(a, b);
+        q[k] = __builtin_fma(ra, ty[b], q[k]);
+      }
+    }
+  }
+  const auto out = pd_glb(M.part_g + ((size_t)tile * M.Npad + i) * K);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = q[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ maps,
+                                                   const int32_t *__restrict__ off, int n_maps,
+                                                   int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  PD_DISPATCH_D(M.d, (grad_item<T, D>(M, item - off[m], lane)));
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reductions.  Phi: one block per map.  Gradient: one thread per
+// (map, i, k), summing the tiles in order.
+__global__ __launch_bounds__(PD_BLOCK) void k_reduce_phi(const MapDev *__restrict__ maps) {
+  const MapDev &M = maps[blockIdx.x];
+  __shared__ double red[PD_BLOCK];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < M.a_items; t += PD_BLOCK) s += M.part_l[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *M.phi = PD_LN2 * red[0] / ((double)M.H * (double)M.W);
+}
+
+__global__ __launch_bounds__(PD_BLOCK) void k_reduce_grad(const MapDev *__restrict__ maps,
+                                                          const int32_t *__restrict__ off,
+                                                          int n_maps) {
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  if (M.grad == nullptr) return;
+  const int o = (blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
+  if (o >= M.N * M.K) return;
+  const int i = o / M.K, k = o - i * M.K;
+  const int tiles = M.tiles_r * M.tiles_c;
+  const double *src = M.part_g + (size_t)i * M.K + k;
+  const size_t stride = (size_t)M.Npad * M.K;
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += src[(size_t)t * stride];
+  M.grad[o] = s * M.grad_scale;
+}
+
+// ---------------------------------------------------------------------------
+// Design-matrix output of pd_features: out[alpha*n + j] in FP64, FP32, or two
+// bf16 planes (hi, then lo = bf16(psi - hi)), from the canonical tables.
+__device__ inline uint16_t pd_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float pd_bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ __launch_bounds__(PD_BLOCK) void k_features_out(const MapDev *__restrict__ maps,
+                                                           int prec, void *out) {
+  const MapDev &M = maps[0];
+  const long long n = (long long)M.H * M.W;
+  const long long j = (long long)blockIdx.x * PD_BLOCK + threadIdx.x;
+  if (j >= n) return;
+  const int r = (int)(j / M.W), c = (int)(j - (long long)r * M.W);
+  const double *px = M.tx64 + (size_t)c * M.DP;
+  const double *py = M.ty64 + (size_t)r * M.DP;
+  int k = 0;
+  for (int deg = 0; deg <= M.d; ++deg)
+    for (int b = 0; b <= deg; ++b, ++k) {
+      const double v = px[deg - b] * py[b];
+      if (prec == 0) {
+        ((double *)out)[(size_t)k * n + j] = v;
+      } else if (prec == 1) {
+        ((float *)out)[(size_t)k * n + j] = (float)v;
+      } else {
+        const uint16_t hi = pd_bf16_rne((float)v);
+        const uint16_t lo = pd_bf16_rne((float)(v - (double)pd_bf16_to_f32(hi)));
+        ((uint16_t *)out)[(size_t)k * n + j] = hi;
+        ((uint16_t *)out)[(size_t)M.K * n + (size_t)k * n + j] = lo;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (prec: 0 = FP64, 1 = FP32).
+void pd_launch_tables(int prec, const MapDev *maps, int n_maps, int max_hw, hipStream_t s) {
+  dim3 grid((max_hw + PD_BLOCK - 1) / PD_BLOCK, n_maps);
+  if (prec == 0) k_tables<double><<<grid, PD_BLOCK, 0, s>>>(maps);
+  else k_tables<float><<<grid, PD_BLOCK, 0, s>>>(maps);
+}
+void pd_launch_center(const MapDev *maps, int n_maps, int max_k, hipStream_t s) {
+  k_center<<<dim3(max_k, n_maps), PD_BLOCK, 0, s>>>(maps);
+}
+void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps, int blocks,
+                    hipStream_t s) {
+  if (prec == 0) k_prep<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
+  else k_prep<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
+}
+void pd_launch_lse(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
+                   hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (prec == 0) k_lse<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  else k_lse<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+}
+void pd_launch_grad(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
+                    hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (prec == 0) k_grad<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  else k_grad<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+}
+void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
+                      bool grad, hipStream_t s) {
+  k_reduce_phi<<<n_maps, PD_BLOCK, 0, s>>>(maps);
+  if (grad && blocks_r > 0) k_reduce_grad<<<blocks_r, PD_BLOCK, 0, s>>>(maps, off_r, n_maps);
+}
+void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s) {
+  const long long blocks = (n + PD_BLOCK - 1) / PD_BLOCK;
+  k_features_out<<<(unsigned)blocks, PD_BLOCK, 0, s>>>(maps, prec, out);
+}

@@ -1,0 +1,66 @@
+// pd_host.h -- host-side planning structures of libpd (not part of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "pd.h"
+#include "pd_internal.h"
+
+struct FitState;
+
+struct pd_ctx {
+  int device = 0;
+  std::string err;
+  char *ws = nullptr;     // evaluation workspace, grown on demand
+  size_t ws_cap = 0;
+  FitState *fit = nullptr;
+  // pinned staging of the map descriptors; `staged` marks the last copy out of it
+  char *stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t staged = nullptr;
+};
+
+// Bump allocator over byte offsets (256-byte aligned regions).
+struct Arena {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct MapRegions {
+  size_t tx64, ty64, txT, thc, C, lse, part_l, part_g, part_c;
+};
+
+// Everything one batched evaluation / assignment needs, laid out in an arena.
+struct EvalPlan {
+  int n = 0, prec = 0;
+  bool any_grad = false;
+  int target_waves = 8192;
+  std::vector<MapDev> maps;
+  std::vector<MapRegions> reg;
+  std::vector<int32_t> offA, offB, offP, offR;
+  int max_hw = 0, max_k = 0;
+  size_t o_maps = 0, o_off = 0;
+  MapDev *d_maps = nullptr;
+  int32_t *d_offA = nullptr, *d_offB = nullptr, *d_offP = nullptr, *d_offR = nullptr;
+};
+
+pd_status pd_fail(pd_ctx *c, pd_status s, const std::string &msg);
+pd_status pd_check_problem(pd_ctx *ctx, const pd_problem &p, int idx);
+pd_status pd_reserve(pd_ctx *ctx, size_t bytes);
+void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec);
+void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
+                  double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
+hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
+void pd_plan_tables(const EvalPlan &P, hipStream_t s);
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s);
+void pd_plan_assign(const EvalPlan &P, hipStream_t s);
+
+pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
+                                 const double *const *theta, double *phi_out,
+                                 double *const *grad_out, hipStream_t s);
+void pd_fit_release(pd_ctx *ctx);

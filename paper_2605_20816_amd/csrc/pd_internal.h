@@ -1,0 +1,125 @@
+// pd_internal.h -- device-side data layout shared by the HIP sources of libpd.
+//
+// One "map" is one grain map with its parameters.  Every kernel takes an array
+// of MapDev records (one per map of the batch) plus prefix offsets of the work
+// items each map contributes, so a single launch serves one map or a batch of
+// maps of different sizes, grain counts and degrees.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PD_WAVE 64
+#define PD_BLOCK 256
+#define PD_WAVES_PER_BLOCK (PD_BLOCK / PD_WAVE)
+#define PD_DMAX 8
+
+// log2(e) and ln(2) as the nearest doubles.
+#define PD_LOG2E 1.4426950408889634074
+#define PD_LN2 0.69314718055994530942
+
+struct MapDev {
+  // problem
+  int32_t H, W, N, d, K, DP, Npad;  // DP = d + 1; Npad = N rounded up to 64
+  int32_t segs;                     // ceil(W / 64): 64-pixel row segments
+  double eps;
+  double grad_scale;                // 1 / (eps * n)
+  const int32_t *labels;            // n
+  const double *theta;              // N x K
+  double *grad;                     // N x K or null
+  double *phi;                      // -> phi_out[map]
+  // per-evaluation workspace (device)
+  double *tx64;                     // [W][DP]  P_a(x1) at each column, FP64
+  double *ty64;                     // [H][DP]  P_b(x2) at each row, FP64
+  void *txT;                        // [W][DP]  the same in the evaluation type
+  double *thc;                      // [N][K]   -log2(e)/eps * (theta_i - mean_j theta_j)
+  void *C;                          // [H][Npad][DP] row coefficients, evaluation type
+  void *lse;                        // [n] base-2 log-sum-exp per pixel, evaluation type
+  double *part_l;                   // [a_items] per-wave partial sums of log2 p_G
+  double *part_g;                   // [tiles][Npad][K] partial sums of (p - delta) psi
+  // gradient tiling: tiles of tile_rows x tile_cols pixels, 64 grains per wave
+  int32_t tile_rows, tile_cols, tiles_r, tiles_c;
+  // work-item counts and offsets inside the batched launches
+  int32_t a_items, a_off;           // row-segment items (objective, assignment)
+  int32_t b_items, b_off;           // gradient items: tiles * (Npad / 64)
+  int32_t r_items, r_off;           // reduction items: ceil(N*K / 256) blocks
+  // assignment
+  int32_t *labels_out;              // n or null
+  int64_t *n_correct;               // -> n_correct_out[map] or null
+  int64_t *part_c;                  // [a_items] per-wave correct counts
+};
+
+// Run CALL with the compile-time degree D = dval (1..PD_DMAX).
+#define PD_DISPATCH_D(dval, CALL)                 \
+  switch (dval) {                                 \
+    case 1: { constexpr int D = 1; CALL; } break; \
+    case 2: { constexpr int D = 2; CALL; } break; \
+    case 3: { constexpr int D = 3; CALL; } break; \
+    case 4: { constexpr int D = 4; CALL; } break; \
+    case 5: { constexpr int D = 5; CALL; } break; \
+    case 6: { constexpr int D = 6; CALL; } break; \
+    case 7: { constexpr int D = 7; CALL; } break; \
+    case 8: { constexpr int D = 8; CALL; } break; \
+    default: break;                               \
+  }
+
+// Wave-uniform map lookup: largest m with off[m] <= item (off has n+1 entries).
+__device__ inline int pd_find_map(const int32_t *__restrict__ off, int n, int item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Address-space views.  pd_uni: data that is read-only for the whole kernel and
+// read at wave-uniform addresses -> scalar loads through the scalar cache.
+// pd_glb: per-lane reads and writes -> global (not flat) memory instructions.
+#define PD_AS_CONST __attribute__((address_space(4)))
+#define PD_AS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const PD_AS_CONST T *pd_uni(const T *p) {
+  return (const PD_AS_CONST T *)(p);
+}
+template <typename T>
+__device__ inline PD_AS_GLOBAL T *pd_glb(T *p) {
+  return (PD_AS_GLOBAL T *)(p);
+}
+template <typename T>
+__device__ inline const PD_AS_GLOBAL T *pd_glb(const T *p) {
+  return (const PD_AS_GLOBAL T *)(p);
+}
+
+// Index of multi-index alpha = (a, b) in the degree-graded order.
+__host__ __device__ constexpr int pd_alpha_index(int a, int b) {
+  return (a + b) * (a + b + 1) / 2 + b;
+}
+
+__device__ inline double pd_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
+  return v;
+}
+
+__device__ inline long long pd_wave_sum_i64(long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
+  return v;
+}
+
+// Host launchers (defined beside their kernels).  prec: 0 = FP64, 1 = FP32.
+void pd_launch_tables(int prec, const MapDev *maps, int n_maps, int max_hw, hipStream_t s);
+void pd_launch_center(const MapDev *maps, int n_maps, int max_k, hipStream_t s);
+void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps, int blocks,
+                    hipStream_t s);
+void pd_launch_lse(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
+                   hipStream_t s);
+void pd_launch_grad(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
+                    hipStream_t s);
+void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
+                      bool grad, hipStream_t s);
+void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s);
+void pd_launch_assign(const MapDev *maps, const int32_t *off, int n_maps, int total,
+                      hipStream_t s);
+void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);

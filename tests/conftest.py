@@ -18,3 +18,15 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def pd():
+    """The GPU library binding with an open context on cuda:0."""
+    import torch
+
+    import paper_2605_20816_amd as pdl
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = pdl.Context(0)
+    yield pdl, ctx
+    ctx.close()
