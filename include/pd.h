@@ -163,6 +163,26 @@ pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);
 
+/* Per-stage timing of one evaluation (the library's tracing hook; not part of
+ * the paper).  Runs the evaluation of pd_objective_grad stage by stage, each
+ * stage `reps` times back to back between HIP events on `stream`, and writes the
+ * average milliseconds per launch of each stage to ms_out (host, PD_NUM_STAGES
+ * entries, in the order of pd_stage).  Gradient stages are included.  Synchronous.
+ * PD_BF16 times its matrix-core stages in the PD_STAGE_LSE / PD_STAGE_GRAD slots. */
+typedef enum {
+  PD_STAGE_TABLES = 0,  /* 1-D Legendre tables                                  */
+  PD_STAGE_CENTER = 1,  /* grain-mean removal and eps scaling of theta          */
+  PD_STAGE_PREP = 2,    /* row coefficients C[r][i][a]                          */
+  PD_STAGE_LSE = 3,     /* per-pixel log-sum-exp and partial sums of log p_G    */
+  PD_STAGE_GRAD = 4,    /* partial sums of (p - delta) psi                      */
+  PD_STAGE_REDUCE = 5,  /* fixed-order reductions to Phi and grad Phi           */
+  PD_NUM_STAGES = 6
+} pd_stage;
+
+pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                          const double *const *theta /*host*/, pd_precision prec, int32_t reps,
+                          double *ms_out /*host*/, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,12 @@ _SIGS = {
     "pd_fit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_FitOpts),
                               ctypes.POINTER(_FitReport), ctypes.c_void_p]),
+    "pd_profile_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
 }
+
+STAGES = ("tables", "center", "prep", "lse", "grad", "reduce")
 
 
 def lib():
@@ -224,6 +229,16 @@ class Context:
         self._check(lib().pd_assign(self._h, arr, n, _ptrs(thetas), lp,
                                     ctypes.c_void_p(cnt.data_ptr()), _stream(stream)))
         return outs, cnt
+
+    def profile_eval(self, probs, thetas, prec="fp64", reps=10, stream=None):
+        """Average milliseconds per launch of each evaluation stage (dict)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        ms = (ctypes.c_double * len(STAGES))()
+        self._check(lib().pd_profile_eval(self._h, arr, n, _ptrs(thetas), PREC[prec], int(reps),
+                                          ms, _stream(stream)))
+        return dict(zip(STAGES, list(ms)))
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
             max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, stream=None):

@@ -70,13 +70,14 @@ pd_status pd_reserve(pd_ctx *ctx, size_t bytes) {
   return PD_OK;
 }
 
-// Tile of the gradient kernel: aim for about `target_waves` waves per map, each
-// over at least 64 pixels, tiles at most 256 columns wide.
+// Tile of the gradient kernel: about `target_waves` waves per map, each over at
+// least 64 pixels, tiles at most 256 columns wide (the per-row fold into the K
+// moments is amortised over the tile width).
 static void choose_tiles(int H, int W, int Npad, int target_waves, int &tr, int &tc) {
   const long long groups = Npad / PD_WAVE;
   long long px = (long long)H * W * groups / target_waves;
   if (px < 64) px = 64;
-  tc = std::min(W, 256);
+  tc = (int)std::min<long long>(std::min(W, 256), px);
   long long rows = px / tc;
   if (rows < 1) rows = 1;
   if (rows > H) rows = H;
@@ -94,6 +95,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
   P.offR.assign(n + 1, 0);
   P.max_hw = 0;
   P.max_k = 0;
+  int max_d = 1;
   const size_t tsz = prec == 0 ? 8 : 4;
   for (int p = 0; p < n; ++p) {
     const pd_problem &q = probs[p];
@@ -115,7 +117,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.tiles_c = (M.W + M.tile_cols - 1) / M.tile_cols;
     M.a_items = M.H * M.segs;
     M.b_items = M.tiles_r * M.tiles_c * (M.Npad / PD_WAVE);
-    M.r_items = (M.N * M.K + PD_BLOCK - 1) / PD_BLOCK;
+    M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
     const long long n_px = (long long)M.H * M.W;
     R.tx64 = L.take(sizeof(double) * M.W * M.DP);
     R.ty64 = L.take(sizeof(double) * M.H * M.DP);
@@ -135,7 +137,9 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.r_off = P.offR[p];
     P.max_hw = std::max(P.max_hw, std::max(M.H, M.W));
     P.max_k = std::max(P.max_k, M.K);
+    max_d = std::max(max_d, M.d);
   }
+  P.dmax = pd_dmax_bucket(max_d);
   P.o_maps = L.take(sizeof(MapDev) * n);
   P.o_off = L.take(sizeof(int32_t) * 4 * (n + 1));
 }
@@ -208,16 +212,16 @@ void pd_plan_tables(const EvalPlan &P, hipStream_t s) {
   pd_launch_tables(P.prec, P.d_maps, P.n, P.max_hw, s);
 }
 
-void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s) {
-  pd_launch_center(P.d_maps, P.n, P.max_k, s);
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center) {
+  if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-  pd_launch_lse(P.prec, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-  if (with_grad) pd_launch_grad(P.prec, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
+  pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  if (with_grad) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
   pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, s);
 }
 
 void pd_plan_assign(const EvalPlan &P, hipStream_t s) {
-  pd_launch_assign(P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  pd_launch_assign(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
 }
 
 #define PD_HIP(ctx, expr)                                                                  \
@@ -354,7 +358,7 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_prob
   pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
   PD_HIP(ctx, pd_plan_upload(ctx, P, s));
   pd_plan_tables(P, s);
-  pd_plan_eval(P, P.any_grad, s);
+  pd_plan_eval(P, P.any_grad, s, true);
   PD_HIP(ctx, hipGetLastError());
   return PD_OK;
 }
@@ -384,6 +388,65 @@ pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   pd_plan_tables(P, s);
   pd_plan_assign(P, s);
   PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                          const double *const *theta, pd_precision prec, int32_t reps,
+                          double *ms_out, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (!probs || n_probs < 1 || !theta || !ms_out || reps < 1)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "pd_profile_eval: bad arguments");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta entry is NULL");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n_probs, code == 2 ? 1 : code);
+  const size_t o_phi = L.take(sizeof(double) * n_probs);
+  std::vector<size_t> o_g(n_probs);
+  for (int p = 0; p < n_probs; ++p)
+    o_g[p] = L.take(sizeof(double) * (size_t)P.maps[p].N * P.maps[p].K);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  std::vector<double *> g(n_probs);
+  for (int p = 0; p < n_probs; ++p) g[p] = (double *)(ctx->ws + o_g[p]);
+  pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), g.data(), nullptr, nullptr);
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  hipEvent_t ev[PD_NUM_STAGES + 1];
+  for (auto &e : ev) PD_HIP(ctx, hipEventCreate(&e));
+  PD_HIP(ctx, hipEventRecord(ev[0], s));
+  for (int r = 0; r < reps; ++r) pd_plan_tables(P, s);
+  PD_HIP(ctx, hipEventRecord(ev[1], s));
+  for (int r = 0; r < reps; ++r) pd_launch_center(P.d_maps, P.n, P.max_k, s);
+  PD_HIP(ctx, hipEventRecord(ev[2], s));
+  if (code == 2) {
+    pd_bf16_profile_stages(ctx, P, reps, s, ev + 2);
+  } else {
+    for (int r = 0; r < reps; ++r) pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
+    PD_HIP(ctx, hipEventRecord(ev[3], s));
+    for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+    PD_HIP(ctx, hipEventRecord(ev[4], s));
+    for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
+    PD_HIP(ctx, hipEventRecord(ev[5], s));
+  }
+  for (int r = 0; r < reps; ++r) pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, s);
+  PD_HIP(ctx, hipEventRecord(ev[6], s));
+  PD_HIP(ctx, hipGetLastError());
+  PD_HIP(ctx, hipEventSynchronize(ev[6]));
+  for (int k = 0; k < PD_NUM_STAGES; ++k) {
+    float ms = 0.f;
+    PD_HIP(ctx, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+    ms_out[k] = (double)ms / reps;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
   return PD_OK;
 }
 

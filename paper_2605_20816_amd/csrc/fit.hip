@@ -1,9 +1,646 @@
-// fit.hip -- device L-BFGS driver (pd_fit).
+// fit.hip -- device L-BFGS driver of pd_fit (Section 5.2).
+//
+// Maximises Phi (minimises f = -Phi) for a batch of maps.  All vectors, the
+// L-BFGS memory and the line-search state live on the device; one "step" is a
+// fixed sequence of kernels -- trial point, objective+gradient, decision,
+// assignment, accuracy check -- captured once as a HIP graph and replayed.  The
+// host only polls a per-map activity flag every few replays.
+//
+// Algorithm (the paper names L-BFGS [Liu-Nocedal 1989] and nothing more; these
+// are the library's documented choices): memory m, H0 = gamma I with
+// gamma = s.y / y.y of the newest stored pair, first trial step 1/||g||_2 when the
+// memory is empty and 1 otherwise, strong-Wolfe line search with bracketing by
+// doubling and zoom by safeguarded cubic interpolation (Nocedal-Wright
+// Algorithms 3.5/3.6, c1 = 1e-4, c2 = 0.9, <= 20 evaluations), pairs stored only
+// if s.y > 1e-10 ||s|| ||y||, a failed search clears the memory and retries once.
+// If a search exhausts its evaluations at a point with sufficient decrease, that
+// point is accepted (it is evaluated once more, which the evaluation count shows).
+// Gauge (Remark 4.3): LAST_ZERO zeroes grain N-1's gradient row (theta_{N-1}
+// stays 0); CENTERED subtracts the grain mean.
 #include "pd_host.h"
 
-void pd_fit_release(pd_ctx *) {}
+#include <math.h>
+#include <string.h>
 
-extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *, int32_t, double *const *,
-                            const pd_fit_opts *, pd_fit_report *, void *) {
-  return pd_fail(ctx, PD_ERR_UNSUPPORTED, "pd_fit: not built yet");
+#include <chrono>
+#include <vector>
+
+#define FIT_THREADS 1024
+#define LS_C1 1e-4
+#define LS_C2 0.9
+#define LS_MAX_EVALS 20
+#define CURV_EPS 1e-10
+
+enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
+enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
+
+struct FitDev {
+  int32_t N, K, NK, m, max_iter, check_every, gauge;
+  int64_t n_pix;
+  double target_acc, gtol;
+  double *x, *g, *d, *xt, *graw, *S, *Y, *rho, *alpha;
+  const double *phi_t;
+  const int64_t *n_correct;
+  double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
+  double cscale;     // -log2(e) / eps
+  int32_t *active, *assign_pending;
+  // state
+  int32_t status, phase, iters, evals, ls_evals, hist_len, hist_head, reset_tried;
+  double f, t, f0, dphi0, gamma, acc;
+  double prev_t, prev_f, prev_d, lo_t, lo_f, lo_d, hi_t, hi_f, hi_d;
+  uint64_t clk_start, clk_target;
+};
+
+struct FitState {
+  hipStream_t stream = nullptr;
+};
+
+// ------------------------------------------------------------------ block helpers
+
+__device__ double blk_sum(double v, double *red) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (tid == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    red[32] = t;
+  }
+  __syncthreads();
+  return red[32];
+}
+
+__device__ double blk_dot(const double *a, const double *b, int n, double *red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s = __builtin_fma(a[i], b[i], s);
+  return blk_sum(s, red);
+}
+
+__device__ double blk_maxabs(const double *a, int n, double *red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, fabs(a[i]));
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, PD_WAVE));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
+    red[32] = t;
+  }
+  __syncthreads();
+  return red[32];
+}
+
+// v <- projection of v onto the gauge-fixed subspace (in place).
+__device__ void blk_gauge(FitDev &F, double *v, double *red) {
+  if (F.gauge == 0) {
+    for (int k = threadIdx.x; k < F.K; k += blockDim.x) v[(size_t)(F.N - 1) * F.K + k] = 0.0;
+  } else if (F.gauge == 1) {
+    for (int k = 0; k < F.K; ++k) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < F.N; i += blockDim.x) s += v[(size_t)i * F.K + k];
+      const double mean = blk_sum(s, red) / (double)F.N;
+      for (int i = threadIdx.x; i < F.N; i += blockDim.x) v[(size_t)i * F.K + k] -= mean;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ inline double cubic_min(double a, double fa, double da, double b, double fb, double db) {
+  const double lo = fmin(a, b), hi = fmax(a, b), width = hi - lo, mid = 0.5 * (a + b);
+  const double d1 = da + db - 3.0 * (fa - fb) / (a - b);
+  const double disc = d1 * d1 - da * db;
+  if (!(disc >= 0.0)) return mid;
+  const double d2 = copysign(sqrt(disc), b - a);
+  const double den = db - da + 2.0 * d2;
+  if (den == 0.0) return mid;
+  const double t = b - (b - a) * ((db + d2 - d1) / den);
+  if (!(lo + 0.1 * width <= t && t <= hi - 0.1 * width)) return mid;
+  return t;
+}
+
+__device__ inline void fit_stop(FitDev &F, int status) {
+  F.status = status;
+  *F.active = 0;
+}
+
+// Start a line search from (x, f, g) along d (block-wide; all threads call).
+__device__ void start_ls(FitDev &F, double *red) {
+  const int n = F.NK;
+  const double gn2 = blk_dot(F.g, F.g, n, red);
+  const double gmax = blk_maxabs(F.g, n, red);
+  if (threadIdx.x == 0 && (gn2 == 0.0 || gmax <= F.gtol)) fit_stop(F, ST_GTOL);
+  __syncthreads();
+  if (F.status != ST_RUNNING) return;
+  const double gnorm = sqrt(gn2);
+  double t1 = F.hist_len == 0 ? 1.0 / gnorm : 1.0;
+  double dphi0 = blk_dot(F.g, F.d, n, red);
+  if (!(dphi0 < 0.0)) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) F.d[i] = -F.g[i];
+    __syncthreads();
+    t1 = 1.0 / gnorm;
+    dphi0 = blk_dot(F.g, F.d, n, red);
+    if (threadIdx.x == 0) F.hist_len = 0;
+  }
+  if (threadIdx.x == 0) {
+    F.f0 = F.f;
+    F.dphi0 = dphi0;
+    F.prev_t = 0.0;
+    F.prev_f = F.f;
+    F.prev_d = dphi0;
+    F.t = t1;
+    F.ls_evals = 0;
+    F.phase = PH_BRACKET;
+  }
+  __syncthreads();
+}
+
+// Accept the trial point (xt, graw = gradient of f, ft); update the memory,
+// take the new quasi-Newton direction and start the next search.
+__device__ void accept_trial(FitDev &F, double ft, double *red) {
+  const int n = F.NK;
+  const int m = F.m;
+  // The ring has m + 1 slots; the candidate pair goes to the free slot after the
+  // newest pair, so a rejected candidate never overwrites a stored one.
+  const int M1 = m + 1;
+  const int put = (F.hist_head + F.hist_len) % M1;
+  double *s = F.S + (size_t)put * n;
+  double *y = F.Y + (size_t)put * n;
+  const double t = F.t;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    s[i] = t * F.d[i];
+    y[i] = F.graw[i] - F.g[i];
+  }
+  __syncthreads();
+  const double sy = blk_dot(s, y, n, red);
+  const double ss = blk_dot(s, s, n, red);
+  const double yy = blk_dot(y, y, n, red);
+  if (threadIdx.x == 0) {
+    if (sy > CURV_EPS * sqrt(ss) * sqrt(yy)) {
+      F.rho[put] = 1.0 / sy;
+      if (F.hist_len < m) F.hist_len++;
+      else F.hist_head = (F.hist_head + 1) % M1;
+      F.gamma = sy / yy;
+    }
+    F.reset_tried = 0;
+    F.f = ft;
+    F.iters++;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    F.x[i] = F.xt[i];
+    F.g[i] = F.graw[i];
+  }
+  __syncthreads();
+  if (F.iters >= F.max_iter) {
+    if (threadIdx.x == 0) {
+      F.phase = PH_STOP;
+      *F.assign_pending = 1;
+    }
+    __syncthreads();
+    return;
+  }
+  if (threadIdx.x == 0 && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
+  // two-loop recursion: d = -H g
+  double *q = F.d;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = F.g[i];
+  __syncthreads();
+  const int L = F.hist_len;
+  for (int k = L - 1; k >= 0; --k) {
+    const int j = (F.hist_head + k) % M1;
+    const double a = F.rho[j] * blk_dot(F.S + (size_t)j * n, q, n, red);
+    if (threadIdx.x == 0) F.alpha[j] = a;
+    const double *yj = F.Y + (size_t)j * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = q[i] - a * yj[i];
+    __syncthreads();
+  }
+  const double scale = L > 0 ? F.gamma : 1.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = scale * q[i];
+  __syncthreads();
+  for (int k = 0; k < L; ++k) {
+    const int j = (F.hist_head + k) % M1;
+    const double b = F.rho[j] * blk_dot(F.Y + (size_t)j * n, q, n, red);
+    const double c = F.alpha[j] - b;
+    const double *sj = F.S + (size_t)j * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = q[i] + c * sj[i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = -q[i];
+  __syncthreads();
+  start_ls(F, red);
+}
+
+// A search ended without a strong-Wolfe point.  Fall back to (t_res > 0), or
+// clear the memory and retry once, or stop.
+__device__ void ls_fail(FitDev &F, double t_res, double *red) {
+  if (t_res > 0.0) {
+    if (threadIdx.x == 0) {
+      F.t = t_res;
+      F.phase = PH_ACCEPT_NEXT;
+    }
+    __syncthreads();
+    return;
+  }
+  if (F.hist_len > 0 && !F.reset_tried) {
+    for (int i = threadIdx.x; i < F.NK; i += blockDim.x) F.d[i] = -F.g[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      F.hist_len = 0;
+      F.reset_tried = 1;
+    }
+    __syncthreads();
+    start_ls(F, red);
+    return;
+  }
+  if (threadIdx.x == 0) fit_stop(F, ST_LSFAIL);
+  __syncthreads();
+}
+
+// grid: one block per map.  Consumes one evaluation at xt.
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
+  FitDev &F = Fs[blockIdx.x];
+  if (*F.active == 0) return;
+  __shared__ double red[40];
+  __shared__ int action;  // 0 continue with new t, 1 accept, 2 fail(lo), 3 fail(prev)
+  const int n = F.NK;
+  // gradient of f = -Phi at xt, gauge-projected, in graw
+  for (int i = threadIdx.x; i < n; i += blockDim.x) F.graw[i] = -F.graw[i];
+  __syncthreads();
+  blk_gauge(F, F.graw, red);
+  const double ft = -*F.phi_t;
+  if (threadIdx.x == 0) F.evals++;
+  if (F.phase == PH_INIT) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      F.g[i] = F.graw[i];
+      F.d[i] = -F.graw[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      F.f = ft;
+      if (!isfinite(ft)) {
+        fit_stop(F, ST_NONFINITE);
+      } else {
+        *F.assign_pending = 1;
+        if (F.max_iter == 0) F.phase = PH_STOP;
+      }
+    }
+    __syncthreads();
+    if (F.status == ST_RUNNING && F.phase == PH_INIT) start_ls(F, red);
+    return;
+  }
+  if (F.phase == PH_ACCEPT_NEXT) {
+    accept_trial(F, ft, red);
+    return;
+  }
+  const double dt = blk_dot(F.graw, F.d, n, red);
+  if (threadIdx.x == 0) {
+    const double t = F.t;
+    // a non-finite objective counts as no sufficient decrease
+    const bool too_big = !(ft <= F.f0 + LS_C1 * t * F.dphi0) || !isfinite(ft);
+    F.ls_evals++;
+    int act = 0;
+    if (F.phase == PH_BRACKET) {
+      if (too_big || (F.ls_evals > 1 && ft >= F.prev_f)) {
+        F.lo_t = F.prev_t; F.lo_f = F.prev_f; F.lo_d = F.prev_d;
+        F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
+        F.phase = PH_ZOOM;
+      } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
+        act = 1;
+      } else if (dt >= 0.0) {
+        F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
+        F.hi_t = F.prev_t; F.hi_f = F.prev_f; F.hi_d = F.prev_d;
+        F.phase = PH_ZOOM;
+      } else {
+        F.prev_t = t; F.prev_f = ft; F.prev_d = dt;
+        F.t = 2.0 * t;
+        if (F.ls_evals >= LS_MAX_EVALS) act = 3;
+      }
+    } else {  // PH_ZOOM
+      if (too_big || ft >= F.lo_f) {
+        F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
+      } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
+        act = 1;
+      } else {
+        if (dt * (F.hi_t - F.lo_t) >= 0.0) {
+          F.hi_t = F.lo_t; F.hi_f = F.lo_f; F.hi_d = F.lo_d;
+        }
+        F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
+      }
+    }
+    if (act == 0 && F.phase == PH_ZOOM) {
+      if (F.ls_evals >= LS_MAX_EVALS) act = 2;
+      else F.t = cubic_min(F.lo_t, F.lo_f, F.lo_d, F.hi_t, F.hi_f, F.hi_d);
+    }
+    action = act;
+  }
+  __syncthreads();
+  const int act = action;
+  if (act == 1) accept_trial(F, ft, red);
+  else if (act == 2) ls_fail(F, F.lo_t, red);
+  else if (act == 3) ls_fail(F, F.prev_t, red);
+}
+
+// Consume a pending accuracy check of the last accepted iterate (thread 0).
+__device__ inline void consume_acc(FitDev &F) {
+  if (*F.assign_pending == 0) return;
+  *F.assign_pending = 0;
+  F.acc = (double)*F.n_correct / (double)F.n_pix;
+  if (F.acc >= F.target_acc) {
+    F.status = ST_TARGET;
+    *F.active = 0;
+    F.clk_target = wall_clock64();
+  } else if (F.phase == PH_STOP) {
+    F.status = ST_BUDGET;
+    *F.active = 0;
+  }
+}
+
+// grid: one block per map.  Finishes the previous step's accuracy check, then
+// forms the trial point xt = x + t d and the evaluation input
+// thc = -(log2 e / eps) (xt - mean_i xt_i).
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
+  FitDev &F = Fs[blockIdx.x];
+  __shared__ double red[40];
+  if (threadIdx.x == 0) consume_acc(F);
+  __syncthreads();
+  if (*F.active == 0) return;
+  const double t = F.t;
+  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) F.xt[i] = F.x[i] + t * F.d[i];
+  __syncthreads();
+  for (int k = 0; k < F.K; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < F.N; i += blockDim.x) s += F.xt[(size_t)i * F.K + k];
+    const double mean = blk_sum(s, red) / (double)F.N;
+    for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+      F.thc[(size_t)i * F.K + k] = F.cscale * (F.xt[(size_t)i * F.K + k] - mean);
+  }
+}
+
+// Start of the fit on the device clock (before any warm start work).
+__global__ void k_fit_stamp(FitDev *Fs, int n_maps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_maps) Fs[p].clk_start = wall_clock64();
+}
+
+// grid: one block per map: project the start, reset the state.
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_start) {
+  FitDev &F = Fs[blockIdx.x];
+  __shared__ double red[40];
+  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+    if (zero_start) F.x[i] = 0.0;
+    F.d[i] = 0.0;
+  }
+  __syncthreads();
+  blk_gauge(F, F.x, red);
+  if (threadIdx.x == 0) {
+    F.status = ST_RUNNING;
+    F.phase = PH_INIT;
+    F.iters = F.evals = F.ls_evals = F.hist_len = F.hist_head = F.reset_tried = 0;
+    F.t = 0.0;
+    F.gamma = 1.0;
+    F.acc = -1.0;
+    F.clk_target = 0;
+    *F.active = 1;
+    *F.assign_pending = 0;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+#define FIT_HIP(ctx, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return pd_fail(ctx, PD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void pd_fit_release(pd_ctx *ctx) {
+  if (ctx->fit) {
+    if (ctx->fit->stream) hipStreamDestroy(ctx->fit->stream);
+    delete ctx->fit;
+    ctx->fit = nullptr;
+  }
+}
+
+pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *probs, int n, double *const *x,
+                        const void *mlp, int prec, hipStream_t s);
+
+// Objective + gradient of every running map at its trial point.
+static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, hipStream_t s) {
+  if (prec == 2) pd_bf16_plan_eval(ctx, P, s, false);
+  else pd_plan_eval(P, true, s, false);
+}
+
+extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
+                            double *const *theta_inout, const pd_fit_opts *opts,
+                            pd_fit_report *reports, void *stream) {
+  using clk = std::chrono::steady_clock;
+  const auto t_call = clk::now();
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!probs || n < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta_inout || !opts || !reports)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta_inout, opts and reports must be non-NULL");
+  int prec;
+  if (opts->prec == PD_FP64) prec = 0;
+  else if (opts->prec == PD_FP32) prec = 1;
+  else if (opts->prec == PD_BF16) prec = 2;
+  else return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown precision");
+  if (opts->gauge < PD_GAUGE_LAST_ZERO || opts->gauge > PD_GAUGE_NONE)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown gauge");
+  if (opts->init < PD_INIT_GIVEN || opts->init > PD_INIT_MLP)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown init");
+  if (opts->init == PD_INIT_MLP && opts->mlp == nullptr)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "PD_INIT_MLP needs opts->mlp");
+  if (opts->history < 1 || opts->history > 64)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "history must be in [1, 64]");
+  if (opts->max_iter < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (opts->check_every < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "check_every must be >= 1");
+  if (!(opts->gtol >= 0.0)) return pd_fail(ctx, PD_ERR_INVALID_ARG, "gtol must be >= 0");
+  for (int p = 0; p < n; ++p) {
+    if (!theta_inout[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta_inout entry is NULL");
+  }
+  pd_status st = pd_validate(ctx, probs, n, stream);
+  if (st != PD_OK) return st;
+  FIT_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->fit) ctx->fit = new FitState();
+  if (!ctx->fit->stream) FIT_HIP(ctx, hipStreamCreateWithFlags(&ctx->fit->stream, hipStreamNonBlocking));
+  hipStream_t s = ctx->fit->stream;
+  // the fit starts after the caller's earlier work on its stream
+  FIT_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+
+  // ---- layout: evaluation plan + fit state
+  const int eval_prec = prec == 2 ? 2 : prec;
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n, eval_prec == 2 ? 1 : eval_prec);
+  const int m = opts->history;
+  std::vector<size_t> o_vec(n);
+  for (int p = 0; p < n; ++p) {
+    const size_t NK = (size_t)P.maps[p].N * P.maps[p].K;
+    o_vec[p] = L.take(sizeof(double) * (5 * NK + 2 * (size_t)(m + 1) * NK + 2 * (size_t)(m + 1)));
+  }
+  const size_t o_F = L.take(sizeof(FitDev) * n);
+  const size_t o_flags = L.take(sizeof(int32_t) * 2 * n);
+  const size_t o_phi = L.take(sizeof(double) * n);
+  const size_t o_nc = L.take(sizeof(int64_t) * n);
+  const size_t o_amaps = L.take(sizeof(MapDev) * n);
+  st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  char *base = ctx->ws;
+  std::vector<FitDev> F(n);
+  std::vector<double *> xt(n), graw(n);
+  int32_t *flags = (int32_t *)(base + o_flags);
+  double *phi_t = (double *)(base + o_phi);
+  int64_t *nc = (int64_t *)(base + o_nc);
+  for (int p = 0; p < n; ++p) {
+    const MapDev &M = P.maps[p];
+    const size_t NK = (size_t)M.N * M.K;
+    double *v = (double *)(base + o_vec[p]);
+    FitDev &f = F[p];
+    memset(&f, 0, sizeof(FitDev));
+    f.N = M.N;
+    f.K = M.K;
+    f.NK = (int32_t)NK;
+    f.m = m;
+    f.max_iter = opts->max_iter;
+    f.check_every = opts->check_every;
+    f.gauge = (int)opts->gauge;
+    f.n_pix = (int64_t)M.H * M.W;
+    f.target_acc = opts->target_acc;
+    f.gtol = opts->gtol;
+    f.x = v;
+    f.g = v + NK;
+    f.d = v + 2 * NK;
+    f.xt = v + 3 * NK;
+    f.graw = v + 4 * NK;
+    f.S = v + 5 * NK;
+    f.Y = f.S + (size_t)(m + 1) * NK;
+    f.rho = f.Y + (size_t)(m + 1) * NK;
+    f.alpha = f.rho + (m + 1);
+    f.phi_t = phi_t + p;
+    f.cscale = -PD_LOG2E / M.eps;
+    f.n_correct = nc + p;
+    f.active = flags + p;
+    f.assign_pending = flags + n + p;
+    xt[p] = f.xt;
+    graw[p] = f.graw;
+  }
+  pd_plan_bind(P, base, xt.data(), phi_t, graw.data(), nullptr, nullptr);
+  for (int p = 0; p < n; ++p) F[p].thc = P.maps[p].thc;
+  for (int p = 0; p < n; ++p) P.maps[p].gate = flags + p;
+  // assignment view of the same maps: theta = x, gate = assign_pending
+  std::vector<MapDev> amaps = P.maps;
+  for (int p = 0; p < n; ++p) {
+    amaps[p].theta = F[p].x;
+    amaps[p].n_correct = nc + p;
+    amaps[p].labels_out = nullptr;
+    amaps[p].gate = flags + n + p;
+  }
+  MapDev *d_amaps = (MapDev *)(base + o_amaps);
+  FitDev *dF = (FitDev *)(base + o_F);
+  FIT_HIP(ctx, pd_plan_upload(ctx, P, s));
+  FIT_HIP(ctx, hipMemcpyAsync(d_amaps, amaps.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
+  FIT_HIP(ctx, hipMemcpyAsync(dF, F.data(), sizeof(FitDev) * n, hipMemcpyHostToDevice, s));
+  const bool zero_start = opts->init == PD_INIT_ZERO;
+  if (!zero_start)
+    for (int p = 0; p < n; ++p)
+      FIT_HIP(ctx, hipMemcpyAsync(F[p].x, theta_inout[p], sizeof(double) * F[p].NK,
+                                  hipMemcpyDeviceToDevice, s));
+  const auto t_stamp = clk::now();
+  k_fit_stamp<<<(n + 255) / 256, 256, 0, s>>>(dF, n);
+  pd_plan_tables(P, s);
+  if (opts->init == PD_INIT_MLP) {
+    std::vector<double *> xs(n);
+    for (int p = 0; p < n; ++p) xs[p] = F[p].x;
+    st = pd_warm_start(ctx, probs, n, xs.data(), opts->mlp, eval_prec, s);
+    if (st != PD_OK) return st;
+  }
+  k_fit_init<<<n, FIT_THREADS, 0, s>>>(dF, zero_start ? 1 : 0);
+  FIT_HIP(ctx, hipGetLastError());
+
+  // ---- one step, captured as a graph
+  auto step = [&](hipStream_t ss) {
+    k_fit_trial<<<n, FIT_THREADS, 0, ss>>>(dF);
+    pd_fit_eval(ctx, P, eval_prec, ss);
+    k_fit_decide<<<n, FIT_THREADS, 0, ss>>>(dF);
+    pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], ss);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  FIT_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  step(s);
+  hipError_t ce = hipStreamEndCapture(s, &graph);
+  if (ce != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ce != hipSuccess) {
+    hipGraphDestroy(graph);
+    return pd_fail(ctx, PD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+  }
+  // ---- replay until every map has stopped
+  int32_t *h_flags = nullptr;
+  FIT_HIP(ctx, hipHostMalloc((void **)&h_flags, sizeof(int32_t) * n, hipHostMallocDefault));
+  const long long max_steps = (long long)(opts->max_iter + 2) * (2 * LS_MAX_EVALS + 4) + 8;
+  long long steps = 0;
+  int poll = 2;
+  hipError_t le = hipSuccess;
+  while (steps < max_steps) {
+    for (int k = 0; k < poll && le == hipSuccess; ++k, ++steps) le = hipGraphLaunch(exec, s);
+    if (le != hipSuccess) break;
+    le = hipMemcpyAsync(h_flags, flags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+    if (le != hipSuccess) break;
+    le = hipStreamSynchronize(s);
+    if (le != hipSuccess) break;
+    bool any = false;
+    for (int p = 0; p < n; ++p) any |= h_flags[p] != 0;
+    if (!any) break;
+    if (poll < 16) poll *= 2;
+  }
+  hipGraphExecDestroy(exec);
+  hipGraphDestroy(graph);
+  hipHostFree(h_flags);
+  if (le != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("fit loop: ") + hipGetErrorString(le));
+  // ---- final accuracy of every map and the results
+  std::vector<MapDev> fin = amaps;
+  for (int p = 0; p < n; ++p) fin[p].gate = nullptr;
+  FIT_HIP(ctx, hipMemcpyAsync(d_amaps, fin.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
+  pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], s);
+  std::vector<int64_t> h_nc(n);
+  FIT_HIP(ctx, hipMemcpyAsync(h_nc.data(), nc, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+  FIT_HIP(ctx, hipMemcpyAsync(F.data(), dF, sizeof(FitDev) * n, hipMemcpyDeviceToHost, s));
+  for (int p = 0; p < n; ++p)
+    FIT_HIP(ctx, hipMemcpyAsync(theta_inout[p], F[p].x, sizeof(double) * F[p].NK,
+                                hipMemcpyDeviceToDevice, s));
+  FIT_HIP(ctx, hipStreamSynchronize(s));
+  const auto t_end = clk::now();
+  int rate_khz = 0;
+  hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
+  const double host_setup = std::chrono::duration<double>(t_stamp - t_call).count();
+  for (int p = 0; p < n; ++p) {
+    pd_fit_report &r = reports[p];
+    const FitDev &f = F[p];
+    r.status = f.status == ST_RUNNING ? ST_BUDGET : f.status;
+    r.iters = f.iters;
+    r.evals = f.evals;
+    r.phi = -f.f;
+    r.acc = (double)h_nc[p] / (double)f.n_pix;
+    r.seconds_total = std::chrono::duration<double>(t_end - t_call).count();
+    r.seconds_to_target = -1.0;
+    // host set-up before the first device work, plus device time to the target
+    if (f.status == ST_TARGET && rate_khz > 0 && f.clk_target >= f.clk_start)
+      r.seconds_to_target =
+          host_setup + (double)(f.clk_target - f.clk_start) / ((double)rate_khz * 1e3);
+    // a stop (gradient tolerance, failed search) at an iterate whose accuracy
+    // check was still pending: the accuracy test comes first
+    if (r.status != ST_TARGET && r.acc >= opts->target_acc) {
+      r.status = ST_TARGET;
+      r.seconds_to_target = r.seconds_total;
+    }
+  }
+  return PD_OK;
 }

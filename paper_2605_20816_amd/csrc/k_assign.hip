@@ -51,6 +51,7 @@ __device__ inline void assign_item(const MapDev &M, int local, int lane) {
   if (lane == 0) pd_glb(M.part_c)[local] = tot;
 }
 
+template <int DMAX>
 __global__ __launch_bounds__(PD_BLOCK) void k_assign(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
                                                      int total) {
@@ -60,13 +61,14 @@ __global__ __launch_bounds__(PD_BLOCK) void k_assign(const MapDev *__restrict__ 
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
-  PD_DISPATCH_D(M.d, (assign_item<D>(M, item - off[m], lane)));
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (assign_item<D>(M, item - off[m], lane)));
 }
 
 // One block per map: fixed-order sum of the per-wave correct counts.
 __global__ __launch_bounds__(PD_BLOCK) void k_reduce_count(const MapDev *__restrict__ maps) {
   const MapDev &M = maps[blockIdx.x];
-  if (M.n_correct == nullptr) return;
+  if (M.n_correct == nullptr || PD_GATED(M)) return;
   __shared__ long long red[PD_BLOCK];
   long long s = 0;
   for (int t = threadIdx.x; t < M.a_items; t += PD_BLOCK) s += M.part_c[t];
@@ -93,10 +95,15 @@ __global__ __launch_bounds__(PD_BLOCK) void k_validate(const MapDev *__restrict_
   if (b) bad[blockIdx.y] = 1;
 }
 
-void pd_launch_assign(const MapDev *maps, const int32_t *off, int n_maps, int total,
+void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  k_assign<<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  switch (dmax) {
+    case 2: k_assign<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    case 4: k_assign<4><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    case 6: k_assign<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    default: k_assign<8><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+  }
   k_reduce_count<<<n_maps, PD_BLOCK, 0, s>>>(maps);
 }
 

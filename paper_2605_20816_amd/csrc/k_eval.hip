@@ -26,7 +26,34 @@
 
 template <typename T> __device__ inline T pd_exp2(T x);
 template <> __device__ inline float pd_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ inline double pd_exp2<double>(double x) { return exp2(x); }
+// FP64 2^t for t <= 0 (the only arguments the kernels form: a logit minus a
+// running maximum or minus the log-sum-exp).  Range reduction t = n + f with
+// n = rint(t), |f| <= 1/2; 2^f = exp(f ln 2) by its Taylor series
+// sum_k (ln 2)^k f^k / k! to degree 13 (truncation error below 2^-58 on
+// |f| <= 1/2) in Horner form; 2^n applied exactly by ldexp, which also yields
+// the subnormal and zero results.  Arguments below -1100 are clamped (the
+// result is 0 either way); NaN propagates through the comparison.
+__device__ inline double pd_exp2_nonpos(double t) {
+  t = (t < -1100.0) ? -1100.0 : t;
+  const double n = __builtin_rint(t);
+  const double f = t - n;
+  double p = 1.3691488853904124e-12;
+  p = __builtin_fma(p, f, 2.5678435993488196e-11);
+  p = __builtin_fma(p, f, 4.44553827187081e-10);
+  p = __builtin_fma(p, f, 7.054911620801121e-09);
+  p = __builtin_fma(p, f, 1.0178086009239696e-07);
+  p = __builtin_fma(p, f, 1.3215486790144305e-06);
+  p = __builtin_fma(p, f, 1.5252733804059838e-05);
+  p = __builtin_fma(p, f, 0.00015403530393381606);
+  p = __builtin_fma(p, f, 0.0013333558146428441);
+  p = __builtin_fma(p, f, 0.009618129107628477);
+  p = __builtin_fma(p, f, 0.055504108664821576);
+  p = __builtin_fma(p, f, 0.2402265069591007);
+  p = __builtin_fma(p, f, 0.6931471805599453);
+  p = __builtin_fma(p, f, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+template <> __device__ inline double pd_exp2<double>(double x) { return pd_exp2_nonpos(x); }
 template <typename T> __device__ inline T pd_log2(T x);
 template <> __device__ inline float pd_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
 template <> __device__ inline double pd_log2<double>(double x) { return log2(x); }
@@ -74,7 +101,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_tables(const MapDev *__restrict__ 
 __global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ maps) {
   const MapDev &M = maps[blockIdx.y];
   const int k = blockIdx.x;
-  if (k >= M.K) return;
+  if (k >= M.K || PD_GATED(M)) return;
   __shared__ double red[PD_BLOCK];
   double s = 0.0;
   for (int i = threadIdx.x; i < M.N; i += PD_BLOCK) s += M.theta[(size_t)i * M.K + k];
@@ -120,6 +147,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
                                                    const int32_t *__restrict__ off, int n_maps) {
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
   const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
   if (flat >= (long long)M.H * M.Npad) return;
   const int r = (int)(flat / M.Npad), i = (int)(flat - (long long)r * M.Npad);
@@ -182,7 +210,7 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
 }
 
-template <typename T>
+template <typename T, int DMAX>
 __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ maps,
                                                   const int32_t *__restrict__ off, int n_maps,
                                                   int total) {
@@ -192,15 +220,63 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
-  PD_DISPATCH_D(M.d, (lse_item<T, D>(M, item - off[m], lane)));
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (lse_item<T, D>(M, item - off[m], lane)));
 }
 
 // ---------------------------------------------------------------------------
 // Kernel B: partial gradient moments per (pixel tile, 64-grain group).
+// Columns are processed 8 at a time so the wave-uniform column data (P_a(x1),
+// lse, label) arrives in a few wide scalar loads per chunk; the one-hot term
+// (delta_{i,G(x)}) is applied only when a label of the chunk falls in this
+// wave's grain group, tested on the scalar unit.
+template <typename T, int D, int CH>
+__device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *lp,
+                                 const PD_AS_CONST int32_t *gp, const T (&cf)[D + 1],
+                                 T (&racc)[D + 1], int gbase, int lane) {
+  constexpr int DP = D + 1;
+  T px[CH][DP];
+  T l[CH];
+  int g[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+#pragma unroll
+    for (int a = 1; a < DP; ++a) px[j][a] = pxp[j * DP + a];
+    l[j] = lp[j];
+    g[j] = gp[j];
+  }
+  unsigned hit = 0;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) hit |= ((unsigned)(g[j] - gbase) < (unsigned)PD_WAVE) ? (1u << j) : 0u;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    T s = cf[0];
+#pragma unroll
+    for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], px[j][a], s);
+    const T p = pd_exp2<T>(s - l[j]);
+    racc[0] += p;
+#pragma unroll
+    for (int a = 1; a < DP; ++a) racc[a] = pd_fma(p, px[j][a], racc[a]);
+  }
+  if (hit) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if ((hit >> j) & 1u) {
+        if (lane == g[j] - gbase) {
+          racc[0] -= (T)1;
+#pragma unroll
+          for (int a = 1; a < DP; ++a) racc[a] -= px[j][a];
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int D>
 __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
+  constexpr int CH = 8;
   const int groups = M.Npad / PD_WAVE;
   const int tile = local / groups;
   const int grp = local - tile * groups;
@@ -223,29 +299,11 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
     for (int a = 0; a < DP; ++a) racc[a] = (T)0;
     const auto lrow = pd_uni((const T *)M.lse + (size_t)r * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
-    for (int c = c0; c < c1; ++c) {
-      const auto pxp = txT + (size_t)c * DP;
-      T px[DP];
-#pragma unroll
-      for (int a = 1; a < DP; ++a) px[a] = pxp[a];
-      const T l = lrow[c];
-      const int g = grow[c];
-      T s = cf[0];
-#pragma unroll
-      for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], px[a], s);
-      const T p = pd_exp2<T>(s - l);
-      racc[0] += p;
-#pragma unroll
-      for (int a = 1; a < DP; ++a) racc[a] = pd_fma(p, px[a], racc[a]);
-      const int gl = g - gbase;
-      if ((unsigned)gl < (unsigned)PD_WAVE) {
-        if (lane == gl) {
-          racc[0] -= (T)1;
-#pragma unroll
-          for (int a = 1; a < DP; ++a) racc[a] -= px[a];
-        }
-      }
-    }
+    int c = c0;
+    for (; c + CH <= c1; c += CH)
+      grad_cols<T, D, CH>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, gbase, lane);
+    for (; c < c1; ++c)
+      grad_cols<T, D, 1>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, gbase, lane);
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -262,7 +320,7 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   for (int k = 0; k < K; ++k) out[k] = q[k];
 }
 
-template <typename T>
+template <typename T, int DMAX>
 __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ maps,
                                                    const int32_t *__restrict__ off, int n_maps,
                                                    int total) {
@@ -272,14 +330,14 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ ma
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
-  PD_DISPATCH_D(M.d, (grad_item<T, D>(M, item - off[m], lane)));
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D>(M, item - off[m], lane)));
 }
 
 // ---------------------------------------------------------------------------
 // Fixed-order reductions.  Phi: one block per map.  Gradient: one thread per
 // (map, i, k), summing the tiles in order.
-__global__ __launch_bounds__(PD_BLOCK) void k_reduce_phi(const MapDev *__restrict__ maps) {
-  const MapDev &M = maps[blockIdx.x];
+__device__ inline void reduce_phi_block(const MapDev &M) {
   __shared__ double red[PD_BLOCK];
   double s = 0.0;
   for (int t = threadIdx.x; t < M.a_items; t += PD_BLOCK) s += M.part_l[t];
@@ -292,21 +350,61 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce_phi(const MapDev *__restric
   if (threadIdx.x == 0) *M.phi = PD_LN2 * red[0] / ((double)M.H * (double)M.W);
 }
 
-__global__ __launch_bounds__(PD_BLOCK) void k_reduce_grad(const MapDev *__restrict__ maps,
-                                                          const int32_t *__restrict__ off,
-                                                          int n_maps) {
-  const int m = pd_find_map(off, n_maps, blockIdx.x);
-  const MapDev &M = maps[m];
-  if (M.grad == nullptr) return;
-  const int o = (blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
-  if (o >= M.N * M.K) return;
-  const int i = o / M.K, k = o - i * M.K;
+// Gradient: a block covers 16 consecutive outputs (i, k) x 16 tile phases;
+// thread (o, ph) sums tiles ph, ph + 16, ... in order, then the 16 phase sums
+// are added by a fixed tree.
+#define RG_OUT 16
+#define RG_PH 16
+__device__ inline void reduce_grad_block(const MapDev &M, int chunk) {
+  __shared__ double red[RG_PH][RG_OUT + 1];
+  const int ol = threadIdx.x % RG_OUT, ph = threadIdx.x / RG_OUT;
+  const int o = chunk * RG_OUT + ol;
+  const int NK = M.N * M.K;
   const int tiles = M.tiles_r * M.tiles_c;
-  const double *src = M.part_g + (size_t)i * M.K + k;
-  const size_t stride = (size_t)M.Npad * M.K;
   double s = 0.0;
-  for (int t = 0; t < tiles; ++t) s += src[(size_t)t * stride];
-  M.grad[o] = s * M.grad_scale;
+  if (o < NK) {
+    const int i = o / M.K, k = o - i * M.K;
+    const auto src = pd_glb(M.part_g + (size_t)i * M.K + k);
+    const size_t stride = (size_t)M.Npad * M.K;
+    int t = ph;
+    for (; t + 3 * RG_PH < tiles; t += 4 * RG_PH) {
+      const double v0 = src[(size_t)t * stride];
+      const double v1 = src[(size_t)(t + RG_PH) * stride];
+      const double v2 = src[(size_t)(t + 2 * RG_PH) * stride];
+      const double v3 = src[(size_t)(t + 3 * RG_PH) * stride];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; t < tiles; t += RG_PH) s += src[(size_t)t * stride];
+  }
+  red[ph][ol] = s;
+  __syncthreads();
+  for (int w = RG_PH / 2; w > 0; w >>= 1) {
+    if (ph < w) red[ph][ol] += red[ph + w][ol];
+    __syncthreads();
+  }
+  if (ph == 0 && o < NK) M.grad[o] = red[0][ol] * M.grad_scale;
+}
+
+// One launch for both reductions: blocks [0, n_maps) reduce Phi of map b;
+// the following blocks reduce gradient chunks (offsets in off, n_maps + 1).
+__global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps,
+                                                     int with_grad) {
+  if ((int)blockIdx.x < n_maps) {
+    const MapDev &M = maps[blockIdx.x];
+    if (PD_GATED(M)) return;
+    reduce_phi_block(M);
+    return;
+  }
+  if (!with_grad) return;
+  const int b = blockIdx.x - n_maps;
+  const int m = pd_find_map(off, n_maps, b);
+  const MapDev &M = maps[m];
+  if (M.grad == nullptr || PD_GATED(M)) return;
+  reduce_grad_block(M, b - off[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,22 +459,29 @@ void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps
   if (prec == 0) k_prep<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
   else k_prep<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
 }
-void pd_launch_lse(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
-                   hipStream_t s) {
+#define PD_LAUNCH_BY_DMAX(KERNEL, T, dmax, blocks, s, ...)                    \
+  switch (dmax) {                                                            \
+    case 2: KERNEL<T, 2><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;    \
+    case 4: KERNEL<T, 4><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;    \
+    case 6: KERNEL<T, 6><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;    \
+    default: KERNEL<T, 8><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;   \
+  }
+
+void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                   int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  if (prec == 0) k_lse<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
-  else k_lse<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse, double, dmax, blocks, s, maps, off, n_maps, total); }
+  else { PD_LAUNCH_BY_DMAX(k_lse, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
-void pd_launch_grad(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
-                    hipStream_t s) {
+void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                    int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  if (prec == 0) k_grad<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
-  else k_grad<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total);
+  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_grad, double, dmax, blocks, s, maps, off, n_maps, total); }
+  else { PD_LAUNCH_BY_DMAX(k_grad, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
                       bool grad, hipStream_t s) {
-  k_reduce_phi<<<n_maps, PD_BLOCK, 0, s>>>(maps);
-  if (grad && blocks_r > 0) k_reduce_grad<<<blocks_r, PD_BLOCK, 0, s>>>(maps, off_r, n_maps);
+  k_reduce<<<n_maps + (grad ? blocks_r : 0), PD_BLOCK, 0, s>>>(maps, off_r, n_maps, grad ? 1 : 0);
 }
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s) {
   const long long blocks = (n + PD_BLOCK - 1) / PD_BLOCK;

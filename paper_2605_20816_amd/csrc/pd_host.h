@@ -43,7 +43,7 @@ struct EvalPlan {
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;
   std::vector<int32_t> offA, offB, offP, offR;
-  int max_hw = 0, max_k = 0;
+  int max_hw = 0, max_k = 0, dmax = 8;
   size_t o_maps = 0, o_off = 0;
   MapDev *d_maps = nullptr;
   int32_t *d_offA = nullptr, *d_offB = nullptr, *d_offP = nullptr, *d_offR = nullptr;
@@ -57,10 +57,17 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
                   double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
 void pd_plan_tables(const EvalPlan &P, hipStream_t s);
-void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s);
+// center: run k_center (thc from theta); the fit driver forms thc itself.
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center);
 void pd_plan_assign(const EvalPlan &P, hipStream_t s);
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
                                  const double *const *theta, double *phi_out,
                                  double *const *grad_out, hipStream_t s);
 void pd_fit_release(pd_ctx *ctx);
+// BF16 path: time its prep / matrix-core stages, recording ev[1], ev[2], ev[3]
+// (the PREP, LSE and GRAD slots).
+void pd_bf16_profile_stages(pd_ctx *ctx, const EvalPlan &P, int reps, hipStream_t s,
+                            hipEvent_t *ev);
+// BF16 matrix-core evaluation of a plan laid out with FP32 buffers.
+void pd_bf16_plan_eval(pd_ctx *ctx, const EvalPlan &P, hipStream_t s, bool center);

@@ -47,7 +47,10 @@ struct MapDev {
   int32_t *labels_out;              // n or null
   int64_t *n_correct;               // -> n_correct_out[map] or null
   int64_t *part_c;                  // [a_items] per-wave correct counts
+  // optional gate: when non-null and zero, every kernel skips this map
+  const int32_t *gate;
 };
+
 
 // Run CALL with the compile-time degree D = dval (1..PD_DMAX).
 #define PD_DISPATCH_D(dval, CALL)                 \
@@ -62,6 +65,26 @@ struct MapDev {
     case 8: { constexpr int D = 8; CALL; } break; \
     default: break;                               \
   }
+
+// The same, restricted to D <= DMAX (a compile-time bound chosen per launch so
+// registers are sized for the largest degree actually present).
+#define PD_DISPATCH_UPTO(DMAX, dval, CALL)                          \
+  switch (dval) {                                                   \
+    case 1: if constexpr (DMAX >= 1) { constexpr int D = 1; CALL; } break; \
+    case 2: if constexpr (DMAX >= 2) { constexpr int D = 2; CALL; } break; \
+    case 3: if constexpr (DMAX >= 3) { constexpr int D = 3; CALL; } break; \
+    case 4: if constexpr (DMAX >= 4) { constexpr int D = 4; CALL; } break; \
+    case 5: if constexpr (DMAX >= 5) { constexpr int D = 5; CALL; } break; \
+    case 6: if constexpr (DMAX >= 6) { constexpr int D = 6; CALL; } break; \
+    case 7: if constexpr (DMAX >= 7) { constexpr int D = 7; CALL; } break; \
+    case 8: if constexpr (DMAX >= 8) { constexpr int D = 8; CALL; } break; \
+    default: break;                                                 \
+  }
+
+// Smallest compiled degree bound (2, 4, 6 or 8) covering max_degree.
+inline int pd_dmax_bucket(int max_degree) {
+  return max_degree <= 2 ? 2 : max_degree <= 4 ? 4 : max_degree <= 6 ? 6 : 8;
+}
 
 // Wave-uniform map lookup: largest m with off[m] <= item (off has n+1 entries).
 __device__ inline int pd_find_map(const int32_t *__restrict__ off, int n, int item) {
@@ -91,6 +114,9 @@ __device__ inline const PD_AS_GLOBAL T *pd_glb(const T *p) {
   return (const PD_AS_GLOBAL T *)(p);
 }
 
+// True when the map's gate is closed (the map is skipped by every kernel).
+#define PD_GATED(M) ((M).gate != nullptr && *pd_uni((M).gate) == 0)
+
 // Index of multi-index alpha = (a, b) in the degree-graded order.
 __host__ __device__ constexpr int pd_alpha_index(int a, int b) {
   return (a + b) * (a + b + 1) / 2 + b;
@@ -113,13 +139,13 @@ void pd_launch_tables(int prec, const MapDev *maps, int n_maps, int max_hw, hipS
 void pd_launch_center(const MapDev *maps, int n_maps, int max_k, hipStream_t s);
 void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps, int blocks,
                     hipStream_t s);
-void pd_launch_lse(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
-                   hipStream_t s);
-void pd_launch_grad(int prec, const MapDev *maps, const int32_t *off, int n_maps, int total,
-                    hipStream_t s);
+void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                   int total, hipStream_t s);
+void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                    int total, hipStream_t s);
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
                       bool grad, hipStream_t s);
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s);
-void pd_launch_assign(const MapDev *maps, const int32_t *off, int n_maps, int total,
+void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       hipStream_t s);
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);

@@ -1,0 +1,127 @@
+"""GPU parity of the device L-BFGS driver (pd_fit) against the oracle's L-BFGS."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def problem(pdl, gm, d, eps):
+    return pdl.Problem(dev(gm.labels, torch.int32), gm.H, gm.W, gm.N, d, eps)
+
+
+def oracle_fit(orc, gm, d, eps, **kw):
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    acc = lambda th: orc.assign(th, gm.H, gm.W, d, gm.labels)[1] / (gm.H * gm.W)
+    return orc.lbfgs_fit(obj, np.zeros((gm.N, orc.num_features(d))), accuracy=acc, **kw)
+
+
+@pytest.mark.parametrize("iters", [1, 3, 8])
+def test_first_iterates_match_oracle(pd, orc, iters):
+    """Same state machine, same arithmetic up to summation order: the first
+    iterates agree to ~1e-9 and the evaluation counts are identical."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    ref = oracle_fit(orc, gm, 1, 1e-2, target_acc=2.0, max_iter=iters)
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="zero", max_iter=iters,
+                  target_acc=2.0)[0]
+    assert rep["iters"] == ref["iters"] == iters
+    assert rep["evals"] == ref["evals"]
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x - ref["theta"])) <= 1e-8 * np.max(np.abs(ref["theta"]))
+    assert abs(rep["phi"] - ref["phi"]) <= 1e-10 * abs(ref["phi"])
+    assert x[-1].tolist() == [0.0, 0.0, 0.0]
+
+
+def test_power_diagram_fit_reaches_99(pd, orc):
+    """Section 5.4 protocol on the 64x64 N = 8 power-diagram map: theta = 0,
+    eps = 1e-2, FP64 L-BFGS to >= 99% pixel accuracy; the same iteration count as
+    the oracle (trajectories agree), accuracy recomputed by the oracle."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    ref = oracle_fit(orc, gm, 1, 1e-2, target_acc=0.99, max_iter=2000)
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="zero", max_iter=2000,
+                  target_acc=0.99)[0]
+    assert rep["status"] == "target" and rep["acc"] >= 0.99
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
+    assert nc / (gm.H * gm.W) == rep["acc"]
+    assert abs(rep["iters"] - ref["iters"]) <= 2, (rep["iters"], ref["iters"])
+    assert rep["seconds_to_target"] > 0
+
+
+def test_fp32_fit_reaches_99(pd, orc):
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp32", init="zero", max_iter=2000,
+                  target_acc=0.99)[0]
+    assert rep["status"] == "target"
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
+    assert nc / (gm.H * gm.W) >= 0.99
+
+
+def test_nonseparable_fit_matches_newton(pd, orc):
+    """Proposition 4.11: unique gauge-fixed maximiser, found by the device fit and
+    by the oracle's dense Newton solve."""
+    pdl, ctx = pd
+    rng = np.random.default_rng(10)
+    H, W, N, d, eps = 8, 9, 3, 2, 0.5
+    lab = synth.random_labels(H, W, N, rng)
+    obj = lambda th: orc.objective_grad(th, lab, H, W, d, eps)
+    hes = lambda th: orc.hessian(th, lab, H, W, d, eps)
+    xn = orc.newton_fit(np.zeros((N, 6)), obj, hes)
+    th = dev(np.zeros((N, 6)))
+    rep = ctx.fit([pdl.Problem(dev(lab, torch.int32), H, W, N, d, eps)], [th], "fp64",
+                  init="zero", max_iter=500, target_acc=2.0, gtol=1e-12)[0]
+    assert rep["status"] in ("gtol", "linesearch", "budget")
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x - xn)) <= 1e-6 * np.max(np.abs(xn))
+
+
+def test_batched_fit_equals_single(pd, orc):
+    pdl, ctx = pd
+    rng = np.random.default_rng(3)
+    maps = [synth.config_c1(), synth.power_diagram(40, 56, 6, rng),
+            synth.anisotropic_power_diagram(48, 48, 9, rng)]
+    degs = [1, 1, 2]
+    probs = [problem(pdl, gm, d, 1e-2) for gm, d in zip(maps, degs)]
+    ths = [dev(np.zeros((gm.N, pdl.num_features(d)))) for gm, d in zip(maps, degs)]
+    reps = ctx.fit(probs, ths, "fp64", init="zero", max_iter=300, target_acc=0.99)
+    for k, (p, gm, d) in enumerate(zip(probs, maps, degs)):
+        t1 = dev(np.zeros((gm.N, pdl.num_features(d))))
+        r1 = ctx.fit([p], [t1], "fp64", init="zero", max_iter=300, target_acc=0.99)[0]
+        assert torch.equal(t1, ths[k])
+        assert (r1["iters"], r1["evals"], r1["status"]) == (reps[k]["iters"], reps[k]["evals"],
+                                                           reps[k]["status"])
+
+
+def test_centered_gauge_and_given_start(pd, orc):
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    rng = np.random.default_rng(4)
+    th0 = rng.normal(size=(gm.N, 3)) * 0.01
+    th = dev(th0)
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", gauge="centered", init="given",
+                  max_iter=200, target_acc=0.99)[0]
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x.sum(0))) <= 1e-12 * np.max(np.abs(x)) * gm.N
+    assert rep["status"] == "target"
+
+
+def test_zero_budget_returns_start(pd, orc):
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="zero", max_iter=0,
+                  target_acc=0.99)[0]
+    assert rep["iters"] == 0 and rep["status"] == "budget"
+    assert abs(rep["phi"] + np.log(gm.N)) < 1e-12
+    assert torch.all(th == 0)
