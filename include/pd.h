@@ -140,7 +140,7 @@ typedef struct {
   pd_precision prec;      /* arithmetic of the objective/gradient evaluations   */
   pd_gauge gauge;         /* PD_GAUGE_LAST_ZERO (paper) or PD_GAUGE_CENTERED     */
   pd_init init;           /* PD_INIT_GIVEN uses theta_inout as the start         */
-  int32_t history;        /* L-BFGS memory, 1..64 (default 10)                   */
+  int32_t history;        /* L-BFGS memory, 1..32 (default 10)                   */
   int32_t max_iter;       /* iteration budget (paper: 1000 or 2000)              */
   double target_acc;      /* stop at Acc >= target_acc (e.g. 0.99); > 1 disables */
   double gtol;            /* stop at ||grad||_inf <= gtol (0 disables)           */

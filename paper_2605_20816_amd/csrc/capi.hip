@@ -57,13 +57,13 @@ pd_status pd_reserve(pd_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->ws_cap) return PD_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
-  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
   ctx->ws_cap = 0;
   const size_t want = bytes + bytes / 4 + (1 << 20);
   e = hipMalloc((void **)&ctx->ws, want);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return pd_fail(ctx, PD_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
   }
   ctx->ws_cap = want;
@@ -115,7 +115,8 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     choose_tiles(M.H, M.W, M.Npad, P.target_waves, M.tile_rows, M.tile_cols);
     M.tiles_r = (M.H + M.tile_rows - 1) / M.tile_rows;
     M.tiles_c = (M.W + M.tile_cols - 1) / M.tile_cols;
-    M.a_items = M.H * M.segs;
+    // row-segment items, padded to whole blocks so a block never spans two maps
+    M.a_items = (M.H * M.segs + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
     M.b_items = M.tiles_r * M.tiles_c * (M.Npad / PD_WAVE);
     M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
     const long long n_px = (long long)M.H * M.W;
@@ -188,7 +189,7 @@ hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (total > ctx->stage_cap) {
-    if (ctx->stage) hipHostFree(ctx->stage);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
     ctx->stage = nullptr;
     ctx->stage_cap = 0;
     e = hipHostMalloc((void **)&ctx->stage, total * 2, hipHostMallocDefault);
@@ -246,7 +247,7 @@ pd_status pd_create(int device, pd_ctx **out) {
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return PD_ERR_HIP;
   }
   if (device < 0 || device >= count) return PD_ERR_INVALID_ARG;
@@ -259,11 +260,11 @@ pd_status pd_create(int device, pd_ctx **out) {
 
 void pd_destroy(pd_ctx *ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
-  if (ctx->ws) hipFree(ctx->ws);
-  if (ctx->stage) hipHostFree(ctx->stage);
-  if (ctx->staged) hipEventDestroy(ctx->staged);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
+  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   pd_fit_release(ctx);
   delete ctx;
 }
@@ -446,7 +447,7 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     PD_HIP(ctx, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
     ms_out[k] = (double)ms / reps;
   }
-  for (auto &e : ev) hipEventDestroy(e);
+  for (auto &e : ev) (void)hipEventDestroy(e);
   return PD_OK;
 }
 

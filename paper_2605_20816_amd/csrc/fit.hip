@@ -20,6 +20,8 @@
 #include "pd_host.h"
 
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -38,7 +40,8 @@ struct FitDev {
   int32_t N, K, NK, m, max_iter, check_every, gauge;
   int64_t n_pix;
   double target_acc, gtol;
-  double *x, *g, *d, *xt, *graw, *S, *Y, *rho, *alpha;
+  double *x, *g, *d, *xt, *graw, *S, *Y, *rho;
+  double *SY, *YY, *Sg, *Yg;  // Gram matrices s_j.y_k, y_j.y_k over the m+1 ring slots; S^T g, Y^T g
   const double *phi_t;
   const int64_t *n_correct;
   double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
@@ -46,55 +49,68 @@ struct FitDev {
   int32_t *active, *assign_pending;
   // state
   int32_t status, phase, iters, evals, ls_evals, hist_len, hist_head, reset_tried;
-  double f, t, f0, dphi0, gamma, acc;
+  double f, t, f0, dphi0, gamma, acc, gg, gmax;
   double prev_t, prev_f, prev_d, lo_t, lo_f, lo_d, hi_t, hi_f, hi_d;
   uint64_t clk_start, clk_target;
+  uint64_t *trace;  // optional stage stamps of the decision kernel (PD_FIT_TRACE builds)
 };
+
+#ifdef PD_FIT_TRACE
+#define FIT_STAMP(F, k)                                                          \
+  do {                                                                           \
+    if ((F).trace && threadIdx.x == 0) (F).trace[((F).evals & 255) * 16 + (k)] = clock64(); \
+  } while (0)
+#else
+#define FIT_STAMP(F, k) do { } while (0)
+#endif
 
 struct FitState {
   hipStream_t stream = nullptr;
 };
 
 // ------------------------------------------------------------------ block helpers
+//
+// Vector work is spread over the block (thread t owns elements t, t + blockDim,
+// ...).  Sums use DPP wave sums and then the wave partials in wave order, so
+// every reduction has a fixed order.  Up to VG dot products are accumulated in
+// one pass over memory.
 
-__device__ double blk_sum(double v, double *red) {
-  const int tid = threadIdx.x;
+#define VG 16
+#define MAX_WAVES (FIT_THREADS / PD_WAVE)
+
+template <int G>
+__device__ void blk_sums(double (&v)[G], double *red) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
+  for (int q = 0; q < G; ++q) v[q] = pd_wave_sum(v[q]);
+  const int nw = blockDim.x >> 6;
+  if (nw == 1) return;
   __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = v;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < G; ++q) red[(threadIdx.x >> 6) * G + q] = v[q];
   __syncthreads();
-  double t = 0.0;
-  if (tid == 0) {
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    red[32] = t;
+  // value q is summed over the waves (in wave order) by thread q, then shared
+  if ((int)threadIdx.x < G) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w * G + threadIdx.x];
+    red[MAX_WAVES * 48 + threadIdx.x] = t;
   }
   __syncthreads();
-  return red[32];
+#pragma unroll
+  for (int q = 0; q < G; ++q) v[q] = red[MAX_WAVES * 48 + q];
 }
 
-__device__ double blk_dot(const double *a, const double *b, int n, double *red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s = __builtin_fma(a[i], b[i], s);
-  return blk_sum(s, red);
-}
-
-__device__ double blk_maxabs(const double *a, int n, double *red) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, fabs(a[i]));
-  const int tid = threadIdx.x;
+__device__ double blk_max(double v, double *red) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, PD_WAVE));
+  const int nw = blockDim.x >> 6;
+  if (nw == 1) return v;
   __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = v;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
-    red[32] = t;
-  }
-  __syncthreads();
-  return red[32];
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+  return t;
 }
 
 // v <- projection of v onto the gauge-fixed subspace (in place).
@@ -102,11 +118,20 @@ __device__ void blk_gauge(FitDev &F, double *v, double *red) {
   if (F.gauge == 0) {
     for (int k = threadIdx.x; k < F.K; k += blockDim.x) v[(size_t)(F.N - 1) * F.K + k] = 0.0;
   } else if (F.gauge == 1) {
-    for (int k = 0; k < F.K; ++k) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < F.N; i += blockDim.x) s += v[(size_t)i * F.K + k];
-      const double mean = blk_sum(s, red) / (double)F.N;
-      for (int i = threadIdx.x; i < F.N; i += blockDim.x) v[(size_t)i * F.K + k] -= mean;
+    for (int k0 = 0; k0 < F.K; k0 += VG) {
+      double sm[VG];
+#pragma unroll
+      for (int q = 0; q < VG; ++q) sm[q] = 0.0;
+      const int cnt = min(VG, F.K - k0);
+      for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < VG; ++q)
+          if (q < cnt) sm[q] += v[(size_t)i * F.K + k0 + q];
+      blk_sums<VG>(sm, red);
+      for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < VG; ++q)
+          if (q < cnt) v[(size_t)i * F.K + k0 + q] -= sm[q] / (double)F.N;
     }
   }
   __syncthreads();
@@ -130,30 +155,57 @@ __device__ inline void fit_stop(FitDev &F, int status) {
   *F.active = 0;
 }
 
-// Start a line search from (x, f, g) along d (block-wide; all threads call).
+// ||g||^2, ||g||_inf and g.d of the current iterate (one pass).
+__device__ void pass_gstats(FitDev &F, double *red) {
+  double v[2] = {0.0, 0.0};
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+    const double gi = F.g[i];
+    v[0] = __builtin_fma(gi, gi, v[0]);
+    v[1] = __builtin_fma(gi, F.d[i], v[1]);
+    mx = fmax(mx, fabs(gi));
+  }
+  blk_sums<2>(v, red);
+  mx = blk_max(mx, red);
+  if (threadIdx.x == 0) {
+    F.gg = v[0];
+    F.dphi0 = v[1];
+    F.gmax = mx;
+  }
+  __syncthreads();
+}
+
+// d = -g and its slope g.d (steepest descent restart).
+__device__ void set_steepest(FitDev &F, double *red) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+    const double gi = F.g[i];
+    F.d[i] = -gi;
+    v[0] = __builtin_fma(gi, -gi, v[0]);
+  }
+  blk_sums<1>(v, red);
+  if (threadIdx.x == 0) F.dphi0 = v[0];
+  __syncthreads();
+}
+
+// Start a line search from (x, f, g) along d; F.gg, F.gmax and F.dphi0 = g.d
+// must be current.
 __device__ void start_ls(FitDev &F, double *red) {
-  const int n = F.NK;
-  const double gn2 = blk_dot(F.g, F.g, n, red);
-  const double gmax = blk_maxabs(F.g, n, red);
-  if (threadIdx.x == 0 && (gn2 == 0.0 || gmax <= F.gtol)) fit_stop(F, ST_GTOL);
+  if (threadIdx.x == 0 && (F.gg == 0.0 || F.gmax <= F.gtol)) fit_stop(F, ST_GTOL);
   __syncthreads();
   if (F.status != ST_RUNNING) return;
-  const double gnorm = sqrt(gn2);
+  const double gnorm = sqrt(F.gg);
   double t1 = F.hist_len == 0 ? 1.0 / gnorm : 1.0;
-  double dphi0 = blk_dot(F.g, F.d, n, red);
-  if (!(dphi0 < 0.0)) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) F.d[i] = -F.g[i];
-    __syncthreads();
+  if (!(F.dphi0 < 0.0)) {
+    set_steepest(F, red);
     t1 = 1.0 / gnorm;
-    dphi0 = blk_dot(F.g, F.d, n, red);
     if (threadIdx.x == 0) F.hist_len = 0;
   }
   if (threadIdx.x == 0) {
     F.f0 = F.f;
-    F.dphi0 = dphi0;
     F.prev_t = 0.0;
     F.prev_f = F.f;
-    F.prev_d = dphi0;
+    F.prev_d = F.dphi0;
     F.t = t1;
     F.ls_evals = 0;
     F.phase = PH_BRACKET;
@@ -161,28 +213,49 @@ __device__ void start_ls(FitDev &F, double *red) {
   __syncthreads();
 }
 
-// Accept the trial point (xt, graw = gradient of f, ft); update the memory,
-// take the new quasi-Newton direction and start the next search.
-__device__ void accept_trial(FitDev &F, double ft, double *red) {
+// Accept the trial point (xt, graw = gradient of f, ft); update the memory and
+// its Gram matrices, form the quasi-Newton direction d = -H g (the two-loop
+// recursion written through S^T g, Y^T g, S^T Y and Y^T Y) and start the next
+// search.
+__device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, double **jb,
+                             double *res, double *coef, double *gSY, double *gYY) {
   const int n = F.NK;
   const int m = F.m;
-  // The ring has m + 1 slots; the candidate pair goes to the free slot after the
-  // newest pair, so a rejected candidate never overwrites a stored one.
-  const int M1 = m + 1;
+  const int M1 = m + 1;  // ring slots: a candidate never overwrites a stored pair
   const int put = (F.hist_head + F.hist_len) % M1;
   double *s = F.S + (size_t)put * n;
   double *y = F.Y + (size_t)put * n;
   const double t = F.t;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    s[i] = t * F.d[i];
-    y[i] = F.graw[i] - F.g[i];
+  FIT_STAMP(F, 5);
+  double v3[3] = {0.0, 0.0, 0.0};
+  {
+    double *__restrict__ ps = s;
+    double *__restrict__ py = y;
+    double *__restrict__ px = F.x;
+    double *__restrict__ pg = F.g;
+    const double *__restrict__ pd = F.d;
+    const double *__restrict__ pgr = F.graw;
+    const double *__restrict__ pxt = F.xt;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double di = pd[i], gri = pgr[i], gi = pg[i], xti = pxt[i];
+      const double si = t * di;
+      const double yi = gri - gi;
+      ps[i] = si;
+      py[i] = yi;
+      v3[0] = __builtin_fma(si, yi, v3[0]);
+      v3[1] = __builtin_fma(si, si, v3[1]);
+      v3[2] = __builtin_fma(yi, yi, v3[2]);
+      px[i] = xti;
+      pg[i] = gri;
+    }
   }
+  blk_sums<3>(v3, red);
+  FIT_STAMP(F, 6);
+  const double sy = v3[0], ss = v3[1], yy = v3[2];
+  const bool stored = sy > CURV_EPS * sqrt(ss) * sqrt(yy);
   __syncthreads();
-  const double sy = blk_dot(s, y, n, red);
-  const double ss = blk_dot(s, s, n, red);
-  const double yy = blk_dot(y, y, n, red);
   if (threadIdx.x == 0) {
-    if (sy > CURV_EPS * sqrt(ss) * sqrt(yy)) {
+    if (stored) {
       F.rho[put] = 1.0 / sy;
       if (F.hist_len < m) F.hist_len++;
       else F.hist_head = (F.hist_head + 1) % M1;
@@ -191,10 +264,6 @@ __device__ void accept_trial(FitDev &F, double ft, double *red) {
     F.reset_tried = 0;
     F.f = ft;
     F.iters++;
-  }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    F.x[i] = F.xt[i];
-    F.g[i] = F.graw[i];
   }
   __syncthreads();
   if (F.iters >= F.max_iter) {
@@ -206,33 +275,146 @@ __device__ void accept_trial(FitDev &F, double ft, double *red) {
     return;
   }
   if (threadIdx.x == 0 && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
-  // two-loop recursion: d = -H g
-  double *q = F.d;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = F.g[i];
-  __syncthreads();
-  const int L = F.hist_len;
-  for (int k = L - 1; k >= 0; --k) {
-    const int j = (F.hist_head + k) % M1;
-    const double a = F.rho[j] * blk_dot(F.S + (size_t)j * n, q, n, red);
-    if (threadIdx.x == 0) F.alpha[j] = a;
-    const double *yj = F.Y + (size_t)j * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = q[i] - a * yj[i];
-    __syncthreads();
+  const int L = F.hist_len, head = F.hist_head;
+  // slot of the k-th live pair (oldest first), kept in LDS
+  int *slot = (int *)ja;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) slot[k] = (head + k) % M1;
+  double *Sg = coef + 4 * M1 + 1, *Yg = Sg + M1, *rho = Yg + M1;
+  for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
+    gSY[e] = F.SY[e];
+    gYY[e] = F.YY[e];
   }
-  const double scale = L > 0 ? F.gamma : 1.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = scale * q[i];
+  for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
   __syncthreads();
-  for (int k = 0; k < L; ++k) {
-    const int j = (F.hist_head + k) % M1;
-    const double b = F.rho[j] * blk_dot(F.Y + (size_t)j * n, q, n, red);
-    const double c = F.alpha[j] - b;
-    const double *sj = F.S + (size_t)j * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = q[i] + c * sj[i];
-    __syncthreads();
+  FIT_STAMP(F, 7);
+  // one pass per 8 live slots: S^T g, Y^T g and, for a stored pair, its Gram
+  // row and column (s_new . y_j, s_j . y_new, y_new . y_j)
+  {
+    const double *__restrict__ pS = F.S;
+    const double *__restrict__ pY = F.Y;
+    const double *__restrict__ pg = F.g;
+    const double *__restrict__ pns = s;
+    const double *__restrict__ pny = y;
+    for (int k0 = 0; k0 < L; k0 += 8) {
+      double acc[5 * 8];
+#pragma unroll
+      for (int q = 0; q < 40; ++q) acc[q] = 0.0;
+      int js[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) js[u] = slot[min(k0 + u, L - 1)];
+      for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const double gi = pg[e], si = pns[e], yi = pny[e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double Sj = pS[(size_t)js[u] * n + e];
+          const double Yj = pY[(size_t)js[u] * n + e];
+          acc[u] = __builtin_fma(Sj, gi, acc[u]);
+          acc[8 + u] = __builtin_fma(Yj, gi, acc[8 + u]);
+          acc[16 + u] = __builtin_fma(si, Yj, acc[16 + u]);
+          acc[24 + u] = __builtin_fma(Sj, yi, acc[24 + u]);
+          acc[32 + u] = __builtin_fma(yi, Yj, acc[32 + u]);
+        }
+      }
+      blk_sums<40>(acc, red);
+      if (threadIdx.x == 0) {
+        for (int u = 0; u < 8 && k0 + u < L; ++u) {
+          const int jj = js[u];
+          Sg[jj] = acc[u];
+          Yg[jj] = acc[8 + u];
+          if (stored) {
+            gSY[put * M1 + jj] = acc[16 + u];
+            gSY[jj * M1 + put] = acc[24 + u];
+            gYY[put * M1 + jj] = acc[32 + u];
+            gYY[jj * M1 + put] = acc[32 + u];
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = -q[i];
+  FIT_STAMP(F, 8);
+  // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0:
+  // lane k holds alpha and beta of the k-th pair; each step is one DPP sum.
+  if (threadIdx.x < PD_WAVE) {
+    const int lane = threadIdx.x;
+    const int jl = lane < L ? slot[lane] : 0;
+    double a = 0.0, b = 0.0;
+    for (int k = L - 1; k >= 0; --k) {
+      const int jk = slot[k];
+      const double c = (lane > k && lane < L) ? a * gSY[jk * M1 + jl] : 0.0;
+      const double sum = pd_wave_sum(c);
+      if (lane == k) a = rho[jk] * (Sg[jk] - sum);
+    }
+    const double gam = L > 0 ? F.gamma : 1.0;
+    // y_k . q_final for every k: sum over all pairs of alpha_k2 YY[k][k2]
+    double yq = lane < L ? Yg[jl] : 0.0;
+    for (int k2 = 0; k2 < L; ++k2) {
+      const double ak2 = __shfl(a, k2, PD_WAVE);
+      if (lane < L) yq -= ak2 * gYY[jl * M1 + slot[k2]];
+    }
+    for (int k = 0; k < L; ++k) {
+      const int jk = slot[k];
+      const double c = (lane < k) ? (a - b) * gSY[jl * M1 + jk] : 0.0;
+      const double sum = pd_wave_sum(c);
+      const double yqk = __shfl(yq, k, PD_WAVE);
+      if (lane == k) b = rho[jk] * (gam * yqk + sum);
+    }
+    if (lane < L) {
+      coef[lane] = gam * a;            // on y_k
+      coef[M1 + lane] = -(a - b);      // on s_k
+    }
+    if (lane == 0) coef[4 * M1] = -gam;  // on g
+  }
   __syncthreads();
+  FIT_STAMP(F, 9);
+  if (stored)
+    for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
+      F.SY[e] = gSY[e];
+      F.YY[e] = gYY[e];
+    }
+  // d, and the statistics of the new iterate for the search start
+  const double cg = coef[4 * M1];
+  double v[2] = {0.0, 0.0};
+  double mx = 0.0;
+  const double *__restrict__ pS = F.S;
+  const double *__restrict__ pY = F.Y;
+  const double *__restrict__ pg = F.g;
+  double *__restrict__ pdir = F.d;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double gi = pg[i];
+    double di = cg * gi;
+    // slots in blocks of 8: the 16 loads of a block are issued before use
+    for (int k0 = 0; k0 < L; k0 += 8) {
+      double yv[8], sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = slot[min(k0 + u, L - 1)];
+        yv[u] = pY[(size_t)j * n + i];
+        sv[u] = pS[(size_t)j * n + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < L) {
+          di = __builtin_fma(coef[k0 + u], yv[u], di);
+          di = __builtin_fma(coef[M1 + k0 + u], sv[u], di);
+        }
+    }
+    pdir[i] = di;
+    v[0] = __builtin_fma(gi, gi, v[0]);
+    v[1] = __builtin_fma(gi, di, v[1]);
+    mx = fmax(mx, fabs(gi));
+  }
+  blk_sums<2>(v, red);
+  mx = blk_max(mx, red);
+  if (threadIdx.x == 0) {
+    F.gg = v[0];
+    F.dphi0 = v[1];
+    F.gmax = mx;
+  }
+  __syncthreads();
+  FIT_STAMP(F, 10);
   start_ls(F, red);
+  FIT_STAMP(F, 11);
 }
 
 // A search ended without a strong-Wolfe point.  Fall back to (t_res > 0), or
@@ -247,8 +429,7 @@ __device__ void ls_fail(FitDev &F, double t_res, double *red) {
     return;
   }
   if (F.hist_len > 0 && !F.reset_tried) {
-    for (int i = threadIdx.x; i < F.NK; i += blockDim.x) F.d[i] = -F.g[i];
-    __syncthreads();
+    set_steepest(F, red);
     if (threadIdx.x == 0) {
       F.hist_len = 0;
       F.reset_tried = 1;
@@ -261,17 +442,46 @@ __device__ void ls_fail(FitDev &F, double t_res, double *red) {
   __syncthreads();
 }
 
+// Shared scratch of the decision kernel.
+#define FIT_MAX_HISTORY 32
+#define HS (FIT_MAX_HISTORY + 1)
+#define DEC_SHARED                                  \
+  __shared__ double red[MAX_WAVES * 48 + 48];       \
+  __shared__ double *ja[5 * HS], *jb[5 * HS];       \
+  __shared__ double res[5 * HS];                    \
+  __shared__ double coef[8 * HS];                   \
+  __shared__ double gSY[HS * HS], gYY[HS * HS];     \
+  __shared__ FitDev sF;                             \
+  __shared__ int action;
+
+__device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+                            double *coef, double *gSY, double *gYY, int *action_p);
+
 // grid: one block per map.  Consumes one evaluation at xt.
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
-  FitDev &F = Fs[blockIdx.x];
-  if (*F.active == 0) return;
-  __shared__ double red[40];
-  __shared__ int action;  // 0 continue with new t, 1 accept, 2 fail(lo), 3 fail(prev)
+  if (*Fs[blockIdx.x].active == 0) return;
+  DEC_SHARED
+  // the state record lives in LDS while the kernel runs (thread 0's line-search
+  // logic touches it many times), and is written back at the end
+  constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
+  __syncthreads();
+  FIT_STAMP(sF, 0);
+  decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
+  __syncthreads();
+  FIT_STAMP(sF, 12);
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
+}
+
+__device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+                            double *coef, double *gSY, double *gYY, int *action_p) {
+  int &action = *action_p;
   const int n = F.NK;
   // gradient of f = -Phi at xt, gauge-projected, in graw
   for (int i = threadIdx.x; i < n; i += blockDim.x) F.graw[i] = -F.graw[i];
   __syncthreads();
   blk_gauge(F, F.graw, red);
+  FIT_STAMP(F, 1);
   const double ft = -*F.phi_t;
   if (threadIdx.x == 0) F.evals++;
   if (F.phase == PH_INIT) {
@@ -290,14 +500,21 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
       }
     }
     __syncthreads();
-    if (F.status == ST_RUNNING && F.phase == PH_INIT) start_ls(F, red);
+    if (F.status == ST_RUNNING && F.phase == PH_INIT) {
+      pass_gstats(F, red);
+      start_ls(F, red);
+    }
     return;
   }
   if (F.phase == PH_ACCEPT_NEXT) {
-    accept_trial(F, ft, red);
+    accept_trial(F, ft, red, ja, jb, res, coef, gSY, gYY);
     return;
   }
-  const double dt = blk_dot(F.graw, F.d, n, red);
+  double dv[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
+  blk_sums<1>(dv, red);
+  FIT_STAMP(F, 2);
+  const double dt = dv[0];
   if (threadIdx.x == 0) {
     const double t = F.t;
     // a non-finite objective counts as no sufficient decrease
@@ -339,8 +556,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
     action = act;
   }
   __syncthreads();
+  FIT_STAMP(F, 3);
   const int act = action;
-  if (act == 1) accept_trial(F, ft, red);
+  if (act == 1) accept_trial(F, ft, red, ja, jb, res, coef, gSY, gYY);
   else if (act == 2) ls_fail(F, F.lo_t, red);
   else if (act == 3) ls_fail(F, F.prev_t, red);
 }
@@ -364,20 +582,36 @@ __device__ inline void consume_acc(FitDev &F) {
 // forms the trial point xt = x + t d and the evaluation input
 // thc = -(log2 e / eps) (xt - mean_i xt_i).
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
-  FitDev &F = Fs[blockIdx.x];
-  __shared__ double red[40];
+  __shared__ double red[MAX_WAVES * 48 + 48];
+  __shared__ FitDev sF;
+  FitDev &F = sF;
+  constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
+  __syncthreads();
   if (threadIdx.x == 0) consume_acc(F);
   __syncthreads();
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
   if (*F.active == 0) return;
   const double t = F.t;
   for (int i = threadIdx.x; i < F.NK; i += blockDim.x) F.xt[i] = F.x[i] + t * F.d[i];
   __syncthreads();
-  for (int k = 0; k < F.K; ++k) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < F.N; i += blockDim.x) s += F.xt[(size_t)i * F.K + k];
-    const double mean = blk_sum(s, red) / (double)F.N;
+  for (int k0 = 0; k0 < F.K; k0 += VG) {
+    double sm[VG];
+#pragma unroll
+    for (int q = 0; q < VG; ++q) sm[q] = 0.0;
+    const int cnt = min(VG, F.K - k0);
     for (int i = threadIdx.x; i < F.N; i += blockDim.x)
-      F.thc[(size_t)i * F.K + k] = F.cscale * (F.xt[(size_t)i * F.K + k] - mean);
+#pragma unroll
+      for (int q = 0; q < VG; ++q)
+        if (q < cnt) sm[q] += F.xt[(size_t)i * F.K + k0 + q];
+    blk_sums<VG>(sm, red);
+    for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+#pragma unroll
+      for (int q = 0; q < VG; ++q)
+        if (q < cnt) {
+          const size_t e = (size_t)i * F.K + k0 + q;
+          F.thc[e] = F.cscale * (F.xt[e] - sm[q] / (double)F.N);
+        }
   }
 }
 
@@ -390,7 +624,7 @@ __global__ void k_fit_stamp(FitDev *Fs, int n_maps) {
 // grid: one block per map: project the start, reset the state.
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_start) {
   FitDev &F = Fs[blockIdx.x];
-  __shared__ double red[40];
+  __shared__ double red[MAX_WAVES * 48 + 48];
   for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
     if (zero_start) F.x[i] = 0.0;
     F.d[i] = 0.0;
@@ -421,7 +655,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
 
 void pd_fit_release(pd_ctx *ctx) {
   if (ctx->fit) {
-    if (ctx->fit->stream) hipStreamDestroy(ctx->fit->stream);
+    if (ctx->fit->stream) (void)hipStreamDestroy(ctx->fit->stream);
     delete ctx->fit;
     ctx->fit = nullptr;
   }
@@ -457,8 +691,8 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown init");
   if (opts->init == PD_INIT_MLP && opts->mlp == nullptr)
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "PD_INIT_MLP needs opts->mlp");
-  if (opts->history < 1 || opts->history > 64)
-    return pd_fail(ctx, PD_ERR_INVALID_ARG, "history must be in [1, 64]");
+  if (opts->history < 1 || opts->history > FIT_MAX_HISTORY)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "history must be in [1, 32]");
   if (opts->max_iter < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "max_iter must be >= 0");
   if (opts->check_every < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "check_every must be >= 1");
   if (!(opts->gtol >= 0.0)) return pd_fail(ctx, PD_ERR_INVALID_ARG, "gtol must be >= 0");
@@ -483,7 +717,8 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   std::vector<size_t> o_vec(n);
   for (int p = 0; p < n; ++p) {
     const size_t NK = (size_t)P.maps[p].N * P.maps[p].K;
-    o_vec[p] = L.take(sizeof(double) * (5 * NK + 2 * (size_t)(m + 1) * NK + 2 * (size_t)(m + 1)));
+    o_vec[p] = L.take(sizeof(double) * (5 * NK + 2 * (size_t)(m + 1) * NK + (size_t)(m + 1) +
+                                        2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)));
   }
   const size_t o_F = L.take(sizeof(FitDev) * n);
   const size_t o_flags = L.take(sizeof(int32_t) * 2 * n);
@@ -522,7 +757,10 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.S = v + 5 * NK;
     f.Y = f.S + (size_t)(m + 1) * NK;
     f.rho = f.Y + (size_t)(m + 1) * NK;
-    f.alpha = f.rho + (m + 1);
+    f.SY = f.rho + (m + 1);
+    f.YY = f.SY + (size_t)(m + 1) * (m + 1);
+    f.Sg = f.YY + (size_t)(m + 1) * (m + 1);
+    f.Yg = f.Sg + (m + 1);
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
     f.n_correct = nc + p;
@@ -544,6 +782,12 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   }
   MapDev *d_amaps = (MapDev *)(base + o_amaps);
   FitDev *dF = (FitDev *)(base + o_F);
+#ifdef PD_FIT_TRACE
+  uint64_t *trace_buf = nullptr;
+  FIT_HIP(ctx, hipMalloc((void **)&trace_buf, sizeof(uint64_t) * 256 * 16 * n));
+  FIT_HIP(ctx, hipMemsetAsync(trace_buf, 0, sizeof(uint64_t) * 256 * 16 * n, s));
+  for (int p = 0; p < n; ++p) F[p].trace = trace_buf + (size_t)p * 256 * 16;
+#endif
   FIT_HIP(ctx, pd_plan_upload(ctx, P, s));
   FIT_HIP(ctx, hipMemcpyAsync(d_amaps, amaps.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
   FIT_HIP(ctx, hipMemcpyAsync(dF, F.data(), sizeof(FitDev) * n, hipMemcpyHostToDevice, s));
@@ -561,14 +805,19 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     st = pd_warm_start(ctx, probs, n, xs.data(), opts->mlp, eval_prec, s);
     if (st != PD_OK) return st;
   }
-  k_fit_init<<<n, FIT_THREADS, 0, s>>>(dF, zero_start ? 1 : 0);
+  k_fit_init<<<n, 256, 0, s>>>(dF, zero_start ? 1 : 0);
   FIT_HIP(ctx, hipGetLastError());
 
   // ---- one step, captured as a graph
+  // threads per map for the L-BFGS vector work: one element per thread up to
+  // 1024 threads (each pass is then about one memory round trip)
+  int max_nk = 1;
+  for (int p = 0; p < n; ++p) max_nk = std::max(max_nk, F[p].NK);
+  const int vt = std::min(FIT_THREADS, std::max(64, (max_nk / 4 + 63) / 64 * 64));
   auto step = [&](hipStream_t ss) {
-    k_fit_trial<<<n, FIT_THREADS, 0, ss>>>(dF);
+    k_fit_trial<<<n, vt, 0, ss>>>(dF);
     pd_fit_eval(ctx, P, eval_prec, ss);
-    k_fit_decide<<<n, FIT_THREADS, 0, ss>>>(dF);
+    k_fit_decide<<<n, vt, 0, ss>>>(dF);
     pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], ss);
   };
   hipGraph_t graph = nullptr;
@@ -579,7 +828,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (ce != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
   ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   if (ce != hipSuccess) {
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     return pd_fail(ctx, PD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
   }
   // ---- replay until every map has stopped
@@ -601,9 +850,9 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     if (!any) break;
     if (poll < 16) poll *= 2;
   }
-  hipGraphExecDestroy(exec);
-  hipGraphDestroy(graph);
-  hipHostFree(h_flags);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipHostFree(h_flags);
   if (le != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("fit loop: ") + hipGetErrorString(le));
   // ---- final accuracy of every map and the results
   std::vector<MapDev> fin = amaps;
@@ -618,8 +867,19 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
                                 hipMemcpyDeviceToDevice, s));
   FIT_HIP(ctx, hipStreamSynchronize(s));
   const auto t_end = clk::now();
+#ifdef PD_FIT_TRACE
+  if (const char *path = getenv("PD_FIT_TRACE_OUT")) {
+    std::vector<uint64_t> h((size_t)256 * 16 * n);
+    (void)hipMemcpy(h.data(), trace_buf, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost);
+    if (FILE *fp = fopen(path, "wb")) {
+      fwrite(h.data(), sizeof(uint64_t), h.size(), fp);
+      fclose(fp);
+    }
+  }
+  (void)hipFree(trace_buf);
+#endif
   int rate_khz = 0;
-  hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
+  (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device);
   const double host_setup = std::chrono::duration<double>(t_stamp - t_call).count();
   for (int p = 0; p < n; ++p) {
     pd_fit_report &r = reports[p];

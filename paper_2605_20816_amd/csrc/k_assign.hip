@@ -8,12 +8,21 @@
 // labels are bit-reproducible.  A NaN score marks the pixel -1.
 #include "pd_internal.h"
 
+// A block = 4 waves = 4 row segments of one map (each map's item count is a
+// multiple of 4).  theta is staged through LDS in chunks of 64 grains and read
+// by all lanes at one address (broadcast); grains are scanned in ascending order.
+#define AS_CHUNK 64
+
 template <int D>
-__device__ inline void assign_item(const MapDev &M, int local, int lane) {
+__device__ inline void assign_block(const MapDev &M, int base, double *sth) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  const int r = local / M.segs;
-  const int c = (local - r * M.segs) * PD_WAVE + lane;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int local = base + wave;
+  const bool wave_valid = local < M.H * M.segs;
+  const int r = wave_valid ? local / M.segs : 0;
+  const int c = wave_valid ? (local - r * M.segs) * PD_WAVE + lane : M.W;
   const bool valid = c < M.W;
   const int cc = valid ? c : M.W - 1;
   const auto px = pd_glb(M.tx64 + (size_t)cc * DP);
@@ -23,29 +32,33 @@ __device__ inline void assign_item(const MapDev &M, int local, int lane) {
   for (int deg = 0; deg <= D; ++deg)
 #pragma unroll
     for (int b = 0; b <= deg; ++b) psi[pd_alpha_index(deg - b, b)] = px[deg - b] * py[b];
-  const auto th = pd_uni(M.theta);
-  double fbest = th[0];
-#pragma unroll
-  for (int k = 1; k < K; ++k) fbest = __builtin_fma(th[k], psi[k], fbest);
-  bool bad = __builtin_isnan(fbest);
+  const auto th = pd_glb(M.theta);
+  double fbest = INFINITY;
+  bool bad = false;
   int best = 0;
-  for (int i = 1; i < M.N; ++i) {
-    const auto ti = th + (size_t)i * K;
-    double f = ti[0];
+  for (int i0 = 0; i0 < M.N; i0 += AS_CHUNK) {
+    const int cnt = min(AS_CHUNK, M.N - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * K; e += PD_BLOCK) sth[e] = th[(size_t)i0 * K + e];
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const double *tj = sth + j * K;
+      double f = tj[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) f = __builtin_fma(ti[k], psi[k], f);
-    bad |= __builtin_isnan(f);
-    if (f < fbest) {
-      fbest = f;
-      best = i;
+      for (int k = 1; k < K; ++k) f = __builtin_fma(tj[k], psi[k], f);
+      bad |= __builtin_isnan(f);
+      if (f < fbest) {
+        fbest = f;
+        best = i0 + j;
+      }
     }
   }
   long long correct = 0;
   if (valid) {
     const int lab = bad ? -1 : best;
-    const size_t j = (size_t)r * M.W + c;
-    if (M.labels_out) pd_glb(M.labels_out)[j] = lab;
-    correct = (lab == pd_glb(M.labels)[j]) ? 1 : 0;
+    const size_t jx = (size_t)r * M.W + c;
+    if (M.labels_out) pd_glb(M.labels_out)[jx] = lab;
+    correct = (lab == pd_glb(M.labels)[jx]) ? 1 : 0;
   }
   const long long tot = pd_wave_sum_i64(correct);
   if (lane == 0) pd_glb(M.part_c)[local] = tot;
@@ -55,14 +68,14 @@ template <int DMAX>
 __global__ __launch_bounds__(PD_BLOCK) void k_assign(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
                                                      int total) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
-  const int lane = threadIdx.x % PD_WAVE;
-  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
-  if (item >= total) return;
-  const int m = pd_find_map(off, n_maps, item);
+  constexpr int KM = (DMAX + 1) * (DMAX + 2) / 2;
+  __shared__ double sth[AS_CHUNK * KM];
+  const int item0 = blockIdx.x * PD_WAVES_PER_BLOCK;
+  if (item0 >= total) return;
+  const int m = pd_find_map(off, n_maps, item0);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (assign_item<D>(M, item - off[m], lane)));
+  PD_DISPATCH_UPTO(DMAX, M.d, (assign_block<D>(M, item0 - off[m], sth)));
 }
 
 // One block per map: fixed-order sum of the per-wave correct counts.

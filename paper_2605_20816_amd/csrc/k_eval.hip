@@ -159,6 +159,10 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
 template <typename T, int D>
 __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
+  if (local >= M.H * M.segs) {  // padding item (item counts are multiples of 4)
+    if (lane == 0) pd_glb(M.part_l)[local] = 0.0;
+    return;
+  }
   const int r = local / M.segs;
   const int c = (local - r * M.segs) * PD_WAVE + lane;
   const bool valid = c < M.W;

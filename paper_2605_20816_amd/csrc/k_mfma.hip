@@ -17,9 +17,9 @@ pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *, int, double *const *, c
 
 void pd_bf16_profile_stages(pd_ctx *, const EvalPlan &P, int reps, hipStream_t s, hipEvent_t *ev) {
   for (int r = 0; r < reps; ++r) pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-  hipEventRecord(ev[1], s);
+  (void)hipEventRecord(ev[1], s);
   for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-  hipEventRecord(ev[2], s);
+  (void)hipEventRecord(ev[2], s);
   for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
-  hipEventRecord(ev[3], s);
+  (void)hipEventRecord(ev[3], s);
 }

@@ -122,10 +122,27 @@ __host__ __device__ constexpr int pd_alpha_index(int a, int b) {
   return (a + b) * (a + b + 1) / 2 + b;
 }
 
+// Wave-wide sums through DPP lane moves (no LDS round trips).  Inclusive scans
+// over each row of 16 lanes (row_shr 1, 2, 4, 8), then row 1 and 3 add the last
+// lane of the row before them (row_bcast:15) and rows 2, 3 add lane 31
+// (row_bcast:31): lane 63 holds the total, in a fixed order.
+template <int CTRL, int ROW_MASK>
+__device__ inline double pd_dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ inline double pd_wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
-  return v;
+  v += pd_dpp_f64<0x111, 0xf>(v);
+  v += pd_dpp_f64<0x112, 0xf>(v);
+  v += pd_dpp_f64<0x114, 0xf>(v);
+  v += pd_dpp_f64<0x118, 0xf>(v);
+  v += pd_dpp_f64<0x142, 0xa>(v);
+  v += pd_dpp_f64<0x143, 0xc>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ inline long long pd_wave_sum_i64(long long v) {
