@@ -93,10 +93,14 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
   P.offB.assign(n + 1, 0);
   P.offP.assign(n + 1, 0);
   P.offR.assign(n + 1, 0);
+  P.off16P.assign(n + 1, 0);
+  P.off16A.assign(n + 1, 0);
+  P.off16B.assign(n + 1, 0);
+  P.off16R.assign(n + 1, 0);
   P.max_hw = 0;
   P.max_k = 0;
   int max_d = 1;
-  const size_t tsz = prec == 0 ? 8 : 4;
+  const size_t tsz = prec == 0 ? 8 : 4;  // FP32 tables for the FP32 and BF16 paths
   for (int p = 0; p < n; ++p) {
     const pd_problem &q = probs[p];
     MapDev &M = P.maps[p];
@@ -120,19 +124,43 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.b_items = M.tiles_r * M.tiles_c * (M.Npad / PD_WAVE);
     M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
     const long long n_px = (long long)M.H * M.W;
+    const bool mf = prec == 2;
+    // BF16 matrix-core path: 32-pixel tiles; k16_lse blocks of 16 tiles;
+    // k16_grad waves = pixel chunks x 128-grain groups (about 4096 waves)
+    M.Kp = (M.K + 15) / 16 * 16;
+    M.n32 = (int)((n_px + 31) / 32 * 32);
+    M.tiles32 = M.n32 / 32;
+    M.a16_items = (M.tiles32 + 15) / 16;
+    M.ggroups = (M.Npad + 32 * PD_MF_GROUP_TILES - 1) / (32 * PD_MF_GROUP_TILES);
+    {
+      // about 4096 waves of k16_grad (4 grain groups per block)
+      long long ct = (long long)M.tiles32 * ((M.ggroups + 3) / 4 * 4) / 4096;
+      if (ct < 1) ct = 1;
+      M.chunk_tiles = (int)std::min<long long>(ct, M.tiles32);
+      M.chunks = (M.tiles32 + M.chunk_tiles - 1) / M.chunk_tiles;
+    }
+    M.b16_items = M.chunks * ((M.ggroups + 3) / 4);  // k16_grad blocks
     R.tx64 = L.take(sizeof(double) * M.W * M.DP);
     R.ty64 = L.take(sizeof(double) * M.H * M.DP);
     R.txT = L.take(tsz * M.W * M.DP);
+    R.tyT = L.take(tsz * M.H * M.DP);
     R.thc = L.take(sizeof(double) * M.N * M.K);
-    R.C = L.take(tsz * (size_t)M.H * M.Npad * M.DP);
-    R.lse = L.take(tsz * n_px);
-    R.part_l = L.take(sizeof(double) * M.a_items);
-    R.part_g = L.take(sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
+    R.C = L.take(mf ? 0 : tsz * (size_t)M.H * M.Npad * M.DP);
+    R.lse = L.take(mf ? 0 : tsz * n_px);
+    R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
+    R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
     R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
+    R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
+    R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
     P.offA[p + 1] = P.offA[p] + M.a_items;
     P.offB[p + 1] = P.offB[p] + M.b_items;
     P.offP[p + 1] = P.offP[p] + (int)(((long long)M.H * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
     P.offR[p + 1] = P.offR[p] + M.r_items;
+    P.off16P[p + 1] = P.off16P[p] + (int)(((long long)M.Npad * M.Kp + PD_BLOCK - 1) / PD_BLOCK);
+    P.off16A[p + 1] = P.off16A[p] + M.a16_items;
+    P.off16B[p + 1] = P.off16B[p] + M.b16_items;
+    P.off16R[p + 1] = P.off16R[p] + (M.N * M.K + 15) / 16;
     M.a_off = P.offA[p];
     M.b_off = P.offB[p];
     M.r_off = P.offR[p];
@@ -142,7 +170,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
   }
   P.dmax = pd_dmax_bucket(max_d);
   P.o_maps = L.take(sizeof(MapDev) * n);
-  P.o_off = L.take(sizeof(int32_t) * 4 * (n + 1));
+  P.o_off = L.take(sizeof(int32_t) * 8 * (n + 1));
 }
 
 void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
@@ -154,6 +182,10 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
     M.tx64 = (double *)(base + R.tx64);
     M.ty64 = (double *)(base + R.ty64);
     M.txT = base + R.txT;
+    M.tyT = base + R.tyT;
+    M.T3 = base + R.T3;
+    M.lse32 = (float *)(base + R.lse32);
+    M.part_g32 = (float *)(base + R.part_g32);
     M.thc = (double *)(base + R.thc);
     M.C = base + R.C;
     M.lse = base + R.lse;
@@ -173,13 +205,17 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
   P.d_offB = off + (P.n + 1);
   P.d_offP = off + 2 * (P.n + 1);
   P.d_offR = off + 3 * (P.n + 1);
+  P.d_off16P = off + 4 * (P.n + 1);
+  P.d_off16A = off + 5 * (P.n + 1);
+  P.d_off16B = off + 6 * (P.n + 1);
+  P.d_off16R = off + 7 * (P.n + 1);
 }
 
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
   // maps and the four offset arrays are contiguous in the arena (o_maps, o_off)
   const size_t maps_bytes = sizeof(MapDev) * P.n;
   const size_t gap = P.o_off - P.o_maps;
-  const size_t total = gap + sizeof(int32_t) * 4 * (P.n + 1);
+  const size_t total = gap + sizeof(int32_t) * 8 * (P.n + 1);
   hipError_t e;
   if (ctx->staged) {
     e = hipEventSynchronize(ctx->staged);
@@ -203,6 +239,10 @@ hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
     o[(P.n + 1) + k] = P.offB[k];
     o[2 * (P.n + 1) + k] = P.offP[k];
     o[3 * (P.n + 1) + k] = P.offR[k];
+    o[4 * (P.n + 1) + k] = P.off16P[k];
+    o[5 * (P.n + 1) + k] = P.off16A[k];
+    o[6 * (P.n + 1) + k] = P.off16B[k];
+    o[7 * (P.n + 1) + k] = P.off16R[k];
   }
   e = hipMemcpyAsync(P.d_maps, ctx->stage, total, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
@@ -410,7 +450,7 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   hipStream_t s = (hipStream_t)stream;
   EvalPlan P;
   Arena L;
-  pd_plan_layout(P, L, probs, n_probs, code == 2 ? 1 : code);
+  pd_plan_layout(P, L, probs, n_probs, code);
   const size_t o_phi = L.take(sizeof(double) * n_probs);
   std::vector<size_t> o_g(n_probs);
   for (int p = 0; p < n_probs; ++p)
@@ -423,12 +463,18 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   PD_HIP(ctx, pd_plan_upload(ctx, P, s));
   hipEvent_t ev[PD_NUM_STAGES + 1];
   for (auto &e : ev) PD_HIP(ctx, hipEventCreate(&e));
+  // one untimed evaluation first (loads the kernels' code on first use)
+  pd_plan_tables(P, s);
+  if (code == 2) pd_bf16_plan_eval(ctx, P, s, true);
+  else pd_plan_eval(P, true, s, true);
   PD_HIP(ctx, hipEventRecord(ev[0], s));
   for (int r = 0; r < reps; ++r) pd_plan_tables(P, s);
   PD_HIP(ctx, hipEventRecord(ev[1], s));
   for (int r = 0; r < reps; ++r) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   PD_HIP(ctx, hipEventRecord(ev[2], s));
   if (code == 2) {
+    for (int p = 0; p < n_probs; ++p)
+      if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
     pd_bf16_profile_stages(ctx, P, reps, s, ev + 2);
   } else {
     for (int r = 0; r < reps; ++r) pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
@@ -438,7 +484,10 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
     PD_HIP(ctx, hipEventRecord(ev[5], s));
   }
-  for (int r = 0; r < reps; ++r) pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, s);
+  for (int r = 0; r < reps; ++r) {
+    if (code == 2) pd_bf16_launch(P, 3, s);
+    else pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, s);
+  }
   PD_HIP(ctx, hipEventRecord(ev[6], s));
   PD_HIP(ctx, hipGetLastError());
   PD_HIP(ctx, hipEventSynchronize(ev[6]));

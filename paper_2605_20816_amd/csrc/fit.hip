@@ -699,6 +699,9 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   for (int p = 0; p < n; ++p) {
     if (!theta_inout[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta_inout entry is NULL");
   }
+  if (prec == 2)
+    for (int p = 0; p < n; ++p)
+      if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
   pd_status st = pd_validate(ctx, probs, n, stream);
   if (st != PD_OK) return st;
   FIT_HIP(ctx, hipSetDevice(ctx->device));
@@ -712,7 +715,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   const int eval_prec = prec == 2 ? 2 : prec;
   EvalPlan P;
   Arena L;
-  pd_plan_layout(P, L, probs, n, eval_prec == 2 ? 1 : eval_prec);
+  pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);
   for (int p = 0; p < n; ++p) {

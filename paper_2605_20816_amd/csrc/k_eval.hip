@@ -92,7 +92,10 @@ __global__ __launch_bounds__(PD_BLOCK) void k_tables(const MapDev *__restrict__ 
   }
   if (idx < M.H) {
     pd_legendre_canonical(idx, M.H, M.d, P);
-    for (int a = 0; a <= M.d; ++a) M.ty64[(size_t)idx * M.DP + a] = P[a];
+    for (int a = 0; a <= M.d; ++a) {
+      M.ty64[(size_t)idx * M.DP + a] = P[a];
+      ((T *)M.tyT)[(size_t)idx * M.DP + a] = (T)P[a];
+    }
   }
 }
 

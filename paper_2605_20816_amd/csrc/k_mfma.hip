@@ -1,25 +1,572 @@
-// k_mfma.hip -- BF16 matrix-core objective/gradient path.
+// k_mfma.hip -- BF16 matrix-core objective/gradient path (v_mfma_f32_32x32x16_bf16).
+//
+// Logits in base 2, s_i(x) = thc_i . psi(x) with thc = -(log2 e / eps)(theta -
+// mean), are a GEMM with inner dimension K (padded to 16 or 32).  At eps = 1e-3
+// the logits reach |s| ~ 1e3..1e4 while the softmax needs them to ~1e-3, i.e.
+// about 22 significant bits.  Both operands are therefore split into three
+// bf16 pieces (hi + mid + lo, each the rounding of the remainder) and the six
+// products of total order <= 2 (hh, hm, mh, hl, lh, mm) are accumulated in FP32;
+// the dropped terms are below 2^-26 relative.  The gradient contraction
+// sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies values of size <= 1 and
+// uses two pieces of each operand (hh, hl, lh).  Log-sum-exp in FP32; Phi and
+// grad Phi are summed in FP64 in a fixed order.
+//
+// Operand/accumulator lane layout of the 32x32x16 instruction (lane l, half
+// h = l / 32): A[i][k] at lane i + 32 (k / 8), element k % 8; B[k][j] at lane
+// j + 32 (k / 8), element k % 8; D[i][j] at lane j + 32 ((i / 4) % 2),
+// register 4 (i / 8) + i % 4.
+//
+// k16_lse:  block = 4 waves x 4 pixel tiles of 32 pixels; the three pieces of
+//           thc for 128 grains at a time are staged in LDS and shared; S = thc
+//           psi^T puts one pixel per lane column and 16 grains per lane, so the
+//           online max / sum of exp2 stays in-lane (halves merged at the end).
+// k16_grad: wave = (pixel chunk, 64 grains); thc pieces and the 2 x 32 x 32
+//           gradient accumulators stay in registers across the chunk; S^T = psi
+//           thc^T puts one grain per lane column, so p - delta feeds the gradient
+//           product directly as its A operand.
 #include "pd_host.h"
 
-pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *, int, const double *const *,
-                                 double *, double *const *, hipStream_t) {
-  return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16: not built yet");
+#include <math.h>
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+#define MF_TILES_PER_WAVE 4     // pixel tiles per wave in k16_lse
+#define MF_GRAIN_STAGE 128      // grains staged in LDS per step of k16_lse
+
+// Exponents (a, b) of feature k in the degree-graded order (degree <= 8).
+__constant__ signed char c_fa[45] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0,
+                                     5, 4, 3, 2, 1, 0, 6, 5, 4, 3, 2, 1, 0,
+                                     7, 6, 5, 4, 3, 2, 1, 0, 8, 7, 6, 5, 4, 3, 2, 1, 0};
+__constant__ signed char c_fb[45] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4,
+                                     0, 1, 2, 3, 4, 5, 0, 1, 2, 3, 4, 5, 6,
+                                     0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5, 6, 7, 8};
+
+__device__ inline float bf_to_f(__bf16 h) { return (float)h; }
+
+// Exponents of feature k in the graded order, at compile time.
+__host__ __device__ constexpr int feat_deg(int k) {
+  int d = 0;
+  while ((d + 1) * (d + 2) / 2 <= k) ++d;
+  return d;
+}
+__host__ __device__ constexpr int feat_b(int k) { return k - feat_deg(k) * (feat_deg(k) + 1) / 2; }
+__host__ __device__ constexpr int feat_a(int k) { return feat_deg(k) - feat_b(k); }
+
+// Row and column of flat pixel pbase + o from those of pbase (o < 32).
+__device__ inline void pix_rc(int r0, int c0, int o, int W, int &r, int &c) {
+  c = c0 + o;
+  r = r0;
+  while (c >= W) {
+    c -= W;
+    ++r;
+  }
+}
+
+// All 16 * NKB features of one pixel (zero beyond K or outside the map), then
+// the 8 of block kb for lane half h: v[e] = psi_{16 kb + 8 h + e}.
+template <int NKB>
+__device__ inline void pixel_feats(const MapDev &M, int r, int c, bool valid, int half,
+                                   float (&v)[NKB][8]) {
+  constexpr int AM = feat_deg(16 * NKB - 1);  // largest exponent needed
+  const float *tx = (const float *)M.txT, *ty = (const float *)M.tyT;
+  float px[AM + 1], py[AM + 1];
+#pragma unroll
+  for (int a = 0; a <= AM; ++a) {
+    px[a] = (valid && a <= M.d) ? tx[c * M.DP + a] : 0.f;
+    py[a] = (valid && a <= M.d) ? ty[r * M.DP + a] : 0.f;
+  }
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k0 = 16 * kb + e, k1 = 16 * kb + 8 + e;
+      const float f0 = px[feat_a(k0)] * py[feat_b(k0)];
+      const float f1 = px[feat_a(k1)] * py[feat_b(k1)];
+      const float f = half ? f1 : f0;
+      const int k = half ? k1 : k0;
+      v[kb][e] = k < M.K ? f : 0.f;
+    }
+}
+
+// Three-piece split of 8 FP32 values.
+__device__ inline void split3(const float (&v)[8], bf16x8 &h, bf16x8 &m, bf16x8 &l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 a = (__bf16)v[e];
+    const float r1 = v[e] - bf_to_f(a);
+    const __bf16 b = (__bf16)r1;
+    const float r2 = r1 - bf_to_f(b);
+    h[e] = a;
+    m[e] = b;
+    l[e] = (__bf16)r2;
+  }
+}
+
+__device__ inline void split2(const float (&v)[8], bf16x8 &h, bf16x8 &l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 a = (__bf16)v[e];
+    h[e] = a;
+    l[e] = (__bf16)(v[e] - bf_to_f(a));
+  }
+}
+
+// acc += (ah + am + al)(bh + bm + bl) up to second-order terms, small first.
+__device__ inline f32x16 mfma6(const bf16x8 &ah, const bf16x8 &am, const bf16x8 &al,
+                               const bf16x8 &bh, const bf16x8 &bm, const bf16x8 &bl, f32x16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// thc (FP64, N x K) -> three bf16 pieces [3][Npad][Kp], zero-padded.
+__global__ __launch_bounds__(PD_BLOCK) void k16_prep(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps) {
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  const long long e = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
+  const long long tot = (long long)M.Npad * M.Kp;
+  if (e >= tot) return;
+  const int i = (int)(e / M.Kp), k = (int)(e - (long long)i * M.Kp);
+  const double v = (i < M.N && k < M.K) ? M.thc[(size_t)i * M.K + k] : 0.0;
+  const __bf16 h = (__bf16)(float)v;
+  const double r1 = v - (double)bf_to_f(h);
+  const __bf16 md = (__bf16)(float)r1;
+  const double r2 = r1 - (double)bf_to_f(md);
+  const __bf16 lo = (__bf16)(float)r2;
+  __bf16 *T = (__bf16 *)M.T3;
+  T[e] = h;
+  T[tot + e] = md;
+  T[2 * tot + e] = lo;
+}
+
+// ---------------------------------------------------------------------------
+template <int NKB>
+__device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
+  constexpr int TPW = MF_TILES_PER_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int half = lane / 32, col = lane % 32;
+  const int Kp = M.Kp;
+  const int tile0 = blk * (4 * TPW) + wave * TPW;
+  // B operands: psi^T of this wave's tiles (pixel = column), three pieces
+  bf16x8 bh[TPW][NKB], bm[TPW][NKB], bl[TPW][NKB];
+  const int n = M.H * M.W;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int p = (tile0 + t) * 32 + col;
+    const int r = p / M.W, c = p - r * M.W;
+    float v[NKB][8];
+    pixel_feats<NKB>(M, r, c, p < n, half, v);
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) split3(v[kb], bh[t][kb], bm[t][kb], bl[t][kb]);
+  }
+  float mrun[TPW], S[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    mrun[t] = -INFINITY;
+    S[t] = 0.f;
+  }
+  const long long tot = (long long)M.Npad * Kp;
+  const __bf16 *T = (const __bf16 *)M.T3;
+  for (int g0 = 0; g0 < M.Npad; g0 += MF_GRAIN_STAGE) {
+    const int gcnt = min(MF_GRAIN_STAGE, M.Npad - g0);
+    __syncthreads();
+    // stage the three pieces of grains [g0, g0 + gcnt): sT[piece][g][Kp]
+    const int words = gcnt * Kp / 8;  // 16-byte units per piece
+    for (int w = threadIdx.x; w < 3 * words; w += PD_BLOCK) {
+      const int piece = w / words, q = w - piece * words;
+      const bf16x8 v = *(const bf16x8 *)(T + piece * tot + (size_t)g0 * Kp + (size_t)q * 8);
+      *(bf16x8 *)(sT + (size_t)piece * MF_GRAIN_STAGE * Kp + (size_t)q * 8) = v;
+    }
+    __syncthreads();
+    for (int gt = 0; gt < gcnt; gt += 32) {
+      bf16x8 ah[NKB], am[NKB], al[NKB];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        const size_t o = (size_t)(gt + col) * Kp + kb * 16 + half * 8;
+        ah[kb] = *(const bf16x8 *)(sT + o);
+        am[kb] = *(const bf16x8 *)(sT + (size_t)MF_GRAIN_STAGE * Kp + o);
+        al[kb] = *(const bf16x8 *)(sT + (size_t)2 * MF_GRAIN_STAGE * Kp + o);
+      }
+      const int gbase = g0 + gt;
+      const bool partial = gbase + 32 > M.N;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        f32x16 acc;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+          acc = mfma6(ah[kb], am[kb], al[kb], bh[t][kb], bm[t][kb], bl[t][kb], acc);
+        if (partial) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int g = gbase + (j / 4) * 8 + half * 4 + (j % 4);
+            if (g >= M.N) acc[j] = -INFINITY;
+          }
+        }
+        float cm = acc[0];
+#pragma unroll
+        for (int j = 1; j < 16; ++j) cm = fmaxf(cm, acc[j]);
+        // rows that are all padding grains (-inf) contribute nothing; skipping them
+        // also avoids exp2(-inf - (-inf)) while this lane's maximum is still -inf
+        if (cm == -INFINITY) continue;
+        const float mn = fmaxf(mrun[t], cm);
+        float s = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mn);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += __builtin_amdgcn_exp2f(acc[j] - mn);
+        S[t] = s;
+        mrun[t] = mn;
+      }
+    }
+  }
+  // merge the two halves (lanes l and l + 32 hold the same pixel)
+  double ell = 0.0;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const float mo = __shfl_xor(mrun[t], 32, PD_WAVE);
+    const float so = __shfl_xor(S[t], 32, PD_WAVE);
+    const float mm = fmaxf(mrun[t], mo);
+    const float ss = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mm) + so * __builtin_amdgcn_exp2f(mo - mm);
+    const float lse = mm + __builtin_amdgcn_logf(ss);
+    const int p = (tile0 + t) * 32 + col;
+    if (half == 0 && p < M.n32) {
+      pd_glb(M.lse32)[p] = p < n ? lse : INFINITY;
+      if (p < n) {
+        const int g = pd_glb(M.labels)[p];
+        if (g >= 0 && g < M.N) {
+          // exact FP64 logit of the true grain
+          const int r = p / M.W, c = p - r * M.W;
+          const double *px = M.tx64 + (size_t)c * M.DP, *py = M.ty64 + (size_t)r * M.DP;
+          const double *th = M.thc + (size_t)g * M.K;
+          double sg = 0.0;
+          for (int k = 0; k < M.K; ++k) sg = __builtin_fma(th[k], px[c_fa[k]] * py[c_fb[k]], sg);
+          ell += sg - (double)lse;
+        } else {
+          ell = NAN;
+        }
+      }
+    }
+  }
+  const double tot_l = pd_wave_sum(ell);
+  if (lane == 0) pd_glb(M.part_l)[blk * 4 + wave] = tot_l;
+}
+
+template <int NKB>
+__global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ maps,
+                                                    const int32_t *__restrict__ off, int n_maps,
+                                                    int total) {
+  __shared__ __align__(16) __bf16 sT[3 * MF_GRAIN_STAGE * 16 * NKB];
+  if ((int)blockIdx.x >= total) return;
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  lse16_block<NKB>(M, blockIdx.x - off[m], sT);
+}
+
+// ---------------------------------------------------------------------------
+// k16_grad: block = 4 waves on one pixel chunk, wave w on grain group 4 q + w.
+// Per 32-pixel tile the four waves build the shared operands once in LDS:
+//   sA  [3][NKB][64] x 16 B : psi rows (pixel = row) for the logit product
+//   sQ  [2][2][64]   x 16 B : psi^T (feature = column) in FP16 hi/lo for the
+//                             gradient product, inner index h*8+e of block kb2
+//                             = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4
+//   sL, sG [32]             : lse and label of the tile's pixels
+// The gradient product takes p - delta in [-1, 1] as one FP16 value (11-bit
+// mantissa, 2^-12 relative) against the two FP16 pieces of psi.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct GradLds {
+  bf16x8 A[3][2][64];
+  f16x8 Q[2][2][64];
+  float L[32];
+  int G[32];
+  int lo, hi;
+};
+
+template <int NKB>
+__device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh) {
+  constexpr int GT = PD_MF_GROUP_TILES;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int half = lane / 32, col = lane % 32;
+  const int qb = (M.ggroups + 3) / 4;  // blocks of 4 grain groups per chunk
+  const int chunk = local_blk / qb;
+  const int grp = (local_blk - chunk * qb) * 4 + wave;
+  const bool active = grp < M.ggroups;
+  const int g0 = min(grp, M.ggroups - 1) * (GT * 32);
+  const int gtn = min(GT, (M.Npad - g0) / 32);
+  const int Kp = M.Kp;
+  const long long tot = (long long)M.Npad * Kp;
+  const __bf16 *T = (const __bf16 *)M.T3;
+  bf16x8 th[GT][NKB], tm[GT][NKB], tl[GT][NKB];
+#pragma unroll
+  for (int t = 0; t < GT; ++t) {
+    const int g = min(g0 + t * 32 + col, M.Npad - 1);
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      const size_t o = (size_t)g * Kp + kb * 16 + half * 8;
+      th[t][kb] = *(const bf16x8 *)(T + o);
+      tm[t][kb] = *(const bf16x8 *)(T + tot + o);
+      tl[t][kb] = *(const bf16x8 *)(T + 2 * tot + o);
+    }
+  }
+  f32x16 accg[GT];
+#pragma unroll
+  for (int t = 0; t < GT; ++t)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) accg[t][j] = 0.f;
+  const int n = M.H * M.W;
+  const int pt0 = chunk * M.chunk_tiles;
+  const int pt1 = min(pt0 + M.chunk_tiles, M.tiles32);
+  const int fcol = col < M.K ? col : 0;
+  const int fa = c_fa[fcol], fb = c_fb[fcol];
+  const bool fvalid = col < M.K;
+  const float *txf = (const float *)M.txT, *tyf = (const float *)M.tyT;
+  for (int pt = pt0; pt < pt1; ++pt) {
+    const int pbase = pt * 32;
+    const int r0 = pbase / M.W, c0 = pbase - r0 * M.W;
+    __syncthreads();
+    if (wave == 0) {
+      int r, c;
+      pix_rc(r0, c0, col, M.W, r, c);
+      float v[NKB][8];
+      pixel_feats<NKB>(M, r, c, pbase + col < n, half, v);
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) split3(v[kb], sh.A[0][kb][lane], sh.A[1][kb][lane], sh.A[2][kb][lane]);
+    } else if (wave <= 2) {
+      const int kb2 = wave - 1;
+      f16x8 qh, ql;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int o = 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
+        int r, c;
+        pix_rc(r0, c0, o, M.W, r, c);
+        const float v = (fvalid && pbase + o < n) ? txf[c * M.DP + fa] * tyf[r * M.DP + fb] : 0.f;
+        const _Float16 h = (_Float16)v;
+        qh[e] = h;
+        ql[e] = (_Float16)(v - (float)h);
+      }
+      sh.Q[kb2][0][lane] = qh;
+      sh.Q[kb2][1][lane] = ql;
+    } else {
+      int g = -1, lo = 0x7fffffff, hi = -1;
+      if (lane < 32) {
+        const int p = pbase + lane;
+        sh.L[lane] = pd_glb(M.lse32)[p];
+        g = p < n ? pd_glb(M.labels)[p] : -1;
+        sh.G[lane] = g;
+        if (g >= 0) lo = hi = g;
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, PD_WAVE));
+        hi = max(hi, __shfl_xor(hi, o, PD_WAVE));
+      }
+      if (lane == 0) {
+        sh.lo = lo;
+        sh.hi = hi;
+      }
+    }
+    __syncthreads();
+    if (!active) continue;
+    bf16x8 ph[NKB], pm[NKB], pl[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      ph[kb] = sh.A[0][kb][lane];
+      pm[kb] = sh.A[1][kb][lane];
+      pl[kb] = sh.A[2][kb][lane];
+    }
+    float lrow[16];
+    int grow[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        lrow[4 * b + r] = sh.L[8 * b + 4 * half + r];
+        grow[4 * b + r] = sh.G[8 * b + 4 * half + r];
+      }
+    f32x16 acc[GT];
+#pragma unroll
+    for (int t = 0; t < GT; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pm[kb], tm[t][kb], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl[kb], th[t][kb], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], tl[t][kb], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pm[kb], th[t][kb], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], tm[t][kb], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], th[t][kb], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < GT; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]);
+    if (sh.hi >= g0 && sh.lo < g0 + GT * 32) {
+#pragma unroll
+      for (int t = 0; t < GT; ++t) {
+        const int grain = g0 + t * 32 + col;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[t][j] -= (grow[j] == grain) ? 1.f : 0.f;
+      }
+    }
+#pragma unroll
+    for (int kb2 = 0; kb2 < 2; ++kb2) {
+      const f16x8 qh = sh.Q[kb2][0][lane], ql = sh.Q[kb2][1][lane];
+      f16x8 x[GT];
+#pragma unroll
+      for (int t = 0; t < GT; ++t)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[t][e] = (_Float16)acc[t][8 * kb2 + e];
+#pragma unroll
+      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], ql, accg[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], qh, accg[t], 0, 0, 0);
+    }
+  }
+  if (!active) return;
+  // accg[t]: rows = grains g0 + 32 t + (8 b + 4 h + r), column = feature col
+  const int FW = 32;
+  float *out = M.part_g32 + (size_t)chunk * M.Npad * FW;
+#pragma unroll
+  for (int t = 0; t < GT; ++t) {
+    if (t >= gtn) break;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int g = g0 + t * 32 + (j / 4) * 8 + half * 4 + (j % 4);
+      pd_glb(out)[(size_t)g * FW + col] = accg[t][j];
+    }
+  }
+}
+
+template <int NKB>
+__global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps,
+                                                     int total) {
+  __shared__ GradLds sh;
+  if ((int)blockIdx.x >= total) return;
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  grad16_block<NKB>(M, blockIdx.x - off[m], sh);
+}
+
+// Phi from the per-wave partials, grad from the chunk partials (fixed order).
+__global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict__ maps,
+                                                       const int32_t *__restrict__ off, int n_maps) {
+  if ((int)blockIdx.x < n_maps) {
+    const MapDev &M = maps[blockIdx.x];
+    if (PD_GATED(M)) return;
+    __shared__ double red[PD_BLOCK];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < M.a16_items * 4; t += PD_BLOCK) s += M.part_l[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *M.phi = PD_LN2 * red[0] / ((double)M.H * (double)M.W);
+    return;
+  }
+  const int b = blockIdx.x - n_maps;
+  const int m = pd_find_map(off, n_maps, b);
+  const MapDev &M = maps[m];
+  if (M.grad == nullptr || PD_GATED(M)) return;
+  // 16 consecutive outputs x 16 chunk phases; phase sums added by a fixed tree
+  __shared__ double red[16][17];
+  const int ol = threadIdx.x % 16, ph = threadIdx.x / 16;
+  const int o = (b - off[m]) * 16 + ol;
+  double s = 0.0;
+  if (o < M.N * M.K) {
+    const int i = o / M.K, k = o - i * M.K;
+    const size_t stride = (size_t)M.Npad * 32;
+    const auto src = pd_glb(M.part_g32 + (size_t)i * 32 + k);
+    for (int c = ph; c < M.chunks; c += 16) s += (double)src[(size_t)c * stride];
+  }
+  red[ph][ol] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (ph < w) red[ph][ol] += red[ph + w][ol];
+    __syncthreads();
+  }
+  if (ph == 0 && o < M.N * M.K) M.grad[o] = red[0][ol] * M.grad_scale;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+static int nkb_for(int dmax) { return dmax <= 4 ? 1 : 2; }
+
+void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
+  const int nkb = nkb_for(P.dmax);
+  if (stage == 0) {
+    k16_prep<<<P.off16P[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16P, P.n);
+  } else if (stage == 1) {
+    const int total = P.off16A[P.n];
+    if (nkb == 1) k16_lse<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
+    else k16_lse<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
+  } else if (stage == 2) {
+    const int total = P.off16B[P.n];  // blocks: chunks x ceil(grain groups / 4)
+    if (nkb == 1) k16_grad<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
+    else k16_grad<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
+  } else {
+    k16_reduce<<<P.n + P.off16R[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16R, P.n);
+  }
 }
 
 void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) {
-  pd_plan_eval(P, true, s, center);
+  if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
+  for (int st = 0; st < 4; ++st) pd_bf16_launch(P, st, s);
+}
+
+pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
+                                 const double *const *theta, double *phi_out,
+                                 double *const *grad_out, hipStream_t s) {
+  for (int p = 0; p < n; ++p)
+    if (probs[p].degree > 6)
+      return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
+  EvalPlan P;
+  Arena L;
+  pd_plan_layout(P, L, probs, n, 2);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
+  hipError_t e = pd_plan_upload(ctx, P, s);
+  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, hipGetErrorString(e));
+  pd_plan_tables(P, s);
+  pd_bf16_plan_eval(ctx, P, s, true);
+  e = hipGetLastError();
+  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, hipGetErrorString(e));
+  return PD_OK;
+}
+
+void pd_bf16_profile_stages(pd_ctx *, const EvalPlan &P, int reps, hipStream_t s, hipEvent_t *ev) {
+  for (int r = 0; r < reps; ++r) pd_bf16_launch(P, 0, s);
+  (void)hipEventRecord(ev[1], s);
+  for (int r = 0; r < reps; ++r) pd_bf16_launch(P, 1, s);
+  (void)hipEventRecord(ev[2], s);
+  for (int r = 0; r < reps; ++r) pd_bf16_launch(P, 2, s);
+  (void)hipEventRecord(ev[3], s);
 }
 
 pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *, int, double *const *, const void *, int,
                         hipStream_t) {
   return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_INIT_MLP: not built yet");
-}
-
-void pd_bf16_profile_stages(pd_ctx *, const EvalPlan &P, int reps, hipStream_t s, hipEvent_t *ev) {
-  for (int r = 0; r < reps; ++r) pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-  (void)hipEventRecord(ev[1], s);
-  for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-  (void)hipEventRecord(ev[2], s);
-  for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
-  (void)hipEventRecord(ev[3], s);
 }

@@ -32,7 +32,7 @@ struct Arena {
 };
 
 struct MapRegions {
-  size_t tx64, ty64, txT, thc, C, lse, part_l, part_g, part_c;
+  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32;
 };
 
 // Everything one batched evaluation / assignment needs, laid out in an arena.
@@ -43,10 +43,12 @@ struct EvalPlan {
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;
   std::vector<int32_t> offA, offB, offP, offR;
+  std::vector<int32_t> off16P, off16A, off16B, off16R;  // BF16 path (prec 2)
   int max_hw = 0, max_k = 0, dmax = 8;
   size_t o_maps = 0, o_off = 0;
   MapDev *d_maps = nullptr;
   int32_t *d_offA = nullptr, *d_offB = nullptr, *d_offP = nullptr, *d_offR = nullptr;
+  int32_t *d_off16P = nullptr, *d_off16A = nullptr, *d_off16B = nullptr, *d_off16R = nullptr;
 };
 
 pd_status pd_fail(pd_ctx *c, pd_status s, const std::string &msg);
@@ -65,6 +67,8 @@ pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
                                  const double *const *theta, double *phi_out,
                                  double *const *grad_out, hipStream_t s);
 void pd_fit_release(pd_ctx *ctx);
+// BF16 path: stage 0 prep (thc pieces), 1 log-sum-exp, 2 gradient, 3 reductions.
+void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s);
 // BF16 path: time its prep / matrix-core stages, recording ev[1], ev[2], ev[3]
 // (the PREP, LSE and GRAD slots).
 void pd_bf16_profile_stages(pd_ctx *ctx, const EvalPlan &P, int reps, hipStream_t s,

@@ -13,6 +13,8 @@
 #define PD_BLOCK 256
 #define PD_WAVES_PER_BLOCK (PD_BLOCK / PD_WAVE)
 #define PD_DMAX 8
+// 32-grain tiles per wave of the matrix-core gradient kernel
+#define PD_MF_GROUP_TILES 2
 
 // log2(e) and ln(2) as the nearest doubles.
 #define PD_LOG2E 1.4426950408889634074
@@ -49,6 +51,14 @@ struct MapDev {
   int64_t *part_c;                  // [a_items] per-wave correct counts
   // optional gate: when non-null and zero, every kernel skips this map
   const int32_t *gate;
+  // FP32 row table and the BF16 matrix-core path
+  void *tyT;                        // [H][DP] P_b(x2) in the evaluation type
+  void *T3;                         // [3][Npad][Kp] bf16 pieces of thc
+  float *lse32;                     // [n32] base-2 log-sum-exp (+inf on padding pixels)
+  float *part_g32;                  // [chunks][Npad][32] partial gradient moments
+  int32_t Kp, n32, tiles32;         // K rounded up to 16; pixels rounded up to 32; 32-pixel tiles
+  int32_t a16_items, b16_items;     // blocks of k16_lse; waves of k16_grad
+  int32_t chunk_tiles, chunks, ggroups;
 };
 
 

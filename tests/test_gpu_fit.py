@@ -125,3 +125,16 @@ def test_zero_budget_returns_start(pd, orc):
     assert rep["iters"] == 0 and rep["status"] == "budget"
     assert abs(rep["phi"] + np.log(gm.N)) < 1e-12
     assert torch.all(th == 0)
+
+
+def test_bf16_fit_reaches_99(pd, orc):
+    """The matrix-core evaluation drives the same device L-BFGS to >= 99% on the
+    power-diagram map (accuracy recomputed by the oracle in FP64)."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "bf16", init="zero", max_iter=2000,
+                  target_acc=0.99)[0]
+    assert rep["status"] == "target"
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
+    assert nc / (gm.H * gm.W) >= 0.99

@@ -221,3 +221,69 @@ def test_validate_labels(pd):
     lab[57] = -1
     with pytest.raises(pdl.PdError):
         ctx.validate([problem(pdl, lab, 10, 10, 2, 1, 0.1)])
+
+
+# ------------------------------------------------------------------ BF16 -------
+
+BF16_CASES = [  # H, W, N, d, eps, theta scale, seed
+    (4, 5, 2, 1, 0.1, 1.0, 0),
+    (31, 67, 9, 2, 0.05, 0.5, 1),
+    (64, 64, 64, 3, 0.02, 0.3, 2),
+    (50, 130, 65, 4, 1e-2, 0.2, 3),
+    (23, 300, 130, 6, 1e-2, 0.1, 4),
+    (40, 41, 200, 5, 1e-3, 0.05, 5),
+    (17, 33, 300, 4, 1e-3, 0.02, 6),
+]
+
+
+@pytest.mark.parametrize("H,W,N,d,eps,scale,seed", BF16_CASES)
+def test_objective_grad_bf16(pd, orc, H, W, N, d, eps, scale, seed):
+    """Matrix-core path (three-piece BF16 logits, two-piece gradient product,
+    FP32 accumulation) against the FP64 oracle at the reduced-precision bound."""
+    pdl, ctx = pd
+    rng = np.random.default_rng(seed)
+    th = synth.random_theta(N, d, rng, scale=scale, multi_index=orc.multi_index(d))
+    lab = synth.random_labels(H, W, N, rng)
+    phi_ref, g_ref = orc.objective_grad(th, lab, H, W, d, eps)
+    phi, grads = ctx.objective_grad([problem(pdl, lab, H, W, N, d, eps)], [dev(th)], "bf16")
+    ep, eg = rel_err(float(phi[0]), phi_ref), grad_err(grads[0].cpu().numpy(), g_ref)
+    print(f"bf16 H={H} W={W} N={N} d={d} eps={eps}: phi rel {ep:.2e} grad rel {eg:.2e}")
+    assert ep <= 2e-3 and eg <= 2e-3
+
+
+def test_bf16_polynomial_map_eps_1e3(pd, orc):
+    """A degree-4 polynomial-diagram map at eps = 1e-3 near its generating theta:
+    logits of size ~1e3 with sharp boundaries."""
+    pdl, ctx = pd
+    rng = np.random.default_rng(21)
+    gm = synth.polynomial_diagram(96, 160, 120, 4, rng)
+    th = synth.coef_to_theta(gm.coef, orc.multi_index(4))
+    th = th + rng.normal(size=th.shape) * 1e-4
+    phi_ref, g_ref = orc.objective_grad(th, gm.labels, gm.H, gm.W, 4, 1e-3)
+    p = problem(pdl, gm.labels, gm.H, gm.W, gm.N, 4, 1e-3)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-3), ("bf16", 2e-3)):
+        phi, g = ctx.objective_grad([p], [dev(th)], prec)
+        ep, eg = rel_err(float(phi[0]), phi_ref), grad_err(g[0].cpu().numpy(), g_ref)
+        print(f"{prec}: phi rel {ep:.2e} grad rel {eg:.2e}")
+        assert ep <= tol and eg <= tol, prec
+
+
+def test_bf16_batched_and_degree_limit(pd, orc):
+    pdl, ctx = pd
+    rng = np.random.default_rng(22)
+    probs, ths, refs = [], [], []
+    for (H, W, N, d) in [(30, 40, 5, 2), (64, 100, 70, 3), (17, 257, 130, 4)]:
+        lab = synth.random_labels(H, W, N, rng)
+        th = synth.random_theta(N, d, rng, scale=0.3, multi_index=orc.multi_index(d))
+        probs.append(problem(pdl, lab, H, W, N, d, 0.05))
+        ths.append(dev(th))
+        refs.append(orc.objective_grad(th, lab, H, W, d, 0.05))
+    phi, g = ctx.objective_grad(probs, ths, "bf16")
+    for k, (pr, gr) in enumerate(refs):
+        assert rel_err(float(phi[k]), pr) <= 2e-3 and grad_err(g[k].cpu().numpy(), gr) <= 2e-3
+        phi_s, g_s = ctx.objective_grad([probs[k]], [ths[k]], "bf16")
+        assert torch.equal(phi_s[0], phi[k]) and torch.equal(g_s[0], g[k])
+    lab = np.zeros(100, np.int32)
+    with pytest.raises(pdl.PdError) as e:
+        ctx.objective_grad([problem(pdl, lab, 10, 10, 3, 7, 0.1)], [dev(np.zeros((3, 36)))], "bf16")
+    assert e.value.status == 2
