@@ -183,6 +183,19 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t
                           const double *const *theta /*host*/, pd_precision prec, int32_t reps,
                           double *ms_out /*host*/, void *stream);
 
+/* Autotuner of the work decomposition (tile shapes of the gradient kernels:
+ * pixel-tile size per 64-grain wave on the FP64/FP32 path, pixel-chunk length
+ * per grain group on the BF16 path).  Times one evaluation of the given batch
+ * for each candidate (waves per map: 1024 .. 32768), keeps the fastest for the
+ * batch's key (precision, largest degree, log2 of the pixel-grain pairs, number
+ * of maps) in the context, and uses it in every later plan with that key.  If
+ * the environment variable PD_AUTOTUNE_CACHE names a file, results are read
+ * from and appended to it (one "prec dmax size_log2 n_maps waves" line each).
+ * Synchronous.  best_waves_out (host, may be NULL) receives the choice. */
+pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                      const double *const *theta /*host*/, pd_precision prec,
+                      int32_t *best_waves_out /*host*/, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

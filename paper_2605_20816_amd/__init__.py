@@ -79,6 +79,9 @@ _SIGS = {
     "pd_profile_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
 }
 
 STAGES = ("tables", "center", "prep", "lse", "grad", "reduce")
@@ -239,6 +242,17 @@ class Context:
         self._check(lib().pd_profile_eval(self._h, arr, n, _ptrs(thetas), PREC[prec], int(reps),
                                           ms, _stream(stream)))
         return dict(zip(STAGES, list(ms)))
+
+    def autotune(self, probs, thetas, prec="fp64", stream=None):
+        """Time the candidate work decompositions on this batch; returns the chosen
+        waves-per-map, which later plans with the same key use."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        best = ctypes.c_int32(0)
+        self._check(lib().pd_autotune(self._h, arr, n, _ptrs(thetas), PREC[prec], ctypes.byref(best),
+                                      _stream(stream)))
+        return int(best.value)
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
             max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, stream=None):

@@ -5,6 +5,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -133,8 +134,8 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.a16_items = (M.tiles32 + 15) / 16;
     M.ggroups = (M.Npad + 32 * PD_MF_GROUP_TILES - 1) / (32 * PD_MF_GROUP_TILES);
     {
-      // about 4096 waves of k16_grad (4 grain groups per block)
-      long long ct = (long long)M.tiles32 * ((M.ggroups + 3) / 4 * 4) / 4096;
+      // about target_waves / 2 waves of k16_grad (4 grain groups per block)
+      long long ct = (long long)M.tiles32 * ((M.ggroups + 3) / 4 * 4) / std::max(1, P.target_waves / 2);
       if (ct < 1) ct = 1;
       M.chunk_tiles = (int)std::min<long long>(ct, M.tiles32);
       M.chunks = (M.tiles32 + M.chunk_tiles - 1) / M.chunk_tiles;
@@ -265,6 +266,37 @@ void pd_plan_assign(const EvalPlan &P, hipStream_t s) {
   pd_launch_assign(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
 }
 
+static std::tuple<int, int, int, int> tune_key(const pd_problem *probs, int n, int prec) {
+  int dmax = 1;
+  double pairs = 0.0;
+  for (int p = 0; p < n; ++p) {
+    dmax = std::max(dmax, probs[p].degree);
+    pairs += (double)probs[p].height * probs[p].width * probs[p].n_grains;
+  }
+  const int lg = (int)floor(log2(std::max(pairs, 1.0)));
+  const int nb = n <= 1 ? 1 : (n <= 8 ? 8 : 64);
+  return std::make_tuple(prec, pd_dmax_bucket(dmax), lg, nb);
+}
+
+static void tune_load(pd_ctx *ctx) {
+  if (ctx->tune_loaded) return;
+  ctx->tune_loaded = true;
+  const char *path = getenv("PD_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  int a, b, c2, d, w;
+  while (fscanf(f, "%d %d %d %d %d", &a, &b, &c2, &d, &w) == 5) ctx->tuned[std::make_tuple(a, b, c2, d)] = w;
+  fclose(f);
+}
+
+int pd_tuned_waves(pd_ctx *ctx, const pd_problem *probs, int n, int prec) {
+  tune_load(ctx);
+  auto it = ctx->tuned.find(tune_key(probs, n, prec));
+  if (it != ctx->tuned.end()) return it->second;
+  return 8192;
+}
+
 #define PD_HIP(ctx, expr)                                                                  \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -393,6 +425,7 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_prob
   if (code == 2) return pd_bf16_objective_grad(ctx, probs, n_probs, theta, phi_out, grad_out, s);
   EvalPlan P;
   Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   pd_plan_layout(P, L, probs, n_probs, code);
   pd_status st = pd_reserve(ctx, L.off);
   if (st != PD_OK) return st;
@@ -450,6 +483,7 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   hipStream_t s = (hipStream_t)stream;
   EvalPlan P;
   Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   pd_plan_layout(P, L, probs, n_probs, code);
   const size_t o_phi = L.take(sizeof(double) * n_probs);
   std::vector<size_t> o_g(n_probs);
@@ -497,6 +531,77 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     ms_out[k] = (double)ms / reps;
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
+  return PD_OK;
+}
+
+pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                      const double *const *theta, pd_precision prec, int32_t *best_waves_out,
+                      void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (!probs || n_probs < 1 || !theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "pd_autotune: bad arguments");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta entry is NULL");
+    if (code == 2 && probs[p].degree > 6)
+      return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  tune_load(ctx);
+  static const int cand[] = {1024, 2048, 4096, 8192, 16384, 32768};
+  float best_ms = 1e30f;
+  int best = 8192;
+  hipEvent_t e0, e1;
+  PD_HIP(ctx, hipEventCreate(&e0));
+  PD_HIP(ctx, hipEventCreate(&e1));
+  for (int w : cand) {
+    EvalPlan P;
+    Arena L;
+    P.target_waves = w;
+    pd_plan_layout(P, L, probs, n_probs, code);
+    const size_t o_phi = L.take(sizeof(double) * n_probs);
+    std::vector<size_t> o_g(n_probs);
+    for (int p = 0; p < n_probs; ++p)
+      o_g[p] = L.take(sizeof(double) * (size_t)P.maps[p].N * P.maps[p].K);
+    pd_status st = pd_reserve(ctx, L.off);
+    if (st != PD_OK) return st;
+    std::vector<double *> g(n_probs);
+    for (int p = 0; p < n_probs; ++p) g[p] = (double *)(ctx->ws + o_g[p]);
+    pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), g.data(), nullptr, nullptr);
+    PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+    pd_plan_tables(P, s);
+    auto run = [&]() {
+      if (code == 2) pd_bf16_plan_eval(ctx, P, s, true);
+      else pd_plan_eval(P, true, s, true);
+    };
+    run();  // warm-up
+    PD_HIP(ctx, hipEventRecord(e0, s));
+    for (int r = 0; r < 5; ++r) run();
+    PD_HIP(ctx, hipEventRecord(e1, s));
+    PD_HIP(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    PD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = w;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const auto key = tune_key(probs, n_probs, code);
+  ctx->tuned[key] = best;
+  if (const char *path = getenv("PD_AUTOTUNE_CACHE")) {
+    if (FILE *f = fopen(path, "a")) {
+      fprintf(f, "%d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+              std::get<3>(key), best);
+      fclose(f);
+    }
+  }
+  if (best_waves_out) *best_waves_out = best;
   return PD_OK;
 }
 

@@ -38,6 +38,7 @@ enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3
 
 struct FitDev {
   int32_t N, K, NK, m, max_iter, check_every, gauge;
+  int32_t vt;  // threads that own elements (from this map's size alone); others add zeros
   int64_t n_pix;
   double target_acc, gtol;
   double *x, *g, *d, *xt, *graw, *S, *Y, *rho;
@@ -123,12 +124,12 @@ __device__ void blk_gauge(FitDev &F, double *v, double *red) {
 #pragma unroll
       for (int q = 0; q < VG; ++q) sm[q] = 0.0;
       const int cnt = min(VG, F.K - k0);
-      for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+      for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
 #pragma unroll
         for (int q = 0; q < VG; ++q)
           if (q < cnt) sm[q] += v[(size_t)i * F.K + k0 + q];
       blk_sums<VG>(sm, red);
-      for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+      for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
 #pragma unroll
         for (int q = 0; q < VG; ++q)
           if (q < cnt) v[(size_t)i * F.K + k0 + q] -= sm[q] / (double)F.N;
@@ -159,7 +160,7 @@ __device__ inline void fit_stop(FitDev &F, int status) {
 __device__ void pass_gstats(FitDev &F, double *red) {
   double v[2] = {0.0, 0.0};
   double mx = 0.0;
-  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = F.g[i];
     v[0] = __builtin_fma(gi, gi, v[0]);
     v[1] = __builtin_fma(gi, F.d[i], v[1]);
@@ -178,7 +179,7 @@ __device__ void pass_gstats(FitDev &F, double *red) {
 // d = -g and its slope g.d (steepest descent restart).
 __device__ void set_steepest(FitDev &F, double *red) {
   double v[1] = {0.0};
-  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = F.g[i];
     F.d[i] = -gi;
     v[0] = __builtin_fma(gi, -gi, v[0]);
@@ -236,7 +237,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
     const double *__restrict__ pd = F.d;
     const double *__restrict__ pgr = F.graw;
     const double *__restrict__ pxt = F.xt;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
       const double di = pd[i], gri = pgr[i], gi = pg[i], xti = pxt[i];
       const double si = t * di;
       const double yi = gri - gi;
@@ -302,7 +303,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
       int js[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) js[u] = slot[min(k0 + u, L - 1)];
-      for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
         const double gi = pg[e], si = pns[e], yi = pny[e];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -380,7 +381,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   const double *__restrict__ pY = F.Y;
   const double *__restrict__ pg = F.g;
   double *__restrict__ pdir = F.d;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = pg[i];
     double di = cg * gi;
     // slots in blocks of 8: the 16 loads of a block are issued before use
@@ -478,14 +479,14 @@ __device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, do
   int &action = *action_p;
   const int n = F.NK;
   // gradient of f = -Phi at xt, gauge-projected, in graw
-  for (int i = threadIdx.x; i < n; i += blockDim.x) F.graw[i] = -F.graw[i];
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) F.graw[i] = -F.graw[i];
   __syncthreads();
   blk_gauge(F, F.graw, red);
   FIT_STAMP(F, 1);
   const double ft = -*F.phi_t;
   if (threadIdx.x == 0) F.evals++;
   if (F.phase == PH_INIT) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
       F.g[i] = F.graw[i];
       F.d[i] = -F.graw[i];
     }
@@ -511,7 +512,7 @@ __device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, do
     return;
   }
   double dv[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
   blk_sums<1>(dv, red);
   FIT_STAMP(F, 2);
   const double dt = dv[0];
@@ -593,19 +594,19 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
   if (*F.active == 0) return;
   const double t = F.t;
-  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) F.xt[i] = F.x[i] + t * F.d[i];
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
   __syncthreads();
   for (int k0 = 0; k0 < F.K; k0 += VG) {
     double sm[VG];
 #pragma unroll
     for (int q = 0; q < VG; ++q) sm[q] = 0.0;
     const int cnt = min(VG, F.K - k0);
-    for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
 #pragma unroll
       for (int q = 0; q < VG; ++q)
         if (q < cnt) sm[q] += F.xt[(size_t)i * F.K + k0 + q];
     blk_sums<VG>(sm, red);
-    for (int i = threadIdx.x; i < F.N; i += blockDim.x)
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
 #pragma unroll
       for (int q = 0; q < VG; ++q)
         if (q < cnt) {
@@ -625,7 +626,7 @@ __global__ void k_fit_stamp(FitDev *Fs, int n_maps) {
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_start) {
   FitDev &F = Fs[blockIdx.x];
   __shared__ double red[MAX_WAVES * 48 + 48];
-  for (int i = threadIdx.x; i < F.NK; i += blockDim.x) {
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
     if (zero_start) F.x[i] = 0.0;
     F.d[i] = 0.0;
   }
@@ -715,6 +716,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   const int eval_prec = prec == 2 ? 2 : prec;
   EvalPlan P;
   Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);
@@ -749,6 +751,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.max_iter = opts->max_iter;
     f.check_every = opts->check_every;
     f.gauge = (int)opts->gauge;
+    f.vt = std::min(FIT_THREADS, std::max(64, ((int)NK / 4 + 63) / 64 * 64));
     f.n_pix = (int64_t)M.H * M.W;
     f.target_acc = opts->target_acc;
     f.gtol = opts->gtol;
@@ -808,15 +811,13 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     st = pd_warm_start(ctx, probs, n, xs.data(), opts->mlp, eval_prec, s);
     if (st != PD_OK) return st;
   }
-  k_fit_init<<<n, 256, 0, s>>>(dF, zero_start ? 1 : 0);
+  // block size: the largest per-map thread count (about 4 elements per thread)
+  int vt = 64;
+  for (int p = 0; p < n; ++p) vt = std::max(vt, F[p].vt);
+  k_fit_init<<<n, vt, 0, s>>>(dF, zero_start ? 1 : 0);
   FIT_HIP(ctx, hipGetLastError());
 
   // ---- one step, captured as a graph
-  // threads per map for the L-BFGS vector work: one element per thread up to
-  // 1024 threads (each pass is then about one memory round trip)
-  int max_nk = 1;
-  for (int p = 0; p < n; ++p) max_nk = std::max(max_nk, F[p].NK);
-  const int vt = std::min(FIT_THREADS, std::max(64, (max_nk / 4 + 63) / 64 * 64));
   auto step = [&](hipStream_t ss) {
     k_fit_trial<<<n, vt, 0, ss>>>(dF);
     pd_fit_eval(ctx, P, eval_prec, ss);

@@ -544,6 +544,7 @@ pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
       return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
   EvalPlan P;
   Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n, 2);
   pd_plan_layout(P, L, probs, n, 2);
   pd_status st = pd_reserve(ctx, L.off);
   if (st != PD_OK) return st;

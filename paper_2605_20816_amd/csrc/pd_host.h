@@ -1,7 +1,9 @@
 // pd_host.h -- host-side planning structures of libpd (not part of the C ABI).
 #pragma once
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pd.h"
@@ -19,7 +21,13 @@ struct pd_ctx {
   char *stage = nullptr;
   size_t stage_cap = 0;
   hipEvent_t staged = nullptr;
+  // autotuned waves per map, keyed by (precision, dmax bucket, log2 pairs, maps)
+  std::map<std::tuple<int, int, int, int>, int> tuned;
+  bool tune_loaded = false;
 };
+
+// Waves per map for this batch: the autotuned value for its key, else a default.
+int pd_tuned_waves(pd_ctx *ctx, const pd_problem *probs, int n, int prec);
 
 // Bump allocator over byte offsets (256-byte aligned regions).
 struct Arena {

@@ -10,8 +10,9 @@ sites, weights, matrices, coefficients, noise):
   (x - y_i).A_i(x - y_i) - w_i.
 * random polynomial diagram of degree D: the power-diagram part
   (|y_i|^2 - w_i) - 2 y_i.x plus sigma * xi, xi_{i,(a,b)} ~ N(0, 1/(a+b+1)^2) on
-  the Legendre products P_a(x1) P_b(x2), a + b <= D; h = 2/sqrt(N),
-  weights uniform in [0, h^2/2], sigma = h^2/4.
+  the Legendre products P_a(x1) P_b(x2), a + b <= D; h = 2/sqrt(N) (the typical
+  site spacing), weights uniform in [0, h^2/8], sigma = h^2/16 (chosen so that
+  at least 95% of the cells are non-empty at N = 1000, D = 4 and N = 250, D = 6).
 * boundary noise: a pixel is on a boundary when a 4-neighbour has another
   label; round(frac * #boundary) of them, drawn without replacement, take a
   label drawn uniformly from their distinct differing 4-neighbour labels.
@@ -107,12 +108,12 @@ def anisotropic_power_diagram(H, W, N, rng, wmax=0.02, lmin=0.5, lmax=2.0):
 def polynomial_diagram(H, W, N, D, rng):
     h = 2.0 / np.sqrt(N)
     y = rng.uniform(-1.0, 1.0, size=(N, 2))
-    w = rng.uniform(0.0, 0.5 * h * h, size=N)
+    w = rng.uniform(0.0, 0.125 * h * h, size=N)
     C = np.zeros((N, D + 1, D + 1))
     C[:, 0, 0] = (y ** 2).sum(1) - w
     C[:, 1, 0] = -2.0 * y[:, 0]
     C[:, 0, 1] = -2.0 * y[:, 1]
-    sigma = 0.25 * h * h
+    sigma = 0.0625 * h * h
     for k in range(D + 1):
         for b in range(k + 1):
             a = k - b
@@ -253,4 +254,24 @@ def coef_to_theta(coef, multi_index):
     for k, (aa, bb) in enumerate(zip(a, b)):
         if aa < Da and bb < Db:
             out[:, k] = coef[:, aa, bb]
+    return out
+
+
+def batch_maps(seed, n_maps, hw=(128, 769), grains=(20, 501), degrees=(2, 3, 4)):
+    """Maps drawn like the 64-map batch (sizes, grain counts and degrees uniform
+    over the given ranges; APD + boundary noise at d = 2, random polynomial
+    diagrams of degree d otherwise), one seed per map (seed + j)."""
+    out = []
+    for j in range(n_maps):
+        rng = np.random.default_rng(seed + j)
+        H, W = (int(v) for v in rng.integers(hw[0], hw[1], size=2))
+        N = int(rng.integers(grains[0], grains[1]))
+        d = int(rng.choice(np.asarray(degrees)))
+        if d == 2:
+            gm = anisotropic_power_diagram(H, W, N, rng, wmax=0.02)
+            gm = boundary_noise(gm, 0.01, rng)
+        else:
+            gm = polynomial_diagram(H, W, N, d, rng)
+        gm.meta.update(degree=d, eps=1e-3 if d > 2 else 1e-2)
+        out.append(gm)
     return out
