@@ -69,9 +69,10 @@ typedef enum { PD_FP64 = 0, PD_FP32 = 1, PD_BF16 = 2 } pd_precision;
  * (the paper's choice, Section 5.1); CENTERED keeps sum_i theta_i = 0. */
 typedef enum { PD_GAUGE_LAST_ZERO = 0, PD_GAUGE_CENTERED = 1, PD_GAUGE_NONE = 2 } pd_gauge;
 
-/* Start of the fit: the caller's theta, theta = 0 (Section 5.2), or the learned
- * warm start (per-grain descriptors -> MLP -> scaled theta). */
-typedef enum { PD_INIT_GIVEN = 0, PD_INIT_ZERO = 1, PD_INIT_MLP = 2 } pd_init;
+/* Start of the fit: the caller's theta, theta = 0 (Section 5.2), the learned
+ * warm start (moment seed + network correction, scaled; see pd_warm_start) or
+ * the moment seed of Section 5.6.2 alone, scaled the same way. */
+typedef enum { PD_INIT_GIVEN = 0, PD_INIT_ZERO = 1, PD_INIT_MLP = 2, PD_INIT_HEURISTIC = 3 } pd_init;
 
 #define PD_MAX_DEGREE 8
 
@@ -130,6 +131,105 @@ pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_pro
                     const double *const *theta /*host*/, int32_t *const *labels_out /*host*/,
                     int64_t *n_correct_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Warm start.  Per grain i (pixels G_i, n pixels, N grains):
+ *   frame   (PD_FRAME_DIM doubles): centroid y'_i (eq. centroid-guess), local
+ *           radius r_i = 2 sqrt(lambda_max(B'_i)) (at least one pixel width
+ *           2 / max(H, W)), central second moments B11, B12, B22 (eq. cov-guess,
+ *           in x units), pixel count |G_i|, 0.  Empty grains: (0, 0, 1, 0, ...).
+ *   descriptor (PD_DESC_DIM floats): log(N |G_i| / n); B'_i / r_i^2 (3 entries);
+ *           the 27 local Legendre indicator moments mean over G_i of
+ *           P_a(u_1) P_b(u_2), 1 <= a + b <= 6, u = (x - y'_i) / r_i, in the
+ *           degree-graded order; log(N) / 10.  Zero for empty grains.  Exact
+ *           integer pixel sums and a fixed summation order make them bitwise
+ *           reproducible.
+ *   moment seed theta'_i (Section 5.6.2): A'_i = B'_i^{-1} (eq. A-guess; the
+ *           identity at degree 1), w'_i = sqrt(det A'_i) area(G_i) / pi, the
+ *           ratio of the grain's area (4 |G_i| / n on [-1, 1]^2) to the area of
+ *           the ellipse of B'_i (eq. w-guess and the sentence after it), the score (x - y')^T A' (x - y') - w' written in the
+ *           Legendre basis (x^2 = (2 P_2(x) + 1) / 3); at degree 1 the common
+ *           |x|^2 is dropped (a gauge term, Lemma 4.2); coefficients of degree
+ *           >= 3 are zero.  Zero rows for empty grains.
+ * The network maps a descriptor to a correction of theta'_i expressed in grain
+ * i's local frame (polynomial in u of total degree d, K_d outputs). */
+#define PD_DESC_DIM 32
+#define PD_FRAME_DIM 8
+#define PD_MLP_IN PD_DESC_DIM
+#define PD_MLP_WIDTH 256
+
+/* Networks by degree: params[d] is a DEVICE FP32 buffer of pd_mlp_num_params(K_d)
+ * floats for maps of degree d, or NULL (those maps use the moment seed alone). */
+typedef struct pd_mlp {
+  const float *params[PD_MAX_DEGREE + 1];
+} pd_mlp;
+
+/* Parameter count of the network 32 -> 256 -> 256 -> k_out with GELU
+ * (0.5 z (1 + erf(z / sqrt 2))) after both hidden layers.  Buffer layout:
+ * W1 (32 x 256, input-major), b1 (256), W2 (256 x 256), b2, W3 (256 x k_out), b3;
+ * layer l computes z = x W_l + b_l.  0 if k_out < 1. */
+int64_t pd_mlp_num_params(int32_t k_out);
+
+/* Descriptors and frames of every grain of each map.  desc_out: host array of
+ * DEVICE float[N_p x PD_DESC_DIM]; frame_out: host array (NULL, or NULL entries,
+ * to skip) of DEVICE double[N_p x PD_FRAME_DIM].  Stream-ordered.  Labels must
+ * lie in [0, N) (pixels with other labels are ignored). */
+pd_status pd_descriptors(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                         float *const *desc_out /*host*/, double *const *frame_out /*host*/,
+                         void *stream);
+
+/* Moment seed theta' (unscaled) of each map: theta_out host array of DEVICE
+ * N_p x K_p FP64.  Stream-ordered. */
+pd_status pd_heuristic(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                       double *const *theta_out /*host*/, void *stream);
+
+/* Training targets from fitted parameters.  With lambda > 0 and g the least-
+ * squares fit theta_fit_i ~ lambda theta'_i + g over grains (g a common shift,
+ * i.e. a gauge; lambda the free scale; lambda = 1 if the fit is not positive),
+ * target_i = (theta_fit_i - g) / lambda - theta'_i re-expanded in grain i's local
+ * frame (x = y'_i + r_i u).  theta_fit: host array of DEVICE N_p x K_p FP64;
+ * target_out: host array of DEVICE float[N_p x K_p]; lambda_out: DEVICE
+ * double[n_probs] or NULL.  Stream-ordered. */
+pd_status pd_warm_targets(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                          const double *const *theta_fit /*host*/,
+                          float *const *target_out /*host*/, double *lambda_out,
+                          void *stream);
+
+/* Network forward pass on `batch` rows of x (DEVICE float[batch x PD_MLP_IN]) into
+ * y_out (DEVICE float[batch x k_out]).  PD_FP32: FP32 arithmetic (the training
+ * forward pass); PD_BF16: weights and activations rounded to bf16 on the matrix
+ * cores, FP32 accumulation and bias.  Stream-ordered. */
+pd_status pd_mlp_forward(pd_ctx *ctx, int32_t k_out, const float *params, const float *x,
+                         int32_t batch, pd_precision prec, float *y_out, void *stream);
+
+/* Loss mean((y - target)^2) over batch x k_out outputs of the FP32 forward pass
+ * (loss_out: DEVICE double[1]) and its gradient with respect to every parameter
+ * (grad_out: DEVICE float[pd_mlp_num_params(k_out)], same layout as params).
+ * Deterministic (fixed summation order).  Stream-ordered. */
+pd_status pd_mlp_backward(pd_ctx *ctx, int32_t k_out, const float *params, const float *x,
+                          const float *target, int32_t batch, double *loss_out, float *grad_out,
+                          void *stream);
+
+/* One Adam step (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); step >= 1.
+ * All arrays DEVICE float[n_params].  Stream-ordered. */
+pd_status pd_mlp_adam(pd_ctx *ctx, int64_t n_params, float *params, const float *grad, float *m,
+                      float *v, int32_t step, float lr, float beta1, float beta2, float eps,
+                      void *stream);
+
+/* Warm start of each map: theta_hat_i = theta'_i + (network correction of grain i,
+ * BF16 inference, taken back to the global frame; no correction where mlp or
+ * mlp->params[d] is NULL), then theta = s* theta_hat with s* maximising the
+ * concave restriction s -> Phi(s theta_hat) (Proposition 4.4): bracketing in
+ * log2 s by steps of 2 from s0 = eps max(H, W) / (28 sqrt N) (at most 12 steps),
+ * then 6 golden-section evaluations; the best evaluated point is kept.  If
+ * Phi(s* theta_hat) < Phi(0) = -log N the map falls back to theta = 0.  The
+ * search evaluates Phi in FP64 for prec PD_FP64, in FP32 otherwise.
+ * theta_out: host array of DEVICE N_p x K_p FP64; scale_out (host, may be NULL):
+ * s* per map (0 after a fall-back).  Synchronous. */
+pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                        const pd_mlp *mlp /*host, may be NULL*/, double *const *theta_out /*host*/,
+                        pd_precision prec, double *scale_out /*host*/, void *stream);
+
 /* L-BFGS fit (Section 5.2) of n_probs maps at once, on the device.
  * Minimises -Phi with memory `history`, strong-Wolfe line search (c1 = 1e-4,
  * c2 = 0.9, cubic zoom, <= 20 evaluations per search), first trial step
@@ -145,7 +245,7 @@ typedef struct {
   double target_acc;      /* stop at Acc >= target_acc (e.g. 0.99); > 1 disables */
   double gtol;            /* stop at ||grad||_inf <= gtol (0 disables)           */
   int32_t check_every;    /* accuracy / stop-flag poll period in iterations      */
-  const void *mlp;        /* PD_INIT_MLP: a pd_mlp (see below), else NULL        */
+  const struct pd_mlp *mlp; /* PD_INIT_MLP: the networks (see pd_warm_start)    */
 } pd_fit_opts;
 
 typedef struct {
@@ -158,7 +258,9 @@ typedef struct {
 } pd_fit_report;
 
 /* theta_inout: host array of DEVICE N_p x K_p FP64 pointers (start if
- * PD_INIT_GIVEN; result on return).  reports: host array of n_probs. */
+ * PD_INIT_GIVEN; result on return).  reports: host array of n_probs.
+ * PD_INIT_MLP / PD_INIT_HEURISTIC run pd_warm_start first (its time counts in
+ * seconds_to_target). */
 pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);

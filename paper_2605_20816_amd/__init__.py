@@ -24,9 +24,12 @@ STATUS = {0: "PD_OK", 1: "PD_ERR_INVALID_ARG", 2: "PD_ERR_UNSUPPORTED", 3: "PD_E
           4: "PD_ERR_HIP", 5: "PD_ERR_NONFINITE", 6: "PD_ERR_NOT_CONVERGED"}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 GAUGE = {"last": 0, "centered": 1, "none": 2}
-INIT = {"given": 0, "zero": 1, "mlp": 2}
+INIT = {"given": 0, "zero": 1, "mlp": 2, "heuristic": 3}
 FIT_STATUS = {0: "target", 1: "budget", 2: "gtol", 3: "linesearch", 4: "nonfinite"}
 MAX_DEGREE = 8
+DESC_DIM = 32
+FRAME_DIM = 8
+MLP_WIDTH = 256
 
 
 class PdError(RuntimeError):
@@ -46,6 +49,10 @@ class _FitOpts(ctypes.Structure):
                 ("history", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("target_acc", ctypes.c_double), ("gtol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p * 9)]
 
 
 class _FitReport(ctypes.Structure):
@@ -82,6 +89,30 @@ _SIGS = {
     "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "pd_mlp_num_params": (ctypes.c_int64, [ctypes.c_int32]),
+    "pd_descriptors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "pd_heuristic": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "pd_warm_targets": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "pd_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_mlp_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
+    "pd_warm_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                     ctypes.POINTER(_Mlp), ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_void_p]),
 }
 
 STAGES = ("tables", "center", "prep", "lse", "grad", "reduce")
@@ -110,6 +141,32 @@ def exported_symbols():
 def num_features(d: int) -> int:
     """Section 3.1: K_d = (d+1)(d+2)/2."""
     return int(lib().pd_num_features(int(d)))
+
+
+def mlp_num_params(k_out: int) -> int:
+    """Parameter count of the warm-start network 32 -> 256 -> 256 -> k_out."""
+    return int(lib().pd_mlp_num_params(int(k_out)))
+
+
+class Mlp:
+    """Warm-start networks by degree: params[d] is a float32 CUDA tensor of
+    mlp_num_params(K_d) entries (or absent)."""
+
+    def __init__(self, params=None):
+        self.params = dict(params or {})
+
+    def handle(self):
+        m = _Mlp()
+        for d, t in self.params.items():
+            if t is None:
+                continue
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError("network parameters must be a contiguous float32 CUDA tensor")
+            if t.numel() != mlp_num_params(num_features(d)):
+                raise ValueError(f"degree {d}: expected {mlp_num_params(num_features(d))} parameters")
+            m.params[d] = t.data_ptr()
+        self._keep = m
+        return ctypes.pointer(m)
 
 
 @dataclass
@@ -260,11 +317,83 @@ class Context:
         Returns a list of report dicts."""
         n = len(probs)
         arr = (_Problem * n)(*[p.c() for p in probs])
+        h = None if mlp is None else mlp.handle()
         opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
-                        check_every, None if mlp is None else mlp.handle())
+                        check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p))
         reps = (_FitReport * n)()
         self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
                                  _stream(stream)))
         return [dict(status=FIT_STATUS.get(r.status, r.status), iters=r.iters, evals=r.evals,
                      phi=r.phi, acc=r.acc, seconds_total=r.seconds_total,
                      seconds_to_target=r.seconds_to_target) for r in reps]
+
+    # ------------------------------------------------------------ warm start
+    def descriptors(self, probs, frames=False, stream=None):
+        """Per-grain descriptors (N x 32 float32) and, if asked, frames (N x 8 float64)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = torch.device("cuda", self.device)
+        desc = [torch.empty((p.N, DESC_DIM), dtype=torch.float32, device=dev) for p in probs]
+        fr = [torch.empty((p.N, FRAME_DIM), dtype=torch.float64, device=dev) for p in probs] if frames else None
+        self._check(lib().pd_descriptors(self._h, arr, n, _ptrs(desc), _ptrs(fr) if fr else None,
+                                         _stream(stream)))
+        return (desc, fr) if frames else desc
+
+    def heuristic(self, probs, stream=None):
+        """Moment seed theta' (N x K float64) of each map (Section 5.6.2)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = torch.device("cuda", self.device)
+        out = [torch.empty((p.N, num_features(p.d)), dtype=torch.float64, device=dev) for p in probs]
+        self._check(lib().pd_heuristic(self._h, arr, n, _ptrs(out), _stream(stream)))
+        return out
+
+    def warm_targets(self, probs, thetas, stream=None):
+        """Local-frame training targets (N x K float32) and the scales lambda (n,)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        dev = torch.device("cuda", self.device)
+        tg = [torch.empty((p.N, num_features(p.d)), dtype=torch.float32, device=dev) for p in probs]
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        self._check(lib().pd_warm_targets(self._h, arr, n, _ptrs(thetas), _ptrs(tg),
+                                          ctypes.c_void_p(lam.data_ptr()), _stream(stream)))
+        return tg, lam
+
+    def mlp_forward(self, params, x, k_out, prec="fp32", stream=None):
+        """Network outputs (B x k_out float32) for descriptors x (B x 32 float32)."""
+        y = torch.empty((x.shape[0], k_out), dtype=torch.float32, device=x.device)
+        self._check(lib().pd_mlp_forward(self._h, int(k_out), ctypes.c_void_p(params.data_ptr()),
+                                         ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                         PREC[prec], ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def mlp_backward(self, params, x, target, loss_out=None, grad_out=None, stream=None):
+        """(loss (1,) float64, gradient like params) of mean((y - target)^2)."""
+        k_out = int(target.shape[1])
+        loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+        grad = grad_out if grad_out is not None else torch.empty_like(params)
+        self._check(lib().pd_mlp_backward(self._h, k_out, ctypes.c_void_p(params.data_ptr()),
+                                          ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(target.data_ptr()), int(x.shape[0]),
+                                          ctypes.c_void_p(loss.data_ptr()),
+                                          ctypes.c_void_p(grad.data_ptr()), _stream(stream)))
+        return loss, grad
+
+    def mlp_adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """One in-place Adam step on params (moments m, v updated)."""
+        self._check(lib().pd_mlp_adam(self._h, int(params.numel()), ctypes.c_void_p(params.data_ptr()),
+                                      ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                      ctypes.c_void_p(v.data_ptr()), int(step), float(lr),
+                                      float(beta1), float(beta2), float(eps), _stream(stream)))
+
+    def warm_start(self, probs, mlp=None, prec="fp32", stream=None):
+        """Warm-start theta (N x K float64) per map and the chosen scales s*."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = torch.device("cuda", self.device)
+        out = [torch.empty((p.N, num_features(p.d)), dtype=torch.float64, device=dev) for p in probs]
+        sc = (ctypes.c_double * n)()
+        self._check(lib().pd_warm_start(self._h, arr, n, None if mlp is None else mlp.handle(),
+                                        _ptrs(out), PREC[prec], sc, _stream(stream)))
+        return out, list(sc)

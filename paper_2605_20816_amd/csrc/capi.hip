@@ -335,6 +335,7 @@ void pd_destroy(pd_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->stage) (void)hipHostFree(ctx->stage);
   if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   pd_fit_release(ctx);

@@ -662,9 +662,6 @@ void pd_fit_release(pd_ctx *ctx) {
   }
 }
 
-pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *probs, int n, double *const *x,
-                        const void *mlp, int prec, hipStream_t s);
-
 // Objective + gradient of every running map at its trial point.
 static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, hipStream_t s) {
   if (prec == 2) pd_bf16_plan_eval(ctx, P, s, false);
@@ -688,7 +685,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   else return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown precision");
   if (opts->gauge < PD_GAUGE_LAST_ZERO || opts->gauge > PD_GAUGE_NONE)
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown gauge");
-  if (opts->init < PD_INIT_GIVEN || opts->init > PD_INIT_MLP)
+  if (opts->init < PD_INIT_GIVEN || opts->init > PD_INIT_HEURISTIC)
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown init");
   if (opts->init == PD_INIT_MLP && opts->mlp == nullptr)
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "PD_INIT_MLP needs opts->mlp");
@@ -705,6 +702,12 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
       if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
   pd_status st = pd_validate(ctx, probs, n, stream);
   if (st != PD_OK) return st;
+  if (opts->init == PD_INIT_MLP || opts->init == PD_INIT_HEURISTIC) {
+    // warm start into the caller's buffers, then a fit from there
+    st = pd_warm_start(ctx, probs, n, opts->init == PD_INIT_MLP ? opts->mlp : nullptr,
+                       theta_inout, opts->prec, nullptr, stream);
+    if (st != PD_OK) return st;
+  }
   FIT_HIP(ctx, hipSetDevice(ctx->device));
   if (!ctx->fit) ctx->fit = new FitState();
   if (!ctx->fit->stream) FIT_HIP(ctx, hipStreamCreateWithFlags(&ctx->fit->stream, hipStreamNonBlocking));
@@ -805,12 +808,6 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   const auto t_stamp = clk::now();
   k_fit_stamp<<<(n + 255) / 256, 256, 0, s>>>(dF, n);
   pd_plan_tables(P, s);
-  if (opts->init == PD_INIT_MLP) {
-    std::vector<double *> xs(n);
-    for (int p = 0; p < n; ++p) xs[p] = F[p].x;
-    st = pd_warm_start(ctx, probs, n, xs.data(), opts->mlp, eval_prec, s);
-    if (st != PD_OK) return st;
-  }
   // block size: the largest per-map thread count (about 4 elements per thread)
   int vt = 64;
   for (int p = 0; p < n; ++p) vt = std::max(vt, F[p].vt);

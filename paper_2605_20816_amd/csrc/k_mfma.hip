@@ -566,8 +566,3 @@ void pd_bf16_profile_stages(pd_ctx *, const EvalPlan &P, int reps, hipStream_t s
   for (int r = 0; r < reps; ++r) pd_bf16_launch(P, 2, s);
   (void)hipEventRecord(ev[3], s);
 }
-
-pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *, int, double *const *, const void *, int,
-                        hipStream_t) {
-  return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_INIT_MLP: not built yet");
-}

@@ -16,6 +16,8 @@ struct pd_ctx {
   std::string err;
   char *ws = nullptr;     // evaluation workspace, grown on demand
   size_t ws_cap = 0;
+  char *aux = nullptr;    // warm-start and network workspace, grown on demand
+  size_t aux_cap = 0;
   FitState *fit = nullptr;
   // pinned staging of the map descriptors; `staged` marks the last copy out of it
   char *stage = nullptr;
