@@ -8,14 +8,20 @@ update, two-loop recursion, hard assignment and accuracy check).  The metric is
 pixel-grain pairs of L + grad L evaluated per second over the timed steps.
 
 Printed: one JSON line with the metric, a live roofline of the dominant kernel
-(per-stage HIP-event timing on the library's stream), the CPU oracle timed on a
-bounded sample, and time-to-99% of the 64x64 power-diagram fit.
+(per-stage HIP-event timing on the library's stream; HBM traffic from the
+committed rocprofv3 counter summary when it was taken on the current kernel
+source), the CPU oracle timed on a bounded sample, and time-to-99% pixel
+accuracy of the plain method (FP64, theta = 0, one map at a time) against the
+accelerated one (all maps in one batched fit, reduced precision, longer L-BFGS
+memory, with and without the learned warm start) on a batch of c4-style maps.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,6 +44,80 @@ def flops_per_pair(stage: str, d: int) -> int:
     return 2 * d + 4 if stage == "lse" else 4 * d + 3
 
 
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch of `kernel` from profiles/traffic_<kernel>.md (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by its copy-kernel calibration
+    factor), or None if the summary is missing or was taken on other source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    for name, sha in rec["sources"].items():
+        src = os.path.join(ROOT, "paper_2605_20816_amd", "csrc", name)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != sha:
+            return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"])
+
+
+def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
+    """Plain (FP64, theta = 0, history 10, one map per call) against accelerated
+    (one batched call, history 32) fits of c4-style maps to 99% pixel accuracy."""
+    from paper_2605_20816_amd import warm_train as wt
+    maps = [synth.config_c4_map(j) for j in range(n_maps)]
+    probs = [pdl.Problem(torch.as_tensor(g.labels).cuda(), g.H, g.W, g.N, g.meta["degree"],
+                         g.meta["eps"]) for g in maps]
+
+    def zeros(pp):
+        return [torch.zeros((p.N, pdl.num_features(p.d)), dtype=torch.float64, device="cuda")
+                for p in pp]
+
+    plain = []
+    for p in probs:
+        r = ctx.fit([p], zeros([p]), "fp64", init="zero", history=10, max_iter=2000,
+                    target_acc=0.99)[0]
+        plain.append(r["seconds_to_target"])
+    nets = None
+    train_s = None
+    if with_net:
+        # networks per degree, trained on plain fits of other maps of the same kinds
+        t0 = time.perf_counter()
+        nets = {}
+        for d in sorted({p.d for p in probs}):
+            tm = [g for g in synth.batch_maps(70000 + 100 * d, 24, hw=(128, 257), grains=(20, 201),
+                                              degrees=(d,))]
+            tp = [pdl.Problem(torch.as_tensor(g.labels).cuda(), g.H, g.W, g.N, d, g.meta["eps"])
+                  for g in tm]
+            th, _ = wt.plain_fits(ctx, tp, "fp32", 2000)
+            X, T = wt.training_rows(ctx, tp, th)
+            nets[d], _ = wt.train(ctx, X, T, steps=2000, lr=1e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+    out = {"workload": f"{n_maps} c4-style maps (seeds 404..{403 + n_maps}): sides 128..768, "
+                       f"N 20..500, d 2..4, eps 1e-2 (d=2) / 1e-3",
+           "plain": "FP64, theta0=0, L-BFGS memory 10, one map per pd_fit call",
+           "target_acc": 0.99, "budget_iters": 2000}
+    variants = [("accelerated_fp32", "fp32", "zero", None), ("accelerated_bf16", "bf16", "zero", None)]
+    if with_net:
+        variants.append(("accelerated_bf16_mlp", "bf16", "mlp", pdl.Mlp(nets)))
+    for name, prec, init, mlp in variants:
+        reps = ctx.fit(probs, zeros(probs), prec, init=init, mlp=mlp, history=32, max_iter=2000,
+                       target_acc=0.99)
+        both = [k for k in range(n_maps) if plain[k] > 0 and reps[k]["seconds_to_target"] > 0]
+        t_plain = sum(plain[k] for k in both)
+        t_acc = max(reps[k]["seconds_to_target"] for k in both) if both else None
+        out[name] = {"maps_at_99": len(both), "plain_seconds": t_plain, "seconds": t_acc,
+                     "speedup": (t_plain / t_acc) if t_acc else None,
+                     "plain_maps_at_99": sum(t > 0 for t in plain),
+                     "maps_at_99_this_mode": sum(r["seconds_to_target"] > 0 for r in reps)}
+    if train_s is not None:
+        out["network_training_seconds_excluded"] = train_s
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +125,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--t99-maps", type=int, default=16,
+                    help="c4-style maps in the time-to-99%% comparison (0 skips it)")
+    ap.add_argument("--no-net", action="store_true",
+                    help="skip the learned warm start in the time-to-99%% comparison")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy of known size "
+                         "that calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -56,6 +143,13 @@ def main():
 
     import paper_2605_20816_amd as pdl
     import synth
+
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = pdl.Context(0)
     gm = synth.config_c2()
@@ -87,20 +181,10 @@ def main():
     achieved = fl / (st[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[args.prec],
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4),
-            "traffic": None, "kernel": f"k_{dom}", "ms_per_launch": round(st[dom], 5),
-            "flops_per_pair": flops_per_pair(dom, d),
+            "traffic": traffic_from_profile(f"k_{dom}"), "kernel": f"k_{dom}",
+            "ms_per_launch": round(st[dom], 5), "flops_per_pair": flops_per_pair(dom, d),
             "stage_ms": {k: round(v, 5) for k, v in st.items()}}
-
-    # time to 99% on the 64x64 N = 8 power-diagram map (FP64 plain fit from zero)
-    c1 = synth.config_c1()
-    p1 = pdl.Problem(torch.as_tensor(c1.labels).cuda(), c1.H, c1.W, c1.N, 1, 1e-2)
-    ctx.fit([p1], [torch.zeros((c1.N, 3), dtype=torch.float64, device="cuda")], "fp64",
-            init="zero", max_iter=2000, target_acc=0.99)
-    r1 = ctx.fit([p1], [torch.zeros((c1.N, 3), dtype=torch.float64, device="cuda")], "fp64",
-                 init="zero", max_iter=2000, target_acc=0.99)[0]
-    t99 = {"workload": "64x64 power diagram, N=8, d=1, eps=1e-2, FP64, theta0=0",
-           "seconds": r1["seconds_to_target"], "iters": r1["iters"], "evals": r1["evals"],
-           "acc": r1["acc"]}
+    t99 = time_to_99(pdl, ctx, args.t99_maps, not args.no_net, torch, synth) if args.t99_maps else None
 
     cpu = None
     if not args.no_cpu:
@@ -115,12 +199,6 @@ def main():
         cpu = {"value": n_eval * pairs / cs, "unit": "pairs/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"{n_eval} full FP64 L+grad L evaluations of the 256x256 N={N} d=2 map"}
-        obj = lambda t: oracle.objective_grad(t, c1.labels, c1.H, c1.W, 1, 1e-2)
-        acc = lambda t: oracle.assign(t, c1.H, c1.W, 1, c1.labels)[1] / (c1.H * c1.W)
-        t0 = time.perf_counter()
-        ro = oracle.lbfgs_fit(obj, np.zeros((c1.N, 3)), accuracy=acc, target_acc=0.99)
-        t99["cpu_oracle_seconds"] = time.perf_counter() - t0
-        t99["cpu_oracle_iters"] = ro["iters"]
 
     out = {
         "metric": "pixel-grain evals/s for L+grad L (device L-BFGS fit step)",

@@ -70,8 +70,8 @@ typedef enum { PD_FP64 = 0, PD_FP32 = 1, PD_BF16 = 2 } pd_precision;
 typedef enum { PD_GAUGE_LAST_ZERO = 0, PD_GAUGE_CENTERED = 1, PD_GAUGE_NONE = 2 } pd_gauge;
 
 /* Start of the fit: the caller's theta, theta = 0 (Section 5.2), the learned
- * warm start (moment seed + network correction, scaled; see pd_warm_start) or
- * the moment seed of Section 5.6.2 alone, scaled the same way. */
+ * warm start (network prediction from per-grain descriptors, scaled; see
+ * pd_warm_start) or the moment seed of Section 5.6.2, scaled the same way. */
 typedef enum { PD_INIT_GIVEN = 0, PD_INIT_ZERO = 1, PD_INIT_MLP = 2, PD_INIT_HEURISTIC = 3 } pd_init;
 
 #define PD_MAX_DEGREE 8
@@ -133,25 +133,26 @@ pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_pro
 
 /* ------------------------------------------------------------------------
  * Warm start.  Per grain i (pixels G_i, n pixels, N grains):
- *   frame   (PD_FRAME_DIM doubles): centroid y'_i (eq. centroid-guess), local
- *           radius r_i = 2 sqrt(lambda_max(B'_i)) (at least one pixel width
+ *   frame   (PD_FRAME_DIM doubles): centroid y'_i (eq. centroid-guess), radius
+ *           r_i = 2 sqrt(lambda_max(B'_i)) (at least one pixel width
  *           2 / max(H, W)), central second moments B11, B12, B22 (eq. cov-guess,
  *           in x units), pixel count |G_i|, 0.  Empty grains: (0, 0, 1, 0, ...).
- *   descriptor (PD_DESC_DIM floats): log(N |G_i| / n); B'_i / r_i^2 (3 entries);
- *           the 27 local Legendre indicator moments mean over G_i of
- *           P_a(u_1) P_b(u_2), 1 <= a + b <= 6, u = (x - y'_i) / r_i, in the
- *           degree-graded order; log(N) / 10.  Zero for empty grains.  Exact
- *           integer pixel sums and a fixed summation order make them bitwise
- *           reproducible.
+ *   descriptor (PD_DESC_DIM floats): log(N |G_i| / n); the 27 Legendre indicator
+ *           moments mean over G_i of P_a(x_1) P_b(x_2), 1 <= a + b <= 6, in the
+ *           degree-graded order; N B11, N B12, N B22; log(N) / 10.  Zero for
+ *           empty grains.  Exact integer pixel sums and a fixed summation order
+ *           make them bitwise reproducible.
  *   moment seed theta'_i (Section 5.6.2): A'_i = B'_i^{-1} (eq. A-guess; the
  *           identity at degree 1), w'_i = sqrt(det A'_i) area(G_i) / pi, the
  *           ratio of the grain's area (4 |G_i| / n on [-1, 1]^2) to the area of
- *           the ellipse of B'_i (eq. w-guess and the sentence after it), the score (x - y')^T A' (x - y') - w' written in the
- *           Legendre basis (x^2 = (2 P_2(x) + 1) / 3); at degree 1 the common
- *           |x|^2 is dropped (a gauge term, Lemma 4.2); coefficients of degree
- *           >= 3 are zero.  Zero rows for empty grains.
- * The network maps a descriptor to a correction of theta'_i expressed in grain
- * i's local frame (polynomial in u of total degree d, K_d outputs). */
+ *           the ellipse of B'_i (eq. w-guess and the sentence after it), the score
+ *           (x - y')^T A' (x - y') - w' of eq. h-APD in the Legendre basis
+ *           (x^2 = (2 P_2(x) + 1) / 3); at degree 1 the common |x|^2 is dropped (a
+ *           gauge term, Lemma 4.2); coefficients of degree >= 3 are zero.
+ *   Empty grains get the row (C, 0, ..., 0), C = 1 + max_i sum_k |theta_ik|, a
+ *           score above every other grain's on [-1, 1]^2, so they win no pixel.
+ * The network maps a descriptor to theta_i in the global Legendre basis, in the
+ * normalisation of pd_warm_targets (K_d outputs). */
 #define PD_DESC_DIM 32
 #define PD_FRAME_DIM 8
 #define PD_MLP_IN PD_DESC_DIM
@@ -182,13 +183,12 @@ pd_status pd_descriptors(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t 
 pd_status pd_heuristic(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                        double *const *theta_out /*host*/, void *stream);
 
-/* Training targets from fitted parameters.  With lambda > 0 and g the least-
- * squares fit theta_fit_i ~ lambda theta'_i + g over grains (g a common shift,
- * i.e. a gauge; lambda the free scale; lambda = 1 if the fit is not positive),
- * target_i = (theta_fit_i - g) / lambda - theta'_i re-expanded in grain i's local
- * frame (x = y'_i + r_i u).  theta_fit: host array of DEVICE N_p x K_p FP64;
- * target_out: host array of DEVICE float[N_p x K_p]; lambda_out: DEVICE
- * double[n_probs] or NULL.  Stream-ordered. */
+/* Training targets from fitted parameters: theta_fit centred over the non-empty
+ * grains (a common shift is a gauge, Lemma 4.2) and divided by its root mean
+ * square over those grains and the K coefficients (the scale of a fit is free,
+ * Proposition 4.8); zero rows for empty grains.  theta_fit: host array of DEVICE
+ * N_p x K_p FP64; target_out: host array of DEVICE float[N_p x K_p]; lambda_out:
+ * DEVICE double[n_probs] (the RMS) or NULL.  Stream-ordered. */
 pd_status pd_warm_targets(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                           const double *const *theta_fit /*host*/,
                           float *const *target_out /*host*/, double *lambda_out,
@@ -216,16 +216,17 @@ pd_status pd_mlp_adam(pd_ctx *ctx, int64_t n_params, float *params, const float 
                       float *v, int32_t step, float lr, float beta1, float beta2, float eps,
                       void *stream);
 
-/* Warm start of each map: theta_hat_i = theta'_i + (network correction of grain i,
- * BF16 inference, taken back to the global frame; no correction where mlp or
- * mlp->params[d] is NULL), then theta = s* theta_hat with s* maximising the
- * concave restriction s -> Phi(s theta_hat) (Proposition 4.4): bracketing in
- * log2 s by steps of 2 from s0 = eps max(H, W) / (28 sqrt N) (at most 12 steps),
- * then 6 golden-section evaluations; the best evaluated point is kept.  If
- * Phi(s* theta_hat) < Phi(0) = -log N the map falls back to theta = 0.  The
- * search evaluates Phi in FP64 for prec PD_FP64, in FP32 otherwise.
- * theta_out: host array of DEVICE N_p x K_p FP64; scale_out (host, may be NULL):
- * s* per map (0 after a fall-back).  Synchronous. */
+/* Warm start of each map: theta_hat = the network outputs for the map's grains
+ * (BF16 inference), centred over its non-empty grains, or the moment seed where
+ * mlp or mlp->params[d] is NULL; empty grains get the row that wins no pixel.
+ * Then theta = s* theta_hat with s* maximising the concave restriction
+ * s -> Phi(s theta_hat) (Proposition 4.4): bracketing in log2 s by steps of 2
+ * from s0 = eps max(H, W) / (28 sqrt N) (at most 12 steps), then 6 golden-section
+ * evaluations; the best evaluated point is kept.  If Phi(s* theta_hat) < Phi(0)
+ * = -log N the map falls back to theta = 0.  The search evaluates Phi in FP64 for
+ * prec PD_FP64, in FP32 otherwise.  theta_out: host array of DEVICE N_p x K_p
+ * FP64; scale_out (host, may be NULL): s* per map (0 after a fall-back).
+ * Synchronous. */
 pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                         const pd_mlp *mlp /*host, may be NULL*/, double *const *theta_out /*host*/,
                         pd_precision prec, double *scale_out /*host*/, void *stream);

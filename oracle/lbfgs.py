@@ -119,7 +119,9 @@ def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=200
 
     x = gauge_project(theta0, gauge) if gauge == "centered" else np.array(theta0, np.float64)
     if gauge == "last":
-        x[-1, :] = 0.0
+        # the common shift -theta_{N-1} puts the start in the gauge theta_{N-1} = 0
+        # without changing Phi or the diagram (Lemma 4.2)
+        x = x - x[-1]
 
     n_evals = 0
 

@@ -1,6 +1,6 @@
-"""Oracle of the warm start: per-grain descriptors, the moment heuristic, the
-local/global Legendre frame changes, training targets, the MLP (forward, MSE
-gradient, Adam) and the scale search.
+"""Oracle of the warm start: per-grain descriptors, the moment seed, training
+targets, the MLP (forward, MSE gradient, Adam), the assembly of a start from
+network outputs and the scale search.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -16,25 +16,23 @@ Everything here is plain FP64 numpy written from the definitions:
   Legendre basis with x^2 = (2 P_2(x) + 1) / 3 (Section 3.3).  At degree 1 the
   matrix is the identity and the common |x|^2 is dropped (it is a gauge term,
   Lemma 4.2).
-* Frame changes substitute an affine map t = alpha x + beta into a Legendre
-  series: each P_a is expanded into monomials (numpy's leg2poly), (alpha x +
-  beta)^k is expanded binomially, and the result is taken back to the Legendre
-  basis (poly2leg).
-* The descriptor of grain i (32 numbers): log(N |G_i| / n), B'_i / r_i^2 (three
-  entries), the 27 local Legendre indicator moments mean_{x in G_i} P_a(u_1)
-  P_b(u_2) for 1 <= a + b <= 6 in the graded order, and log(N) / 10; the local
-  coordinate is u = (x - y'_i) / r_i with r_i = 2 sqrt(lambda_max(B'_i)) (at
-  least one pixel width 2 / max(H, W)).
-* Training target of grain i from a fitted theta: with lambda > 0 and shift g the
-  least-squares fit of theta_i ~ lambda theta'_i + g over grains (g is a common
-  shift, a gauge, and lambda the free scale of Proposition 4.8),
-  Delta_i = (theta_i - g) / lambda - theta'_i, written in grain i's local frame.
+* Grains without pixels get the row (C, 0, ..., 0), C = 1 + max_i sum_k |theta_ik|
+  over the other grains: since |P_a| <= 1 on [-1, 1], their score exceeds every
+  other score, so they win no pixel.
+* The descriptor of grain i (32 numbers): log(N |G_i| / n), the 27 Legendre
+  indicator moments mean_{x in G_i} P_a(x_1) P_b(x_2) for 1 <= a + b <= 6 in the
+  graded order, N B'_i (three entries) and log(N) / 10.
+* Training target of grain i from a fitted theta: theta_i minus the mean over the
+  non-empty grains (a common shift is a gauge, Lemma 4.2), divided by the root
+  mean square of those centred values (the scale of a fit is free, Proposition
+  4.8).
 * MLP: 32 -> 256 -> 256 -> K, exact GELU z Phi(z), mean-squared-error loss over
   all B x K outputs, Adam (Kingma and Ba 2015).
-* Warm start: theta_hat_i = theta'_i + (network output for grain i taken back to
-  the global frame), then theta = s* theta_hat where s* maximises the concave
+* Warm start: theta_hat = network outputs centred over the non-empty grains
+  (or the moment seed), then theta = s* theta_hat where s* maximises the concave
   one-dimensional restriction s -> Phi(s theta_hat) (Proposition 4.4), found by
-  bracketing in log2(s) and a golden-section search.
+  bracketing in log2(s) and a golden-section search; theta = 0 if that is worse
+  than Phi(0).
 """
 from __future__ import annotations
 
@@ -100,15 +98,12 @@ def descriptors(labels, H, W, N, frames=None):
         if cnt == 0:
             continue
         rr, cc = np.nonzero(lab == i)
-        y1, y2, r = fr[i, 0], fr[i, 1], fr[i, 2]
-        u1 = (x1[cc] - y1) / r
-        u2 = (x2[rr] - y2) / r
         out[i, 0] = math.log(cnt * N / n)
-        out[i, 1:4] = fr[i, 3:6] / (r * r)
         for q, (a, b) in enumerate(pairs):
-            Pa = npleg.legval(u1, np.eye(a + 1)[a])
-            Pb = npleg.legval(u2, np.eye(b + 1)[b])
-            out[i, 4 + q] = np.mean(Pa * Pb)
+            Pa = npleg.legval(x1[cc], np.eye(a + 1)[a])
+            Pb = npleg.legval(x2[rr], np.eye(b + 1)[b])
+            out[i, 1 + q] = np.mean(Pa * Pb)
+        out[i, 28:31] = N * fr[i, 3:6]
         out[i, 31] = math.log(N) / 10.0
     return out
 
@@ -157,75 +152,45 @@ def heuristic_theta(frames, H, W, d):
         th[i, idx[(2, 0)]] = 2.0 * A[0, 0] / 3.0
         th[i, idx[(1, 1)]] = 2.0 * A[0, 1]
         th[i, idx[(0, 2)]] = 2.0 * A[1, 1] / 3.0
+    return fix_empty(th, frames)
+
+
+def fix_empty(theta, frames):
+    """Rows of grains without pixels := (C, 0, ..., 0), C = 1 + max over the other
+    grains of sum_k |theta_ik| (their score then exceeds every other on [-1, 1]^2)."""
+    th = np.array(theta, np.float64, copy=True)
+    live = np.asarray(frames)[:, 6] > 0
+    if np.all(live):
+        return th
+    C = 1.0 + (np.max(np.sum(np.abs(th[live]), axis=1)) if np.any(live) else 0.0)
+    th[~live] = 0.0
+    th[~live, 0] = C
     return th
 
 
-def affine_matrix(alpha, beta, d):
-    """M[a, a'] = coefficient of P_a'(x) in P_a(alpha x + beta), a, a' <= d."""
-    M = np.zeros((d + 1, d + 1))
-    for a in range(d + 1):
-        mono = npleg.leg2poly(np.eye(a + 1)[a])          # P_a(t) = sum_k mono[k] t^k
-        sub = np.zeros(d + 1)
-        for k, ck in enumerate(mono):                    # t^k = (alpha x + beta)^k
-            for j in range(k + 1):
-                sub[j] += ck * math.comb(k, j) * alpha ** j * beta ** (k - j)
-        leg = npleg.poly2leg(sub[: a + 1])
-        M[a, : leg.size] = leg
-    return M
-
-
-def change_frame(coef, d, al1, be1, al2, be2):
-    """Coefficients in P_a(x1) P_b(x2) of sum_ab c_ab P_a(al1 x1 + be1) P_b(al2 x2 + be2)."""
-    pairs = _graded(d)
-    idx = {p: k for k, p in enumerate(pairs)}
-    M1 = affine_matrix(al1, be1, d)
-    M2 = affine_matrix(al2, be2, d)
-    out = np.zeros(len(pairs))
-    for k, (a, b) in enumerate(pairs):
-        c = coef[k]
-        if c == 0.0:
-            continue
-        for a2 in range(a + 1):
-            for b2 in range(b + 1):
-                out[idx[(a2, b2)]] += c * M1[a, a2] * M2[b, b2]
-    return out
-
-
-def to_local(coef_global, frame, d):
-    """Global-frame coefficients re-expanded in u = (x - y') / r (x = y' + r u)."""
-    y1, y2, r = frame[0], frame[1], frame[2]
-    return change_frame(coef_global, d, r, y1, r, y2)
-
-
-def to_global(coef_local, frame, d):
-    """Local-frame coefficients re-expanded in x (u = x / r - y' / r)."""
-    y1, y2, r = frame[0], frame[1], frame[2]
-    return change_frame(coef_local, d, 1.0 / r, -y1 / r, 1.0 / r, -y2 / r)
-
-
-def targets(theta_fit, theta_h, frames, d):
-    """(N x K local-frame targets, lambda): least-squares scale and shift of the
-    fitted theta onto the seed, residual in each grain's local frame."""
+def targets(theta_fit, frames):
+    """(N x K targets, rms): the fitted theta centred over the non-empty grains and
+    divided by the root mean square of the centred values; zero rows for empty
+    grains."""
     tf = np.asarray(theta_fit, np.float64)
-    th = np.asarray(theta_h, np.float64)
-    a = tf - tf.mean(axis=0)
-    b = th - th.mean(axis=0)
-    num, den = float(np.sum(a * b)), float(np.sum(b * b))
-    lam = num / den if (den > 0.0 and num > 0.0) else 1.0
-    g = tf.mean(axis=0) - lam * th.mean(axis=0)
-    delta = (tf - g) / lam - th
-    out = np.zeros_like(delta)
-    for i in range(delta.shape[0]):
-        out[i] = to_local(delta[i], frames[i], d)
-    return out, lam
+    live = np.asarray(frames)[:, 6] > 0
+    out = np.zeros_like(tf)
+    if not np.any(live):
+        return out, 1.0
+    c = tf[live] - tf[live].mean(axis=0)
+    ss = float(np.sum(c * c))
+    rms = math.sqrt(ss / c.size) if ss > 0.0 else 1.0
+    out[live] = c / rms
+    return out, rms
 
 
-def apply_correction(theta_h, local, frames, d):
-    """theta_hat = theta' + correction taken back to the global frame."""
-    out = np.array(theta_h, np.float64, copy=True)
-    for i in range(out.shape[0]):
-        out[i] += to_global(np.asarray(local[i], np.float64), frames[i], d)
-    return out
+def assemble(outputs, frames):
+    """theta_hat from network outputs: centred over the non-empty grains, empty
+    grains given the row that wins no pixel."""
+    y = np.asarray(outputs, np.float64)
+    live = np.asarray(frames)[:, 6] > 0
+    th = y - (y[live].mean(axis=0) if np.any(live) else 0.0)
+    return fix_empty(th, frames)
 
 
 # ---------------------------------------------------------------- the network

@@ -16,7 +16,8 @@
 // If a search exhausts its evaluations at a point with sufficient decrease, that
 // point is accepted (it is evaluated once more, which the evaluation count shows).
 // Gauge (Remark 4.3): LAST_ZERO zeroes grain N-1's gradient row (theta_{N-1}
-// stays 0); CENTERED subtracts the grain mean.
+// stays 0; a given start is first shifted by -theta_{N-1}, Lemma 4.2); CENTERED
+// subtracts the grain mean.
 #include "pd_host.h"
 
 #include <math.h>
@@ -631,7 +632,17 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     F.d[i] = 0.0;
   }
   __syncthreads();
-  blk_gauge(F, F.x, red);
+  if (F.gauge == 0) {
+    // a given start is moved into the gauge theta_{N-1} = 0 by the common shift
+    // -theta_{N-1}, which leaves Phi and the diagram unchanged (Lemma 4.2)
+    double *last = red;  // K values
+    for (int k = (int)threadIdx.x; k < F.K; k += blockDim.x) last[k] = F.x[(size_t)(F.N - 1) * F.K + k];
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.x[i] -= last[i % F.K];
+    __syncthreads();
+  } else {
+    blk_gauge(F, F.x, red);
+  }
   if (threadIdx.x == 0) {
     F.status = ST_RUNNING;
     F.phase = PH_INIT;

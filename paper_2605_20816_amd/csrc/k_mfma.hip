@@ -7,9 +7,10 @@
 // bf16 pieces (hi + mid + lo, each the rounding of the remainder) and the six
 // products of total order <= 2 (hh, hm, mh, hl, lh, mm) are accumulated in FP32;
 // the dropped terms are below 2^-26 relative.  The gradient contraction
-// sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies values of size <= 1 and
-// uses two pieces of each operand (hh, hl, lh).  Log-sum-exp in FP32; Phi and
-// grad Phi are summed in FP64 in a fixed order.
+// sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies values of size <= 1: p - delta
+// as one FP16 value (2^-12 relative) against the two FP16 pieces of psi, on
+// v_mfma_f32_32x32x16_f16.  Log-sum-exp in FP32; Phi and grad Phi are summed in
+// FP64 in a fixed order.
 //
 // Operand/accumulator lane layout of the 32x32x16 instruction (lane l, half
 // h = l / 32): A[i][k] at lane i + 32 (k / 8), element k % 8; B[k][j] at lane

@@ -1,5 +1,5 @@
 // pd_warm.h -- device view of one map for the warm-start kernels (descriptors,
-// moment heuristic, training targets, applying a predicted correction) and the
+// moment seed, training targets, warm start from network outputs) and the
 // launchers of the network kernels.
 #pragma once
 
@@ -18,20 +18,20 @@ struct WarmDev {
   int32_t *bbox;           // N x 4 (r0, r1, c0, c1)
   double *frame;           // N x 8 (y1, y2, r, B11, B12, B22, count, 0)
   float *desc;             // N x 32
-  double *theta_h;         // N x K moment heuristic
+  double *theta_h;         // N x K moment seed
   const double *theta_fit; // N x K fitted theta (targets)
-  float *target;           // N x K local-frame targets
-  double *lambda;          // scale of the target alignment (1 value), may be NULL
-  const float *mlp_out;    // N x out_stride network outputs (local frame)
+  float *target;           // N x K normalised targets
+  double *lambda;          // RMS of the centred fitted theta (1 value), may be NULL
+  const float *mlp_out;    // N x out_stride network outputs, or NULL
   int32_t out_stride;
   double *theta_out;       // N x K warm start before scaling
 };
 
 void pd_warm_launch_desc(const WarmDev *W, const int32_t *off, int n_maps, int total_grains,
                          int max_n, hipStream_t s);
-void pd_warm_launch_heuristic(const WarmDev *W, int n_maps, int max_n, hipStream_t s);
+void pd_warm_launch_heuristic(const WarmDev *W, int n_maps, hipStream_t s);
 void pd_warm_launch_targets(const WarmDev *W, int n_maps, hipStream_t s);
-void pd_warm_launch_apply(const WarmDev *W, int n_maps, int max_n, hipStream_t s);
+void pd_warm_launch_apply(const WarmDev *W, int n_maps, hipStream_t s);
 
 // Network of the warm start: 32 -> 256 -> 256 -> kout (GELU after both hidden
 // layers).  Parameters are one FP32 buffer [W1 (32 x 256), b1, W2 (256 x 256), b2,

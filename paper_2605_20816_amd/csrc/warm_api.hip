@@ -1,6 +1,6 @@
 // warm_api.hip -- C ABI of the warm start: descriptors, moment seed, training
-// targets, network forward / backward / Adam, and pd_warm_start (seed + network
-// correction + scale search).
+// targets, network forward / backward / Adam, and pd_warm_start (network or
+// moment seed, then a scale search along the ray).
 #include "pd.h"
 #include "pd_host.h"
 #include "pd_warm.h"
@@ -341,7 +341,7 @@ pd_status pd_heuristic(pd_ctx *ctx, const pd_problem *probs, int32_t n, double *
   for (int p = 0; p < n; ++p) W.maps[p].theta_h = theta_out[p];
   WARM_HIP(ctx, warm_upload(ctx, W, ctx->aux, s));
   launch_desc(W, ctx->aux, s);
-  pd_warm_launch_heuristic((const WarmDev *)(ctx->aux + W.o_maps), n, W.max_n, s);
+  pd_warm_launch_heuristic((const WarmDev *)(ctx->aux + W.o_maps), n, s);
   WARM_HIP(ctx, hipGetLastError());
   return PD_OK;
 }
@@ -363,7 +363,7 @@ pd_status pd_warm_targets(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   Arena L;
   warm_layout(W, L, probs, n);
   DescRegions R;
-  desc_regions(R, L, W, true);
+  desc_regions(R, L, W, false);
   st = reserve_aux(ctx, L.off);
   if (st != PD_OK) return st;
   desc_bind(W, R, ctx->aux);
@@ -375,7 +375,6 @@ pd_status pd_warm_targets(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   WARM_HIP(ctx, warm_upload(ctx, W, ctx->aux, s));
   launch_desc(W, ctx->aux, s);
   const WarmDev *dW = (const WarmDev *)(ctx->aux + W.o_maps);
-  pd_warm_launch_heuristic(dW, n, W.max_n, s);
   pd_warm_launch_targets(dW, n, s);
   WARM_HIP(ctx, hipGetLastError());
   return PD_OK;
@@ -505,14 +504,14 @@ pd_status pd_warm_start(pd_ctx *ctx, const pd_problem *probs, int32_t n, const p
   WARM_HIP(ctx, warm_upload(ctx, W, base, s));
   launch_desc(W, base, s);
   const WarmDev *dW = (const WarmDev *)(base + W.o_maps);
-  pd_warm_launch_heuristic(dW, n, W.max_n, s);
+  pd_warm_launch_heuristic(dW, n, s);
   for (int d = 1; d <= PD_MAX_DEGREE; ++d) {
     if (!rows_deg[d] || !(mlp && mlp->params[d])) continue;
     const int K = (d + 1) * (d + 2) / 2;
     pd_mlp_launch_bf16(mlp->params[d], K, (const float *)(base + o_desc_deg[d]), rows_deg[d],
                        base + o_bf, (float *)(base + o_y_deg[d]), K, s);
   }
-  pd_warm_launch_apply(dW, n, W.max_n, s);
+  pd_warm_launch_apply(dW, n, s);
   WARM_HIP(ctx, hipGetLastError());
 
   // ---- scale search, all maps advanced together (one evaluation per map per round)

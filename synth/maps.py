@@ -59,9 +59,19 @@ def _compact(labels, N):
 
 
 def _argmin_rows(H, W, score_row):
+    """Row by row, the first index of the smallest score (N x W scores per row).
+    Large rows use torch's multi-threaded CPU argmin (same first-index rule)."""
     out = np.empty((H, W), np.int32)
+    try:
+        import torch
+    except ImportError:          # pragma: no cover - torch is part of this image
+        torch = None
     for r in range(H):
-        out[r] = np.argmin(score_row(r), axis=0)
+        S = score_row(r)
+        if torch is not None and S.size >= 1 << 20:
+            out[r] = torch.from_numpy(np.ascontiguousarray(S)).argmin(dim=0).numpy()
+        else:
+            out[r] = np.argmin(S, axis=0)
     return out.reshape(-1)
 
 

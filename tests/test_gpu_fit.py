@@ -138,3 +138,19 @@ def test_bf16_fit_reaches_99(pd, orc):
     assert rep["status"] == "target"
     _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
     assert nc / (gm.H * gm.W) >= 0.99
+
+
+def test_given_start_is_moved_into_the_gauge(pd, orc):
+    """Lemma 4.2: a given start enters the gauge theta_{N-1} = 0 by the common
+    shift -theta_{N-1}, which leaves Phi unchanged (not by zeroing the row)."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    rng = np.random.default_rng(8)
+    th0 = rng.normal(size=(gm.N, 3)) * 0.05
+    th = dev(th0)
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="given", max_iter=0,
+                  target_acc=2.0)[0]
+    x = th.cpu().numpy()
+    assert np.array_equal(x, th0 - th0[-1])
+    phi_ref, _ = orc.objective_grad(th0, gm.labels, gm.H, gm.W, 1, 1e-2)
+    assert abs(rep["phi"] - phi_ref) <= 1e-12 * abs(phi_ref)

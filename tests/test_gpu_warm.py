@@ -71,22 +71,15 @@ def test_targets_match_oracle(pd):
     items = maps_for_warm()
     probs = problems(pdl, items)
     rng = np.random.default_rng(5)
-    fits = []
-    for gm, d, eps in items:
-        fr = warm.grain_frames(gm.labels, gm.H, gm.W, gm.N)
-        th = warm.heuristic_theta(fr, gm.H, gm.W, d)
-        fits.append(2.5 * th + rng.normal(size=th.shape) * 0.1 * np.max(np.abs(th)) + 0.3)
+    fits = [rng.normal(size=(gm.N, pdl.num_features(d))) * 3.0 + 0.7 for gm, d, eps in items]
     tg, lam = ctx.warm_targets(probs, [dev(f) for f in fits])
     lam = lam.cpu().numpy()
     for k, ((gm, d, eps), f) in enumerate(zip(items, fits)):
         fr = warm.grain_frames(gm.labels, gm.H, gm.W, gm.N)
-        th = warm.heuristic_theta(fr, gm.H, gm.W, d)
-        ref, lref = warm.targets(f, th, fr, d)
-        assert abs(lam[k] - lref) <= 1e-10 * abs(lref)
+        ref, rms = warm.targets(f, fr)
+        assert abs(lam[k] - rms) <= 1e-12 * rms
         got = tg[k].cpu().numpy().astype(np.float64)
-        keep = fr[:, 6] > 0
-        scale = np.max(np.abs(ref[keep]))
-        assert np.max(np.abs(got[keep] - ref[keep])) <= 1e-5 * scale
+        assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("batch,K", [(1, 3), (37, 6), (300, 15), (1000, 28)])
@@ -165,22 +158,51 @@ def test_warm_start_heuristic_scale_matches_oracle(pd, orc):
         assert vref > -math.log(gm.N)
 
 
+def test_warm_start_assembles_network_outputs(pd):
+    """theta_hat = BF16 network outputs centred over the non-empty grains, empty
+    grains on the row that wins no pixel; the returned start is s* theta_hat."""
+    pdl, ctx = pd
+    items = [it for it in maps_for_warm() if it[1] <= 6]
+    rng = np.random.default_rng(31)
+    nets = {}
+    for gm, d, eps in items:
+        nets.setdefault(d, dev(warm.mlp_init(pdl.num_features(d), rng) * 0.1))
+    probs = problems(pdl, items)
+    ths, scales = ctx.warm_start(probs, pdl.Mlp(nets), "fp32")
+    desc = ctx.descriptors(probs)
+    for (gm, d, eps), th, s, D in zip(items, ths, scales, desc):
+        fr = warm.grain_frames(gm.labels, gm.H, gm.W, gm.N)
+        y = ctx.mlp_forward(nets[d], D, pdl.num_features(d), "bf16").cpu().numpy()
+        ref = warm.assemble(y.astype(np.float64), fr)
+        got = th.cpu().numpy()
+        if s == 0.0:
+            assert np.all(got == 0)
+        else:
+            assert np.max(np.abs(got / s - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
 def test_warm_start_falls_back_to_zero(pd):
-    """A network whose corrections make every scale worse than theta = 0 leaves
-    the map at the cold start (scale 0)."""
+    """A network that predicts the reverse of a diagram (each grain's score rises
+    towards its own centroid) makes every scale worse than theta = 0: the map falls
+    back to the cold start."""
     pdl, ctx = pd
     gm = synth.config_c1()
     prob = problems(pdl, [(gm, 1, 1e-2)])
     K = 3
-    p = torch.zeros(pdl.mlp_num_params(K), dtype=torch.float32, device="cuda")
-    # output bias: a huge local tilt on every grain (the same polynomial in each
-    # grain's own frame, hence different global functions)
-    p[-K:] = torch.tensor([0.0, 1e6, -1e6])
-    ths, scales = ctx.warm_start(prob, pdl.Mlp({1: p}), "fp64")
-    phi, _ = ctx.objective_grad(prob, ths, "fp64", grad=False)
-    assert float(phi[0]) >= -math.log(gm.N) - 1e-12
-    if scales[0] == 0.0:
-        assert torch.all(ths[0] == 0)
+    p = torch.zeros(pdl.mlp_num_params(K), dtype=torch.float32)
+    o2 = 33 * 256
+    o3 = o2 + 257 * 256
+    p[1 * 256 + 0] = 1.0            # hidden 0 <- mean x1 (centroid)
+    p[2 * 256 + 1] = 1.0            # hidden 1 <- mean x2
+    p[32 * 256 + 0] = 2.0           # biases keep GELU on its increasing branch
+    p[32 * 256 + 1] = 2.0
+    p[o2 + 0 * 256 + 0] = 1.0
+    p[o2 + 1 * 256 + 1] = 1.0
+    p[o3 + 0 * K + 1] = 1.0         # theta_i = (0, +y1, +y2) up to a common shift
+    p[o3 + 1 * K + 2] = 1.0
+    ths, scales = ctx.warm_start(prob, pdl.Mlp({1: p.cuda()}), "fp64")
+    assert scales[0] == 0.0
+    assert torch.all(ths[0] == 0)
 
 
 def test_fit_from_heuristic_and_network(pd, orc):

@@ -481,3 +481,15 @@ def test_polynomial_generator_reconstructs(orc):
     th = synth.coef_to_theta(gm.coef, orc.multi_index(3))
     _, nc, _ = orc.assign(th, gm.H, gm.W, 3, gm.labels)
     assert nc >= gm.H * gm.W - 3
+
+
+def test_oracle_fit_start_keeps_phi_under_gauge_shift(orc):
+    """Lemma 4.2: the oracle fit moves a given start into the gauge theta_{N-1} = 0
+    by a common shift, so its starting Phi equals Phi of the given theta."""
+    gm = synth.config_c1()
+    rng = np.random.default_rng(8)
+    th0 = rng.normal(size=(gm.N, 3)) * 0.05
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, 1, 1e-2)
+    r = orc.lbfgs_fit(obj, th0, max_iter=0)
+    assert np.array_equal(r["theta"], th0 - th0[-1])
+    assert abs(r["phi"] - obj(th0)[0]) <= 1e-12 * abs(obj(th0)[0])

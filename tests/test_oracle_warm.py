@@ -23,42 +23,12 @@ def leg_eval_2d(coef, d, X1, X2):
     return out
 
 
-@pytest.mark.parametrize("d", [1, 2, 4, 6])
-def test_change_frame_is_substitution(d):
-    """Section 3.3: a Legendre series in (al x + be) re-expanded in P(x) takes the
-    same values at every point (a dropped binomial term or a transposed index
-    fails at random points)."""
-    rng = np.random.default_rng(d)
-    K = (d + 1) * (d + 2) // 2
-    c = rng.normal(size=K)
-    al1, be1, al2, be2 = 0.7, -0.3, 1.9, 0.45
-    out = warm.change_frame(c, d, al1, be1, al2, be2)
-    X1, X2 = rng.uniform(-1.5, 1.5, size=(2, 200))
-    ref = leg_eval_2d(c, d, al1 * X1 + be1, al2 * X2 + be2)
-    got = leg_eval_2d(out, d, X1, X2)
-    assert np.max(np.abs(got - ref)) <= 1e-11 * (1 + np.max(np.abs(ref)))
-
-
-def test_local_global_round_trip():
-    rng = np.random.default_rng(7)
-    d = 6
-    c = rng.normal(size=28)
-    fr = np.array([0.31, -0.42, 0.07, 0, 0, 0, 10, 0])
-    back = warm.to_global(warm.to_local(c, fr, d), fr, d)
-    assert np.max(np.abs(back - c)) <= 1e-9 * np.max(np.abs(c)) * (1 / 0.07) ** 6 * 1e-3 + 1e-12
-    # local coefficients evaluate to the same function at x = y' + r u
-    loc = warm.to_local(c, fr, d)
-    U1, U2 = rng.uniform(-1, 1, size=(2, 50))
-    ref = leg_eval_2d(c, d, fr[0] + fr[2] * U1, fr[1] + fr[2] * U2)
-    assert np.max(np.abs(leg_eval_2d(loc, d, U1, U2) - ref)) <= 1e-10 * (1 + np.max(np.abs(ref)))
-
-
 def test_rectangle_frame_closed_form():
     """A rectangular grain of w x h pixels: centroid at its middle, B' =
     diag((w^2 - 1)/12 (2/W)^2, (h^2 - 1)/12 (2/H)^2) (discrete uniform variance)."""
     H, W = 20, 30
     lab = np.ones((H, W), np.int32)
-    r0, r1, c0, c1 = 3, 9, 5, 17     # 7 rows x 13 columns
+    r0, r1, c0, c1 = 3, 9, 5, 17     # 7 rows x 13 columns, off-centre
     lab[r0:r1 + 1, c0:c1 + 1] = 0
     fr = warm.grain_frames(lab.reshape(-1), H, W, 2)
     w, h = c1 - c0 + 1, r1 - r0 + 1
@@ -73,12 +43,29 @@ def test_rectangle_frame_closed_form():
     assert fr[0, 2] == pytest.approx(2 * math.sqrt(fr[0, 3]), rel=1e-13)   # wider than tall
     D = warm.descriptors(lab.reshape(-1), H, W, 2, fr)
     assert D[0, 0] == pytest.approx(math.log(w * h * 2 / (H * W)), rel=1e-14)
-    # symmetric grain: every moment with an odd exponent vanishes
+    # the degree-1 moments are the centroid; N B' follows the closed form
+    assert D[0, 1] == pytest.approx(y1, abs=1e-14) and D[0, 2] == pytest.approx(y2, abs=1e-14)
+    assert D[0, 28] == pytest.approx(2 * (w * w - 1) / 12 * (2 / W) ** 2, rel=1e-13)
+    assert D[0, 31] == pytest.approx(math.log(2) / 10)
+
+
+def test_centred_rectangle_odd_moments_vanish():
+    """A grain symmetric about the domain centre: pixel centres come in exact
+    +-x pairs, so every Legendre moment with an odd exponent is zero, and the
+    even ones equal the product of the 1-D means (separable grain)."""
+    H, W = 24, 30
+    lab = np.ones((H, W), np.int32)
+    lab[5:19, 8:22] = 0              # rows 5..18, columns 8..21: centred
+    D = warm.descriptors(lab.reshape(-1), H, W, 2)
     pairs = [p for p in warm._graded(6) if p != (0, 0)]
+    x1 = (2 * np.arange(8, 22) + 1 - W) / W
+    x2 = (2 * np.arange(5, 19) + 1 - H) / H
     for q, (a, b) in enumerate(pairs):
         if a % 2 or b % 2:
-            assert abs(D[0, 4 + q]) <= 1e-14
-    assert D[0, 31] == pytest.approx(math.log(2) / 10)
+            assert abs(D[0, 1 + q]) <= 1e-15
+        else:
+            ref = np.mean(npleg.legval(x1, np.eye(a + 1)[a])) * np.mean(npleg.legval(x2, np.eye(b + 1)[b]))
+            assert D[0, 1 + q] == pytest.approx(ref, rel=1e-12, abs=1e-15)
 
 
 def test_empty_grain_descriptor_is_zero():
@@ -88,7 +75,11 @@ def test_empty_grain_descriptor_is_zero():
     fr = warm.grain_frames(lab, H, W, 3)
     assert fr[1].tolist() == [0, 0, 1, 0, 0, 0, 0, 0]
     assert np.all(warm.descriptors(lab, H, W, 3, fr)[1] == 0)
-    assert np.all(warm.heuristic_theta(fr, H, W, 2)[1] == 0)
+    th = warm.heuristic_theta(fr, H, W, 2)
+    assert np.all(th[1, 1:] == 0) and th[1, 0] == 1 + np.max(np.abs(th[[0, 2]]).sum(1))
+    # the empty grain wins no pixel
+    F, _, _ = oracle.assign(th, H, W, 2)
+    assert not np.any(F == 1)
 
 
 @pytest.mark.parametrize("d", [1, 2, 3])
@@ -138,30 +129,23 @@ def test_heuristic_disk_weight_is_squared_radius():
     assert q[2] == pytest.approx(4.0, rel=3e-3)
 
 
-def test_targets_recover_affine_image():
-    """If theta_fit = lam (theta' + local-frame residual) + g, the targets return
-    exactly that residual and lam (least squares with a common shift)."""
+def test_targets_are_gauge_and_scale_free():
+    """Targets of a * theta + g (a > 0, g a common row) equal those of theta
+    (Lemma 4.2: a common shift leaves the diagram; the scale is free), have zero
+    mean and unit root mean square; assembling them back gives theta up to
+    that shift and scale."""
     rng = np.random.default_rng(3)
     gm = synth.polynomial_diagram(32, 32, 6, 3, rng)
-    d = 3
     fr = warm.grain_frames(gm.labels, gm.H, gm.W, gm.N)
-    th = warm.heuristic_theta(fr, gm.H, gm.W, d)
-    loc = rng.normal(size=th.shape) * 1e-3
-    glob = np.array([warm.to_global(loc[i], fr[i], d) for i in range(gm.N)])
-    # a common shift of the residual is a gauge (absorbed into g), and a component
-    # along the centred seed is absorbed into lam: keep the residual free of both
-    glob -= glob.mean(0)
-    b = th - th.mean(0)
-    glob -= (np.sum(glob * b) / np.sum(b * b)) * b
-    loc = np.array([warm.to_local(glob[i], fr[i], d) for i in range(gm.N)])
-    lam, g = 3.7, rng.normal(size=th.shape[1])
-    fit = lam * (th + glob) + g
-    tg, lam2 = warm.targets(fit, th, fr, d)
-    assert lam2 == pytest.approx(lam, rel=1e-9)
-    assert np.max(np.abs(tg - loc)) <= 1e-7 * np.max(np.abs(loc)) + 1e-12
-    # apply_correction inverts it
-    hat = warm.apply_correction(th, tg, fr, d)
-    assert np.max(np.abs(hat - (th + glob))) <= 1e-7 * np.max(np.abs(th))
+    th = rng.normal(size=(gm.N, 10))
+    t1, r1 = warm.targets(th, fr)
+    t2, r2 = warm.targets(3.7 * th + rng.normal(size=10), fr)
+    assert np.max(np.abs(t1 - t2)) <= 1e-12
+    assert r2 == pytest.approx(3.7 * r1, rel=1e-12)
+    assert np.max(np.abs(t1.mean(0))) <= 1e-14
+    assert np.sqrt(np.mean(t1 ** 2)) == pytest.approx(1.0, rel=1e-12)
+    back = warm.assemble(t1 * r1, fr)
+    assert np.max(np.abs(back - (th - th.mean(0)))) <= 1e-12 * np.max(np.abs(th))
 
 
 def test_mlp_gradient_matches_finite_differences():
