@@ -65,7 +65,9 @@ def traffic_from_profile(kernel: str):
 
 def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
     """Plain (FP64, theta = 0, history 10, one map per call) against accelerated
-    (one batched call, history 32) fits of c4-style maps to 99% pixel accuracy."""
+    (one batched call, history 32; reduced precision; optionally the diagonal
+    preconditioner and the learned warm start) fits of c4-style maps to 99% pixel
+    accuracy."""
     from paper_2605_20816_amd import warm_train as wt
     maps = [synth.config_c4_map(j) for j in range(n_maps)]
     probs = [pdl.Problem(torch.as_tensor(g.labels).cuda(), g.H, g.W, g.N, g.meta["degree"],
@@ -100,12 +102,15 @@ def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
                        f"N 20..500, d 2..4, eps 1e-2 (d=2) / 1e-3",
            "plain": "FP64, theta0=0, L-BFGS memory 10, one map per pd_fit call",
            "target_acc": 0.99, "budget_iters": 2000}
-    variants = [("accelerated_fp32", "fp32", "zero", None), ("accelerated_bf16", "bf16", "zero", None)]
+    variants = [("accelerated_fp32", "fp32", "zero", None, 0),
+                ("accelerated_fp32_precond", "fp32", "zero", None, 10),
+                ("accelerated_bf16", "bf16", "zero", None, 0)]
     if with_net:
-        variants.append(("accelerated_bf16_mlp", "bf16", "mlp", pdl.Mlp(nets)))
-    for name, prec, init, mlp in variants:
+        variants.append(("accelerated_bf16_mlp", "bf16", "mlp", pdl.Mlp(nets), 0))
+        variants.append(("accelerated_fp32_precond_mlp", "fp32", "mlp", pdl.Mlp(nets), 10))
+    for name, prec, init, mlp, pre in variants:
         reps = ctx.fit(probs, zeros(probs), prec, init=init, mlp=mlp, history=32, max_iter=2000,
-                       target_acc=0.99)
+                       target_acc=0.99, precondition=pre)
         both = [k for k in range(n_maps) if plain[k] > 0 and reps[k]["seconds_to_target"] > 0]
         t_plain = sum(plain[k] for k in both)
         t_acc = max(reps[k]["seconds_to_target"] for k in both) if both else None

@@ -122,6 +122,15 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs /*host*/, int32
                             double *const *grad_out /*host*/, pd_precision prec,
                             void *stream);
 
+/* Diagonal of the Hessian of -Phi (eq. hess of Proposition 4.4):
+ * diag_out[p][i*K + k] = (1 / (eps^2 n)) sum_x p_i(x) (1 - p_i(x)) psi_k(x)^2 >= 0,
+ * the preconditioner of pd_fit.  theta: host array of DEVICE N_p x K_p FP64;
+ * diag_out: host array of DEVICE N_p x K_p FP64.  PD_FP64 or PD_FP32 arithmetic
+ * (PD_BF16: PD_ERR_UNSUPPORTED).  Stream-ordered. */
+pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                          const double *const *theta /*host*/, double *const *diag_out /*host*/,
+                          pd_precision prec, void *stream);
+
 /* Hard assignment F_theta (Section 2.1, smallest index on ties) in FP64 with the
  * canonical score order f = theta_i0, f = fma(theta_ik, psi_k, f), k = 1..K-1,
  * so labels are bit-reproducible.  labels_out (host array; entries may be NULL)
@@ -247,6 +256,12 @@ typedef struct {
   double gtol;            /* stop at ||grad||_inf <= gtol (0 disables)           */
   int32_t check_every;    /* accuracy / stop-flag poll period in iterations      */
   const struct pd_mlp *mlp; /* PD_INIT_MLP: the networks (see pd_warm_start)    */
+  int32_t precondition;   /* 0: H0 = gamma I.  T > 0: H0 = gamma Dinv with
+                             Dinv = diag(1 / (D + 1e-6 max D)), D the Hessian
+                             diagonal of pd_hessian_diag taken at the start and at
+                             every T-th accepted iterate, gamma = s.y / y.Dinv y of
+                             the newest pair, every search starting at t = 1.
+                             Gauge PD_GAUGE_LAST_ZERO, PD_FP64 or PD_FP32.         */
 } pd_fit_opts;
 
 typedef struct {

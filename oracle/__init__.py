@@ -200,6 +200,15 @@ def hessian(theta, labels, H, W, d, eps):
     return -Hm.reshape(N * K, N * K) / (eps * eps * n)
 
 
+def hessian_diag(theta, labels, H, W, d, eps):
+    """Diagonal of the Hessian of -Phi (eq. hess): D_ik = (1/(eps^2 n))
+    sum_x p_i(x) (1 - p_i(x)) psi_k(x)^2, N x K (dense probabilities: small maps)."""
+    th = _theta(theta, d)
+    X = features(H, W, d)
+    P = softmax_probs(th, H, W, d, eps)
+    return ((P * (1.0 - P)) @ (X * X).T) / (eps * eps * H * W)
+
+
 def gauge_project(v, mode: str):
     """Remark 4.3: 'last' zeroes the reference grain N-1; 'centered' removes the
     common-shift component; 'none' leaves v unchanged."""

@@ -108,10 +108,17 @@ def _line_search(evalf, x, f0, g0, d, t1):
 
 
 def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=2000,
-              history=10, gauge="last", gtol=0.0, callback=None):
+              history=10, gauge="last", gtol=0.0, callback=None, precondition=None,
+              diag_every=10, diag_floor=1e-6):
     """Maximise Phi (minimise f = -Phi) from theta0.
 
     objective(theta) -> (Phi, grad Phi);  accuracy(theta) -> Acc in [0, 1] or None.
+    precondition(theta) -> the diagonal of the Hessian of -Phi (N x K, eq. hess):
+    if given, the initial inverse Hessian of the two-loop recursion is
+    gamma * diag(1 / (D + diag_floor * max D)) instead of gamma * I, with D taken at
+    the start and at every diag_every-th accepted iterate, gamma = s.y / y.D^-1 y
+    of the newest pair (1 with an empty memory), and every search starts at t = 1
+    (the last grain's row stays 0: gauge "last" only).
     Returns a dict with theta, phi, acc, iters, evals, status and per-iteration
     records (phi, acc, evals, t) for trajectory comparisons.
     """
@@ -131,7 +138,19 @@ def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=200
         phi, g = objective(xx)
         return -phi, gauge_project(-g, gauge)
 
+    if precondition is not None and gauge != "last":
+        raise ValueError("the diagonal preconditioner keeps gauge 'last'")
+    Dinv = None
+
+    def refresh(xx):
+        D = np.asarray(precondition(xx), np.float64)
+        Di = 1.0 / (D + diag_floor * float(np.max(D)))
+        Di[-1, :] = 0.0
+        return Di
+
     f, g = evalf(x)
+    if precondition is not None:
+        Dinv = refresh(x)
     S, Y, R = [], [], []
     gamma = 1.0
     it = 0
@@ -142,24 +161,25 @@ def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=200
         status = "target"
         return dict(theta=x, phi=-f, acc=acc, iters=0, evals=n_evals, status=status,
                     records=records)
-    d = -g
+    steep = (lambda gg: -gg) if Dinv is None else (lambda gg: -Dinv * gg)
+    d = steep(g)
     reset_tried = False
     while it < max_iter:
         gnorm = float(np.sqrt(np.sum(g * g)))
         if gnorm == 0.0 or float(np.max(np.abs(g))) <= gtol:
             status = "gtol"
             break
-        t1 = 1.0 / gnorm if not S else 1.0
+        t1 = 1.0 / gnorm if (not S and Dinv is None) else 1.0
         dphi0 = float(g.ravel() @ d.ravel())
         if not (dphi0 < 0.0):
             S, Y, R = [], [], []
-            d = -g
-            t1 = 1.0 / gnorm
+            d = steep(g)
+            t1 = 1.0 / gnorm if Dinv is None else 1.0
         ok, t, xt, ft, gt, ev = _line_search(evalf, x, f, g, d, t1)
         if not ok:
             if S and not reset_tried:
                 S, Y, R = [], [], []
-                d = -g
+                d = steep(g)
                 reset_tried = True
                 continue
             status = "linesearch"
@@ -168,15 +188,20 @@ def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=200
         s = t * d
         y = gt - g
         sy = float(s.ravel() @ y.ravel())
-        if sy > CURV_EPS * math.sqrt(float(s.ravel() @ s.ravel())) * math.sqrt(float(y.ravel() @ y.ravel())):
+        stored = sy > CURV_EPS * math.sqrt(float(s.ravel() @ s.ravel())) * math.sqrt(float(y.ravel() @ y.ravel()))
+        if stored:
             if len(S) == history:
                 S.pop(0), Y.pop(0), R.pop(0)
             S.append(s)
             Y.append(y)
             R.append(1.0 / sy)
-            gamma = sy / float(y.ravel() @ y.ravel())
         x, f, g = xt, ft, gt
         it += 1
+        if Dinv is not None and it % diag_every == 0:
+            Dinv = refresh(x)
+        if stored:
+            yDy = float(y.ravel() @ y.ravel()) if Dinv is None else float(np.sum(y * Dinv * y))
+            gamma = sy / yDy
         acc = accuracy(x) if accuracy is not None else None
         records.append(dict(phi=-f, acc=acc, evals=ev, t=t))
         if callback is not None:
@@ -191,7 +216,7 @@ def lbfgs_fit(objective, theta0, *, accuracy=None, target_acc=0.99, max_iter=200
             a = rj * float(sj.ravel() @ q.ravel())
             alphas.append(a)
             q = q - a * yj
-        r = (gamma if S else 1.0) * q
+        r = (gamma if S else 1.0) * (q if Dinv is None else Dinv * q)
         for (sj, yj, rj), a in zip(zip(S, Y, R), reversed(alphas)):
             b = rj * float(yj.ravel() @ r.ravel())
             r = r + (a - b) * sj

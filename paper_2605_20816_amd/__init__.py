@@ -48,7 +48,8 @@ class _FitOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("gauge", ctypes.c_int), ("init", ctypes.c_int),
                 ("history", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("target_acc", ctypes.c_double), ("gtol", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("precondition", ctypes.c_int32)]
 
 
 class _Mlp(ctypes.Structure):
@@ -89,6 +90,10 @@ _SIGS = {
     "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "pd_hessian_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                       ctypes.c_void_p]),
     "pd_mlp_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "pd_descriptors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_void_p),
@@ -274,6 +279,16 @@ class Context:
                                             _stream(stream)))
         return phi, grads
 
+    def hessian_diag(self, probs, thetas, prec="fp64", stream=None):
+        """Diagonal of the Hessian of -Phi (N x K float64 per map)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        out = [torch.empty_like(t) for t in thetas]
+        self._check(lib().pd_hessian_diag(self._h, arr, n, _ptrs(thetas), _ptrs(out), PREC[prec],
+                                          _stream(stream)))
+        return out
+
     def assign(self, probs, thetas, labels_out=True, stream=None):
         """F_theta per map and #correct.  Returns ([labels int32 (n,)] or None, counts int64)."""
         n = len(probs)
@@ -312,14 +327,16 @@ class Context:
         return int(best.value)
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
-            max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, stream=None):
+            max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, precondition=0,
+            stream=None):
         """Device L-BFGS fit of every map; thetas are updated in place.
         Returns a list of report dicts."""
         n = len(probs)
         arr = (_Problem * n)(*[p.c() for p in probs])
         h = None if mlp is None else mlp.handle()
         opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
-                        check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p))
+                        check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p),
+                        int(precondition))
         reps = (_FitReport * n)()
         self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
                                  _stream(stream)))

@@ -150,6 +150,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.lse = L.take(mf ? 0 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
+    R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
     R.part_c = L.take(sizeof(int64_t) * M.a_items);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
@@ -193,6 +194,9 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
     M.part_l = (double *)(base + R.part_l);
     M.part_g = (double *)(base + R.part_g);
     M.part_c = (int64_t *)(base + R.part_c);
+    M.part_d = P.with_diag ? (double *)(base + R.part_d) : nullptr;
+    M.diag = nullptr;
+    M.want_diag = nullptr;
     M.theta = theta ? theta[p] : nullptr;
     M.phi = phi_out ? phi_out + p : nullptr;
     M.grad = grad_out ? grad_out[p] : nullptr;
@@ -258,8 +262,8 @@ void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center)
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
   pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-  if (with_grad) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
-  pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, s);
+  if (with_grad) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.with_diag, s);
+  pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, with_grad && P.with_diag, s);
 }
 
 void pd_plan_assign(const EvalPlan &P, hipStream_t s) {
@@ -438,6 +442,51 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_prob
   return PD_OK;
 }
 
+pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                          const double *const *theta, double *const *diag_out,
+                          pd_precision prec, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (code == 2) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "pd_hessian_diag: PD_FP64 or PD_FP32");
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta || !diag_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta and diag_out must be non-NULL");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p] || !diag_out[p])
+      return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta / diag_out entry " + std::to_string(p) + " is NULL");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  P.with_diag = true;
+  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
+  pd_plan_layout(P, L, probs, n_probs, code);
+  std::vector<size_t> o_g(n_probs);
+  for (int p = 0; p < n_probs; ++p) o_g[p] = L.take(sizeof(double) * P.maps[p].N * P.maps[p].K);
+  const size_t o_phi = L.take(sizeof(double) * n_probs);
+  const size_t o_flag = L.take(sizeof(int32_t));
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  std::vector<double *> g(n_probs);
+  for (int p = 0; p < n_probs; ++p) g[p] = (double *)(ctx->ws + o_g[p]);
+  pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), g.data(), nullptr, nullptr);
+  int32_t *flag = (int32_t *)(ctx->ws + o_flag);
+  for (int p = 0; p < n_probs; ++p) {
+    P.maps[p].diag = diag_out[p];
+    P.maps[p].want_diag = flag;
+  }
+  PD_HIP(ctx, hipMemsetD32Async((hipDeviceptr_t)flag, 1, 1, s));
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  pd_plan_tables(P, s);
+  pd_plan_eval(P, true, s, true);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
 pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
                     const double *const *theta, int32_t *const *labels_out,
                     int64_t *n_correct_out, void *stream) {
@@ -516,12 +565,12 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     PD_HIP(ctx, hipEventRecord(ev[3], s));
     for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
     PD_HIP(ctx, hipEventRecord(ev[4], s));
-    for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], s);
+    for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], false, s);
     PD_HIP(ctx, hipEventRecord(ev[5], s));
   }
   for (int r = 0; r < reps; ++r) {
     if (code == 2) pd_bf16_launch(P, 3, s);
-    else pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, s);
+    else pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, false, s);
   }
   PD_HIP(ctx, hipEventRecord(ev[6], s));
   PD_HIP(ctx, hipGetLastError());

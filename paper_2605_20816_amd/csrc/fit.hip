@@ -49,6 +49,13 @@ struct FitDev {
   double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
   double cscale;     // -log2(e) / eps
   int32_t *active, *assign_pending;
+  // diagonal preconditioner (precond = refresh period T, 0 = off): Dinv =
+  // 1 / (diag + floor max diag) from the evaluation's Hessian diagonal
+  int32_t precond;
+  int32_t *want_diag;   // read by the gradient kernels: compute diag this evaluation
+  const double *diag;
+  double *Dinv;
+  double diag_floor;
   // state
   int32_t status, phase, iters, evals, ls_evals, hist_len, hist_head, reset_tried;
   double f, t, f0, dphi0, gamma, acc, gg, gmax;
@@ -177,13 +184,14 @@ __device__ void pass_gstats(FitDev &F, double *red) {
   __syncthreads();
 }
 
-// d = -g and its slope g.d (steepest descent restart).
+// d = -H0 g (H0 = I, or the diagonal preconditioner) and its slope g.d.
 __device__ void set_steepest(FitDev &F, double *red) {
   double v[1] = {0.0};
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = F.g[i];
-    F.d[i] = -gi;
-    v[0] = __builtin_fma(gi, -gi, v[0]);
+    const double di = F.precond ? -F.Dinv[i] * gi : -gi;
+    F.d[i] = di;
+    v[0] = __builtin_fma(gi, di, v[0]);
   }
   blk_sums<1>(v, red);
   if (threadIdx.x == 0) F.dphi0 = v[0];
@@ -197,10 +205,10 @@ __device__ void start_ls(FitDev &F, double *red) {
   __syncthreads();
   if (F.status != ST_RUNNING) return;
   const double gnorm = sqrt(F.gg);
-  double t1 = F.hist_len == 0 ? 1.0 / gnorm : 1.0;
+  double t1 = (F.hist_len == 0 && !F.precond) ? 1.0 / gnorm : 1.0;
   if (!(F.dphi0 < 0.0)) {
     set_steepest(F, red);
-    t1 = 1.0 / gnorm;
+    t1 = F.precond ? 1.0 : 1.0 / gnorm;
     if (threadIdx.x == 0) F.hist_len = 0;
   }
   if (threadIdx.x == 0) {
@@ -213,6 +221,50 @@ __device__ void start_ls(FitDev &F, double *red) {
     F.phase = PH_BRACKET;
   }
   __syncthreads();
+}
+
+// Dinv = 1 / (diag + floor * max diag) from the last evaluation; the gauge row of
+// grain N-1 stays 0.
+__device__ void refresh_dinv(FitDev &F, double *red) {
+  double mx = 0.0;
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) mx = fmax(mx, F.diag[i]);
+  mx = blk_max(mx, red);
+  const double fl = F.diag_floor * mx;
+  const int last = (F.N - 1) * F.K;
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt)
+    F.Dinv[i] = (F.gauge == 0 && i >= last) ? 0.0 : 1.0 / (F.diag[i] + fl);
+  __syncthreads();
+}
+
+// gYY[j][k] = y_j . Dinv y_k for every pair of the L live slots: row a against
+// up to 16 columns b >= a per pass.
+__device__ void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *red) {
+  const int M1 = F.m + 1;
+  const int n = F.NK;
+  const double *__restrict__ pY = F.Y;
+  for (int a = 0; a < L; ++a) {
+    const int ja = slot[a];
+    for (int b0 = a; b0 < L; b0 += 16) {
+      int jb[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) jb[u] = slot[min(b0 + u, L - 1)];
+      double acc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
+        const double ya = pY[(size_t)ja * n + e] * F.Dinv[e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[u] = __builtin_fma(ya, pY[(size_t)jb[u] * n + e], acc[u]);
+      }
+      blk_sums<16>(acc, red);
+      if (threadIdx.x == 0)
+        for (int u = 0; u < 16 && b0 + u < L; ++u) {
+          gYY[ja * M1 + jb[u]] = acc[u];
+          gYY[jb[u] * M1 + ja] = acc[u];
+        }
+      __syncthreads();
+    }
+  }
 }
 
 // Accept the trial point (xt, graw = gradient of f, ft); update the memory and
@@ -261,7 +313,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
       F.rho[put] = 1.0 / sy;
       if (F.hist_len < m) F.hist_len++;
       else F.hist_head = (F.hist_head + 1) % M1;
-      F.gamma = sy / yy;
+      if (!F.precond) F.gamma = sy / yy;
     }
     F.reset_tried = 0;
     F.f = ft;
@@ -277,6 +329,8 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
     return;
   }
   if (threadIdx.x == 0 && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
+  const bool refresh = F.precond > 0 && (F.iters % F.precond) == 0;
+  if (refresh) refresh_dinv(F, red);
   const int L = F.hist_len, head = F.hist_head;
   // slot of the k-th live pair (oldest first), kept in LDS
   int *slot = (int *)ja;
@@ -306,15 +360,18 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
       for (int u = 0; u < 8; ++u) js[u] = slot[min(k0 + u, L - 1)];
       for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
         const double gi = pg[e], si = pns[e], yi = pny[e];
+        // Y^T g and Y^T y_new in the metric of H0 (Dinv, or the identity)
+        const double w = F.precond ? F.Dinv[e] : 1.0;
+        const double gw = F.precond ? gi * w : gi, yw = F.precond ? yi * w : yi;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const double Sj = pS[(size_t)js[u] * n + e];
           const double Yj = pY[(size_t)js[u] * n + e];
           acc[u] = __builtin_fma(Sj, gi, acc[u]);
-          acc[8 + u] = __builtin_fma(Yj, gi, acc[8 + u]);
+          acc[8 + u] = __builtin_fma(Yj, gw, acc[8 + u]);
           acc[16 + u] = __builtin_fma(si, Yj, acc[16 + u]);
           acc[24 + u] = __builtin_fma(Sj, yi, acc[24 + u]);
-          acc[32 + u] = __builtin_fma(yi, Yj, acc[32 + u]);
+          acc[32 + u] = __builtin_fma(yw, Yj, acc[32 + u]);
         }
       }
       blk_sums<40>(acc, red);
@@ -334,6 +391,9 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
       __syncthreads();
     }
   }
+  if (refresh) gram_yy(F, slot, L, gYY, red);
+  if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
+  __syncthreads();
   FIT_STAMP(F, 8);
   // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0:
   // lane k holds alpha and beta of the k-th pair; each step is one DPP sum.
@@ -369,7 +429,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   }
   __syncthreads();
   FIT_STAMP(F, 9);
-  if (stored)
+  if (stored || refresh)
     for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
       F.SY[e] = gSY[e];
       F.YY[e] = gYY[e];
@@ -384,7 +444,8 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   double *__restrict__ pdir = F.d;
   for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = pg[i];
-    double di = cg * gi;
+    // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
+    double dy = cg * gi, ds = 0.0;
     // slots in blocks of 8: the 16 loads of a block are issued before use
     for (int k0 = 0; k0 < L; k0 += 8) {
       double yv[8], sv[8];
@@ -397,10 +458,11 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (k0 + u < L) {
-          di = __builtin_fma(coef[k0 + u], yv[u], di);
-          di = __builtin_fma(coef[M1 + k0 + u], sv[u], di);
+          dy = __builtin_fma(coef[k0 + u], yv[u], dy);
+          ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
         }
     }
+    const double di = F.precond ? __builtin_fma(F.Dinv[i], dy, ds) : dy + ds;
     pdir[i] = di;
     v[0] = __builtin_fma(gi, gi, v[0]);
     v[1] = __builtin_fma(gi, di, v[1]);
@@ -413,6 +475,8 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
     F.dphi0 = v[1];
     F.gmax = mx;
   }
+  if (threadIdx.x == 0 && F.precond)
+    *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
   __syncthreads();
   FIT_STAMP(F, 10);
   start_ls(F, red);
@@ -487,11 +551,13 @@ __device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, do
   const double ft = -*F.phi_t;
   if (threadIdx.x == 0) F.evals++;
   if (F.phase == PH_INIT) {
+    if (F.precond) refresh_dinv(F, red);
     for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
       F.g[i] = F.graw[i];
-      F.d[i] = -F.graw[i];
+      F.d[i] = F.precond ? -F.Dinv[i] * F.graw[i] : -F.graw[i];
     }
     __syncthreads();
+    if (threadIdx.x == 0 && F.precond) *F.want_diag = (1 % F.precond) == 0 ? 1 : 0;
     if (threadIdx.x == 0) {
       F.f = ft;
       if (!isfinite(ft)) {
@@ -653,6 +719,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     F.clk_target = 0;
     *F.active = 1;
     *F.assign_pending = 0;
+    if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
   }
 }
 
@@ -711,6 +778,11 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (prec == 2)
     for (int p = 0; p < n; ++p)
       if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
+  if (opts->precondition < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "precondition must be >= 0");
+  if (opts->precondition > 0 && prec == 2)
+    return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the diagonal preconditioner needs PD_FP64 or PD_FP32");
+  if (opts->precondition > 0 && opts->gauge != PD_GAUGE_LAST_ZERO)
+    return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the diagonal preconditioner keeps PD_GAUGE_LAST_ZERO");
   pd_status st = pd_validate(ctx, probs, n, stream);
   if (st != PD_OK) return st;
   if (opts->init == PD_INIT_MLP || opts->init == PD_INIT_HEURISTIC) {
@@ -731,16 +803,17 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   EvalPlan P;
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
+  P.with_diag = opts->precondition > 0;
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);
   for (int p = 0; p < n; ++p) {
     const size_t NK = (size_t)P.maps[p].N * P.maps[p].K;
-    o_vec[p] = L.take(sizeof(double) * (5 * NK + 2 * (size_t)(m + 1) * NK + (size_t)(m + 1) +
+    o_vec[p] = L.take(sizeof(double) * (7 * NK + 2 * (size_t)(m + 1) * NK + (size_t)(m + 1) +
                                         2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)));
   }
   const size_t o_F = L.take(sizeof(FitDev) * n);
-  const size_t o_flags = L.take(sizeof(int32_t) * 2 * n);
+  const size_t o_flags = L.take(sizeof(int32_t) * 3 * n);
   const size_t o_phi = L.take(sizeof(double) * n);
   const size_t o_nc = L.take(sizeof(int64_t) * n);
   const size_t o_amaps = L.take(sizeof(MapDev) * n);
@@ -781,6 +854,11 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.YY = f.SY + (size_t)(m + 1) * (m + 1);
     f.Sg = f.YY + (size_t)(m + 1) * (m + 1);
     f.Yg = f.Sg + (m + 1);
+    f.Dinv = f.Yg + (m + 1);
+    f.diag = f.Dinv + NK;
+    f.precond = opts->precondition;
+    f.want_diag = flags + 2 * n + p;
+    f.diag_floor = 1e-6;
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
     f.n_correct = nc + p;
@@ -792,6 +870,11 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   pd_plan_bind(P, base, xt.data(), phi_t, graw.data(), nullptr, nullptr);
   for (int p = 0; p < n; ++p) F[p].thc = P.maps[p].thc;
   for (int p = 0; p < n; ++p) P.maps[p].gate = flags + p;
+  if (opts->precondition > 0)
+    for (int p = 0; p < n; ++p) {
+      P.maps[p].diag = (double *)F[p].diag;
+      P.maps[p].want_diag = F[p].want_diag;
+    }
   // assignment view of the same maps: theta = x, gate = assign_pending
   std::vector<MapDev> amaps = P.maps;
   for (int p = 0; p < n; ++p) {

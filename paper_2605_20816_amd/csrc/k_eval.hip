@@ -237,10 +237,11 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
 // lse, label) arrives in a few wide scalar loads per chunk; the one-hot term
 // (delta_{i,G(x)}) is applied only when a label of the chunk falls in this
 // wave's grain group, tested on the scalar unit.
-template <typename T, int D, int CH>
+// With DIAG, also w = p (1 - p) times P_a(x1)^2 per lane (Hessian diagonal).
+template <typename T, int D, int CH, bool DIAG>
 __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *lp,
                                  const PD_AS_CONST int32_t *gp, const T (&cf)[D + 1],
-                                 T (&racc)[D + 1], int gbase, int lane) {
+                                 T (&racc)[D + 1], T (&dacc)[D + 1], int gbase, int lane) {
   constexpr int DP = D + 1;
   T px[CH][DP];
   T l[CH];
@@ -264,6 +265,12 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
     racc[0] += p;
 #pragma unroll
     for (int a = 1; a < DP; ++a) racc[a] = pd_fma(p, px[j][a], racc[a]);
+    if (DIAG) {
+      const T w = pd_fma(-p, p, p);
+      dacc[0] += w;
+#pragma unroll
+      for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(w, px[j][a] * px[j][a], dacc[a]);
+    }
   }
   if (hit) {
 #pragma unroll
@@ -279,7 +286,7 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
   }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool DIAG>
 __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
@@ -292,39 +299,48 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   const int c0 = tcol * M.tile_cols, c1 = min(c0 + M.tile_cols, M.W);
   const int gbase = grp * PD_WAVE;
   const int i = gbase + lane;
-  double q[K];
+  double q[K], qd[DIAG ? K : 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) q[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
   const auto txT = pd_uni((const T *)M.txT);
   for (int r = r0; r < r1; ++r) {
     const auto cp = pd_glb((const T *)M.C + ((size_t)r * M.Npad + i) * DP);
     T cf[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) cf[a] = cp[a];
-    T racc[DP];
+    T racc[DP], dacc[DP];
 #pragma unroll
-    for (int a = 0; a < DP; ++a) racc[a] = (T)0;
+    for (int a = 0; a < DP; ++a) racc[a] = dacc[a] = (T)0;
     const auto lrow = pd_uni((const T *)M.lse + (size_t)r * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
     int c = c0;
     for (; c + CH <= c1; c += CH)
-      grad_cols<T, D, CH>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, gbase, lane);
+      grad_cols<T, D, CH, DIAG>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
     for (; c < c1; ++c)
-      grad_cols<T, D, 1>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, gbase, lane);
+      grad_cols<T, D, 1, DIAG>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
       const double ra = (double)racc[a];
+      const double da = (double)dacc[a];
 #pragma unroll
       for (int b = 0; a + b <= D; ++b) {
         const int k = pd_alpha_index(a, b);
         q[k] = __builtin_fma(ra, ty[b], q[k]);
+        if (DIAG) qd[k] = __builtin_fma(da, ty[b] * ty[b], qd[k]);
       }
     }
   }
   const auto out = pd_glb(M.part_g + ((size_t)tile * M.Npad + i) * K);
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = q[k];
+  if (DIAG) {
+    const auto outd = pd_glb(M.part_d + ((size_t)tile * M.Npad + i) * K);
+#pragma unroll
+    for (int k = 0; k < K; ++k) outd[k] = qd[k];
+  }
 }
 
 template <typename T, int DMAX>
@@ -338,7 +354,27 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ ma
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D>(M, item - off[m], lane)));
+  // evaluations that also want the Hessian diagonal go to k_grad_diag
+  if (M.want_diag != nullptr && *pd_uni(M.want_diag) != 0) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, false>(M, item - off[m], lane)));
+}
+
+// The same work list, for maps whose want_diag is set: gradient partials plus
+// the partials of sum_x p (1 - p) psi^2 (a separate kernel, so the extra
+// accumulators do not raise k_grad's register count).
+template <typename T, int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_grad_diag(const MapDev *__restrict__ maps,
+                                                        const int32_t *__restrict__ off,
+                                                        int n_maps, int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  if (M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true>(M, item - off[m], lane)));
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +398,8 @@ __device__ inline void reduce_phi_block(const MapDev &M) {
 // are added by a fixed tree.
 #define RG_OUT 16
 #define RG_PH 16
-__device__ inline void reduce_grad_block(const MapDev &M, int chunk) {
+__device__ inline void reduce_grad_block(const MapDev &M, int chunk, const double *part,
+                                         double *dst, double scale) {
   __shared__ double red[RG_PH][RG_OUT + 1];
   const int ol = threadIdx.x % RG_OUT, ph = threadIdx.x / RG_OUT;
   const int o = chunk * RG_OUT + ol;
@@ -371,7 +408,7 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk) {
   double s = 0.0;
   if (o < NK) {
     const int i = o / M.K, k = o - i * M.K;
-    const auto src = pd_glb(M.part_g + (size_t)i * M.K + k);
+    const auto src = pd_glb(part + (size_t)i * M.K + k);
     const size_t stride = (size_t)M.Npad * M.K;
     int t = ph;
     for (; t + 3 * RG_PH < tiles; t += 4 * RG_PH) {
@@ -392,14 +429,15 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk) {
     if (ph < w) red[ph][ol] += red[ph + w][ol];
     __syncthreads();
   }
-  if (ph == 0 && o < NK) M.grad[o] = red[0][ol] * M.grad_scale;
+  if (ph == 0 && o < NK) dst[o] = red[0][ol] * scale;
 }
 
-// One launch for both reductions: blocks [0, n_maps) reduce Phi of map b;
-// the following blocks reduce gradient chunks (offsets in off, n_maps + 1).
+// One launch for all reductions: blocks [0, n_maps) reduce Phi of map b; the
+// next off[n_maps] blocks reduce gradient chunks; with with_diag, as many more
+// reduce the Hessian-diagonal chunks of maps whose want_diag is set.
 __global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
-                                                     int with_grad) {
+                                                     int with_grad, int with_diag) {
   if ((int)blockIdx.x < n_maps) {
     const MapDev &M = maps[blockIdx.x];
     if (PD_GATED(M)) return;
@@ -407,11 +445,21 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ 
     return;
   }
   if (!with_grad) return;
-  const int b = blockIdx.x - n_maps;
+  int b = blockIdx.x - n_maps;
+  const bool diag = b >= off[n_maps];
+  if (diag) {
+    if (!with_diag) return;
+    b -= off[n_maps];
+  }
   const int m = pd_find_map(off, n_maps, b);
   const MapDev &M = maps[m];
   if (M.grad == nullptr || PD_GATED(M)) return;
-  reduce_grad_block(M, b - off[m]);
+  if (!diag) {
+    reduce_grad_block(M, b - off[m], M.part_g, M.grad, M.grad_scale);
+  } else {
+    if (M.diag == nullptr || M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
+    reduce_grad_block(M, b - off[m], M.part_d, M.diag, M.grad_scale / M.eps);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -481,14 +529,19 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
   else { PD_LAUNCH_BY_DMAX(k_lse, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                    int total, hipStream_t s) {
+                    int total, bool diag, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
   if (prec == 0) { PD_LAUNCH_BY_DMAX(k_grad, double, dmax, blocks, s, maps, off, n_maps, total); }
   else { PD_LAUNCH_BY_DMAX(k_grad, float, dmax, blocks, s, maps, off, n_maps, total); }
+  if (diag) {
+    if (prec == 0) { PD_LAUNCH_BY_DMAX(k_grad_diag, double, dmax, blocks, s, maps, off, n_maps, total); }
+    else { PD_LAUNCH_BY_DMAX(k_grad_diag, float, dmax, blocks, s, maps, off, n_maps, total); }
+  }
 }
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
-                      bool grad, hipStream_t s) {
-  k_reduce<<<n_maps + (grad ? blocks_r : 0), PD_BLOCK, 0, s>>>(maps, off_r, n_maps, grad ? 1 : 0);
+                      bool grad, bool diag, hipStream_t s) {
+  const int blocks = n_maps + (grad ? blocks_r * (diag ? 2 : 1) : 0);
+  k_reduce<<<blocks, PD_BLOCK, 0, s>>>(maps, off_r, n_maps, grad ? 1 : 0, diag ? 1 : 0);
 }
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s) {
   const long long blocks = (n + PD_BLOCK - 1) / PD_BLOCK;

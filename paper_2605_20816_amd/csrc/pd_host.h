@@ -42,13 +42,14 @@ struct Arena {
 };
 
 struct MapRegions {
-  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32;
+  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32, part_d;
 };
 
 // Everything one batched evaluation / assignment needs, laid out in an arena.
 struct EvalPlan {
   int n = 0, prec = 0;
   bool any_grad = false;
+  bool with_diag = false;  // FP64/FP32: room for Hessian-diagonal partials (set before layout)
   int target_waves = 8192;
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;

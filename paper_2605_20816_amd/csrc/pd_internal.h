@@ -59,6 +59,11 @@ struct MapDev {
   int32_t Kp, n32, tiles32;         // K rounded up to 16; pixels rounded up to 32; 32-pixel tiles
   int32_t a16_items, b16_items;     // blocks of k16_lse; waves of k16_grad
   int32_t chunk_tiles, chunks, ggroups;
+  // Hessian diagonal sum_x p_i (1 - p_i) psi_k^2 / (eps^2 n) of -Phi (eq. hess),
+  // computed by the gradient kernels when want_diag is non-null and set
+  const int32_t *want_diag;
+  double *diag;                     // N x K or null
+  double *part_d;                   // [tiles][Npad][K] partial sums (FP64/FP32 paths)
 };
 
 
@@ -169,9 +174,9 @@ void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps
 void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                    int total, hipStream_t s);
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                    int total, hipStream_t s);
+                    int total, bool diag, hipStream_t s);
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
-                      bool grad, hipStream_t s);
+                      bool grad, bool diag, hipStream_t s);
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s);
 void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       hipStream_t s);

@@ -154,3 +154,93 @@ def test_given_start_is_moved_into_the_gauge(pd, orc):
     assert np.array_equal(x, th0 - th0[-1])
     phi_ref, _ = orc.objective_grad(th0, gm.labels, gm.H, gm.W, 1, 1e-2)
     assert abs(rep["phi"] - phi_ref) <= 1e-12 * abs(phi_ref)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_hessian_diag_matches_oracle(pd, orc, prec, tol):
+    """Diagonal of eq. hess (sum_x p (1 - p) psi^2 / (eps^2 n)) against the oracle."""
+    pdl, ctx = pd
+    rng = np.random.default_rng(41)
+    cases = [(23, 70, 9, 2, 0.05), (40, 33, 70, 3, 0.02), (17, 19, 5, 6, 0.3)]
+    probs, ths, refs = [], [], []
+    for H, W, N, d, eps in cases:
+        lab = synth.random_labels(H, W, N, rng)
+        th = synth.random_theta(N, d, rng, scale=0.2, multi_index=orc.multi_index(d))
+        probs.append(pdl.Problem(dev(lab, torch.int32), H, W, N, d, eps))
+        ths.append(dev(th))
+        refs.append(orc.hessian_diag(th, lab, H, W, d, eps))
+    out = ctx.hessian_diag(probs, ths, prec)
+    for D, ref in zip(out, refs):
+        D = D.cpu().numpy()
+        assert np.all(D >= 0)
+        assert np.max(np.abs(D - ref)) <= tol * np.max(ref)
+
+
+def poly_map(seed=3, H=64, W=64, N=16, d=3):
+    return synth.polynomial_diagram(H, W, N, d, np.random.default_rng(seed))
+
+
+@pytest.mark.parametrize("iters", [1, 4, 12])
+def test_preconditioned_iterates_match_oracle(pd, orc, iters):
+    """Diagonal preconditioner refreshed every 5 iterations: the same state machine
+    as the oracle's, so the first iterates agree (12 crosses two refreshes)."""
+    pdl, ctx = pd
+    gm = poly_map()
+    d, eps = 3, 1e-3
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    pre = lambda th: orc.hessian_diag(th, gm.labels, gm.H, gm.W, d, eps)
+    ref = orc.lbfgs_fit(obj, np.zeros((gm.N, 10)), target_acc=2.0, max_iter=iters,
+                        precondition=pre, diag_every=5)
+    th = dev(np.zeros((gm.N, 10)))
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "fp64", init="zero", max_iter=iters,
+                  target_acc=2.0, precondition=5)[0]
+    assert rep["iters"] == ref["iters"] == iters
+    assert rep["evals"] == ref["evals"]
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x - ref["theta"])) <= 1e-7 * np.max(np.abs(ref["theta"]))
+    assert np.all(x[-1] == 0)
+
+
+def test_preconditioned_fit_needs_fewer_iterations(pd, orc):
+    pdl, ctx = pd
+    gm = poly_map(5, 128, 128, 40, 4)
+    p = problem(pdl, gm, 4, 1e-3)
+    th0 = dev(np.zeros((gm.N, 15)))
+    r0 = ctx.fit([p], [th0], "fp32", init="zero", max_iter=2000, target_acc=0.99)[0]
+    th1 = dev(np.zeros((gm.N, 15)))
+    r1 = ctx.fit([p], [th1], "fp32", init="zero", max_iter=2000, target_acc=0.99,
+                 precondition=10)[0]
+    assert r0["status"] == r1["status"] == "target"
+    _, nc, _ = orc.assign(th1.cpu().numpy(), gm.H, gm.W, 4, gm.labels)
+    assert nc / gm.labels.size >= 0.99
+    print(f"\niterations to 99%: plain {r0['iters']}, preconditioned {r1['iters']}")
+    assert r1["iters"] < r0["iters"]
+
+
+def test_preconditioned_batched_equals_single(pd):
+    pdl, ctx = pd
+    rng = np.random.default_rng(9)
+    maps = [(poly_map(), 3), (synth.anisotropic_power_diagram(40, 52, 12, rng), 2)]
+    probs = [problem(pdl, gm, d, 1e-2) for gm, d in maps]
+    ths = [dev(np.zeros((gm.N, pdl.num_features(d)))) for gm, d in maps]
+    reps = ctx.fit(probs, ths, "fp32", init="zero", max_iter=150, target_acc=0.99, precondition=10)
+    for k, (p, (gm, d)) in enumerate(zip(probs, maps)):
+        t1 = dev(np.zeros((gm.N, pdl.num_features(d))))
+        r1 = ctx.fit([p], [t1], "fp32", init="zero", max_iter=150, target_acc=0.99,
+                     precondition=10)[0]
+        assert torch.equal(t1, ths[k])
+        assert (r1["iters"], r1["evals"]) == (reps[k]["iters"], reps[k]["evals"])
+
+
+def test_preconditioner_argument_checks(pd):
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    p = problem(pdl, gm, 1, 1e-2)
+    th = dev(np.zeros((gm.N, 3)))
+    for kw, status in ((dict(prec="bf16"), "UNSUPPORTED"), (dict(gauge="centered"), "UNSUPPORTED"),
+                       (dict(precondition=-1), "INVALID_ARG")):
+        args = dict(prec="fp32", init="zero", max_iter=5, precondition=10)
+        args.update(kw)
+        prec = args.pop("prec")
+        with pytest.raises(pdl.PdError, match=status):
+            ctx.fit([p], [th], prec, **args)
