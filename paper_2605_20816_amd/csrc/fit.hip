@@ -28,7 +28,7 @@
 #include <chrono>
 #include <vector>
 
-#define FIT_THREADS 1024
+#define FIT_THREADS 512
 #define LS_C1 1e-4
 #define LS_C2 0.9
 #define LS_MAX_EVALS 20
@@ -236,32 +236,47 @@ __device__ void refresh_dinv(FitDev &F, double *red) {
   __syncthreads();
 }
 
-// gYY[j][k] = y_j . Dinv y_k for every pair of the L live slots: row a against
-// up to 16 columns b >= a per pass.
+// gYY[j][k] = y_j . Dinv y_k for every pair of the L live slots, in tiles of 4
+// rows x 8 columns on or right of the diagonal block (one pass over memory and
+// one 32-value block sum per tile).
 __device__ void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *red) {
   const int M1 = F.m + 1;
   const int n = F.NK;
   const double *__restrict__ pY = F.Y;
-  for (int a = 0; a < L; ++a) {
-    const int ja = slot[a];
-    for (int b0 = a; b0 < L; b0 += 16) {
-      int jb[16];
+  for (int a0 = 0; a0 < L; a0 += 4) {
+    for (int b0 = a0; b0 < L; b0 += 8) {
+      int ja[4], jb[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) jb[u] = slot[min(b0 + u, L - 1)];
-      double acc[16];
+      for (int u = 0; u < 4; ++u) ja[u] = slot[min(a0 + u, L - 1)];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int v = 0; v < 8; ++v) jb[v] = slot[min(b0 + v, L - 1)];
+      double acc[32];
+#pragma unroll
+      for (int q = 0; q < 32; ++q) acc[q] = 0.0;
       for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
-        const double ya = pY[(size_t)ja * n + e] * F.Dinv[e];
+        const double w = F.Dinv[e];
+        double ya[4], yb[8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] = __builtin_fma(ya, pY[(size_t)jb[u] * n + e], acc[u]);
+        for (int u = 0; u < 4; ++u) ya[u] = pY[(size_t)ja[u] * n + e] * w;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) yb[v] = pY[(size_t)jb[v] * n + e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 8; ++v) acc[u * 8 + v] = __builtin_fma(ya[u], yb[v], acc[u * 8 + v]);
       }
-      blk_sums<16>(acc, red);
-      if (threadIdx.x == 0)
-        for (int u = 0; u < 16 && b0 + u < L; ++u) {
-          gYY[ja * M1 + jb[u]] = acc[u];
-          gYY[jb[u] * M1 + ja] = acc[u];
-        }
+      blk_sums<32>(acc, red);
+      // constant indices only: a runtime bound here would move acc to scratch
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+            if (a0 + u < L && b0 + v < L) {
+              gYY[ja[u] * M1 + jb[v]] = acc[u * 8 + v];
+              gYY[jb[v] * M1 + ja[u]] = acc[u * 8 + v];
+            }
+      }
       __syncthreads();
     }
   }
@@ -376,7 +391,9 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
       }
       blk_sums<40>(acc, red);
       if (threadIdx.x == 0) {
-        for (int u = 0; u < 8 && k0 + u < L; ++u) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k0 + u >= L) continue;
           const int jj = js[u];
           Sg[jj] = acc[u];
           Yg[jj] = acc[8 + u];
