@@ -152,6 +152,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
     R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
     R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
     R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
@@ -194,6 +195,7 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
     M.part_l = (double *)(base + R.part_l);
     M.part_g = (double *)(base + R.part_g);
     M.part_c = (int64_t *)(base + R.part_c);
+    M.onehot = P.onehot_pre && P.prec != 2 ? (double *)(base + R.onehot) : nullptr;
     M.part_d = P.with_diag ? (double *)(base + R.part_d) : nullptr;
     M.diag = nullptr;
     M.want_diag = nullptr;
@@ -258,11 +260,17 @@ void pd_plan_tables(const EvalPlan &P, hipStream_t s) {
   pd_launch_tables(P.prec, P.d_maps, P.n, P.max_hw, s);
 }
 
+void pd_plan_onehot(const EvalPlan &P, hipStream_t s) {
+  if (P.prec == 2 || !P.onehot_pre) return;
+  pd_launch_onehot(P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.d_offR, P.offR[P.n], s);
+}
+
 void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
   pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-  if (with_grad) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.with_diag, s);
+  if (with_grad)
+    pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.with_diag, !P.onehot_pre, s);
   pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, with_grad && P.with_diag, s);
 }
 
@@ -533,6 +541,7 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   hipStream_t s = (hipStream_t)stream;
   EvalPlan P;
   Arena L;
+  P.onehot_pre = true;  // as in a fit
   P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   pd_plan_layout(P, L, probs, n_probs, code);
   const size_t o_phi = L.take(sizeof(double) * n_probs);
@@ -549,10 +558,15 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   for (auto &e : ev) PD_HIP(ctx, hipEventCreate(&e));
   // one untimed evaluation first (loads the kernels' code on first use)
   pd_plan_tables(P, s);
+  pd_plan_onehot(P, s);
   if (code == 2) pd_bf16_plan_eval(ctx, P, s, true);
   else pd_plan_eval(P, true, s, true);
   PD_HIP(ctx, hipEventRecord(ev[0], s));
-  for (int r = 0; r < reps; ++r) pd_plan_tables(P, s);
+  // the tables stage includes the per-plan indicator moments
+  for (int r = 0; r < reps; ++r) {
+    pd_plan_tables(P, s);
+    pd_plan_onehot(P, s);
+  }
   PD_HIP(ctx, hipEventRecord(ev[1], s));
   for (int r = 0; r < reps; ++r) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   PD_HIP(ctx, hipEventRecord(ev[2], s));
@@ -565,7 +579,8 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     PD_HIP(ctx, hipEventRecord(ev[3], s));
     for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
     PD_HIP(ctx, hipEventRecord(ev[4], s));
-    for (int r = 0; r < reps; ++r) pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], false, s);
+    for (int r = 0; r < reps; ++r)
+      pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], false, !P.onehot_pre, s);
     PD_HIP(ctx, hipEventRecord(ev[5], s));
   }
   for (int r = 0; r < reps; ++r) {
@@ -611,6 +626,7 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   for (int w : cand) {
     EvalPlan P;
     Arena L;
+    P.onehot_pre = true;  // as in a fit
     P.target_waves = w;
     pd_plan_layout(P, L, probs, n_probs, code);
     const size_t o_phi = L.take(sizeof(double) * n_probs);
@@ -624,6 +640,7 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), g.data(), nullptr, nullptr);
     PD_HIP(ctx, pd_plan_upload(ctx, P, s));
     pd_plan_tables(P, s);
+    pd_plan_onehot(P, s);
     auto run = [&]() {
       if (code == 2) pd_bf16_plan_eval(ctx, P, s, true);
       else pd_plan_eval(P, true, s, true);

@@ -33,6 +33,7 @@
 #define LS_C2 0.9
 #define LS_MAX_EVALS 20
 #define CURV_EPS 1e-10
+#define FIT_MAX_HISTORY 32
 
 enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
 enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
@@ -88,7 +89,7 @@ struct FitState {
 #define MAX_WAVES (FIT_THREADS / PD_WAVE)
 
 template <int G>
-__device__ void blk_sums(double (&v)[G], double *red) {
+__device__ __attribute__((always_inline)) inline void blk_sums(double (&v)[G], double *red) {
 #pragma unroll
   for (int q = 0; q < G; ++q) v[q] = pd_wave_sum(v[q]);
   const int nw = blockDim.x >> 6;
@@ -109,7 +110,7 @@ __device__ void blk_sums(double (&v)[G], double *red) {
   for (int q = 0; q < G; ++q) v[q] = red[MAX_WAVES * 48 + q];
 }
 
-__device__ double blk_max(double v, double *red) {
+__device__ __attribute__((always_inline)) inline double blk_max(double v, double *red) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, PD_WAVE));
   const int nw = blockDim.x >> 6;
@@ -123,7 +124,7 @@ __device__ double blk_max(double v, double *red) {
 }
 
 // v <- projection of v onto the gauge-fixed subspace (in place).
-__device__ void blk_gauge(FitDev &F, double *v, double *red) {
+__device__ __attribute__((always_inline)) inline void blk_gauge(FitDev &F, double *v, double *red) {
   if (F.gauge == 0) {
     for (int k = threadIdx.x; k < F.K; k += blockDim.x) v[(size_t)(F.N - 1) * F.K + k] = 0.0;
   } else if (F.gauge == 1) {
@@ -165,7 +166,7 @@ __device__ inline void fit_stop(FitDev &F, int status) {
 }
 
 // ||g||^2, ||g||_inf and g.d of the current iterate (one pass).
-__device__ void pass_gstats(FitDev &F, double *red) {
+__device__ __attribute__((always_inline)) inline void pass_gstats(FitDev &F, double *red) {
   double v[2] = {0.0, 0.0};
   double mx = 0.0;
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
@@ -185,7 +186,7 @@ __device__ void pass_gstats(FitDev &F, double *red) {
 }
 
 // d = -H0 g (H0 = I, or the diagonal preconditioner) and its slope g.d.
-__device__ void set_steepest(FitDev &F, double *red) {
+__device__ __attribute__((always_inline)) inline void set_steepest(FitDev &F, double *red) {
   double v[1] = {0.0};
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = F.g[i];
@@ -200,7 +201,7 @@ __device__ void set_steepest(FitDev &F, double *red) {
 
 // Start a line search from (x, f, g) along d; F.gg, F.gmax and F.dphi0 = g.d
 // must be current.
-__device__ void start_ls(FitDev &F, double *red) {
+__device__ __attribute__((always_inline)) inline void start_ls(FitDev &F, double *red) {
   if (threadIdx.x == 0 && (F.gg == 0.0 || F.gmax <= F.gtol)) fit_stop(F, ST_GTOL);
   __syncthreads();
   if (F.status != ST_RUNNING) return;
@@ -225,7 +226,7 @@ __device__ void start_ls(FitDev &F, double *red) {
 
 // Dinv = 1 / (diag + floor * max diag) from the last evaluation; the gauge row of
 // grain N-1 stays 0.
-__device__ void refresh_dinv(FitDev &F, double *red) {
+__device__ __attribute__((always_inline)) inline void refresh_dinv(FitDev &F, double *red) {
   double mx = 0.0;
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) mx = fmax(mx, F.diag[i]);
   mx = blk_max(mx, red);
@@ -239,10 +240,11 @@ __device__ void refresh_dinv(FitDev &F, double *red) {
 // gYY[j][k] = y_j . Dinv y_k for every pair of the L live slots, in tiles of 4
 // rows x 8 columns on or right of the diagonal block (one pass over memory and
 // one 32-value block sum per tile).
-__device__ void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *red) {
+__device__ __attribute__((always_inline)) inline void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *red) {
   const int M1 = F.m + 1;
   const int n = F.NK;
-  const double *__restrict__ pY = F.Y;
+  const auto pY = pd_glb((const double *)F.Y);
+  const auto pw = pd_glb((const double *)F.Dinv);
   for (int a0 = 0; a0 < L; a0 += 4) {
     for (int b0 = a0; b0 < L; b0 += 8) {
       int ja[4], jb[8];
@@ -254,7 +256,7 @@ __device__ void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *
 #pragma unroll
       for (int q = 0; q < 32; ++q) acc[q] = 0.0;
       for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
-        const double w = F.Dinv[e];
+        const double w = pw[e];
         double ya[4], yb[8];
 #pragma unroll
         for (int u = 0; u < 4; ++u) ya[u] = pY[(size_t)ja[u] * n + e] * w;
@@ -282,11 +284,76 @@ __device__ void gram_yy(FitDev &F, const int *slot, int L, double *gYY, double *
   }
 }
 
+// One pass over the memory for the live slots k0 .. k0+U-1 (clipped to L):
+// S^T g, Y^T g (in the metric of H0) and, when the new pair is stored, its Gram
+// row and column.  Returns U.
+template <int U>
+__device__ __attribute__((always_inline)) inline int slot_pass(
+    FitDev &F, const int *slot, int k0, int L, bool stored, int put, const double *s,
+    const double *y, double *Sg, double *Yg, double *gSY, double *gYY, double *red) {
+  const int n = F.NK;
+  const int M1 = F.m + 1;
+  const auto pS = pd_glb((const double *)F.S);
+  const auto pY = pd_glb((const double *)F.Y);
+  const auto pg = pd_glb((const double *)F.g);
+  const auto pns = pd_glb(s);
+  const auto pny = pd_glb(y);
+  const auto pw = pd_glb((const double *)F.Dinv);
+  const bool pre = F.precond != 0;
+  double acc[5 * U];
+#pragma unroll
+  for (int q = 0; q < 5 * U; ++q) acc[q] = 0.0;
+  int js[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) js[u] = slot[min(k0 + u, L - 1)];
+  for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
+    const double gi = pg[e], si = pns[e], yi = pny[e];
+    // Y^T g and Y^T y_new in the metric of H0 (Dinv, or the identity)
+    const double w = pre ? pw[e] : 1.0;
+    const double gw = pre ? gi * w : gi, yw = pre ? yi * w : yi;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double Sj = pS[(size_t)js[u] * n + e];
+      const double Yj = pY[(size_t)js[u] * n + e];
+      acc[u] = __builtin_fma(Sj, gi, acc[u]);
+      acc[U + u] = __builtin_fma(Yj, gw, acc[U + u]);
+      acc[2 * U + u] = __builtin_fma(si, Yj, acc[2 * U + u]);
+      acc[3 * U + u] = __builtin_fma(Sj, yi, acc[3 * U + u]);
+      acc[4 * U + u] = __builtin_fma(yw, Yj, acc[4 * U + u]);
+    }
+  }
+  blk_sums<5 * U>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u >= L) continue;
+      const int jj = js[u];
+      Sg[jj] = acc[u];
+      Yg[jj] = acc[U + u];
+      if (stored) {
+        gSY[put * M1 + jj] = acc[2 * U + u];
+        gSY[jj * M1 + put] = acc[3 * U + u];
+        gYY[put * M1 + jj] = acc[4 * U + u];
+        gYY[jj * M1 + put] = acc[4 * U + u];
+      }
+    }
+  }
+  __syncthreads();
+  return U;
+}
+
+// v of lane k (k wave-uniform) on every lane.
+__device__ inline double lane_bcast(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+
 // Accept the trial point (xt, graw = gradient of f, ft); update the memory and
 // its Gram matrices, form the quasi-Newton direction d = -H g (the two-loop
 // recursion written through S^T g, Y^T g, S^T Y and Y^T Y) and start the next
 // search.
-__device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, double **jb,
+__device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, double ft, double *red, double **ja, double **jb,
                              double *res, double *coef, double *gSY, double *gYY) {
   const int n = F.NK;
   const int m = F.m;
@@ -298,13 +365,13 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   FIT_STAMP(F, 5);
   double v3[3] = {0.0, 0.0, 0.0};
   {
-    double *__restrict__ ps = s;
-    double *__restrict__ py = y;
-    double *__restrict__ px = F.x;
-    double *__restrict__ pg = F.g;
-    const double *__restrict__ pd = F.d;
-    const double *__restrict__ pgr = F.graw;
-    const double *__restrict__ pxt = F.xt;
+    const auto ps = pd_glb(s);
+    const auto py = pd_glb(y);
+    const auto px = pd_glb(F.x);
+    const auto pg = pd_glb(F.g);
+    const auto pd = pd_glb((const double *)F.d);
+    const auto pgr = pd_glb((const double *)F.graw);
+    const auto pxt = pd_glb((const double *)F.xt);
     for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
       const double di = pd[i], gri = pgr[i], gi = pg[i], xti = pxt[i];
       const double si = t * di;
@@ -358,87 +425,71 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
   __syncthreads();
   FIT_STAMP(F, 7);
-  // one pass per 8 live slots: S^T g, Y^T g and, for a stored pair, its Gram
-  // row and column (s_new . y_j, s_j . y_new, y_new . y_j)
-  {
-    const double *__restrict__ pS = F.S;
-    const double *__restrict__ pY = F.Y;
-    const double *__restrict__ pg = F.g;
-    const double *__restrict__ pns = s;
-    const double *__restrict__ pny = y;
-    for (int k0 = 0; k0 < L; k0 += 8) {
-      double acc[5 * 8];
-#pragma unroll
-      for (int q = 0; q < 40; ++q) acc[q] = 0.0;
-      int js[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) js[u] = slot[min(k0 + u, L - 1)];
-      for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
-        const double gi = pg[e], si = pns[e], yi = pny[e];
-        // Y^T g and Y^T y_new in the metric of H0 (Dinv, or the identity)
-        const double w = F.precond ? F.Dinv[e] : 1.0;
-        const double gw = F.precond ? gi * w : gi, yw = F.precond ? yi * w : yi;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double Sj = pS[(size_t)js[u] * n + e];
-          const double Yj = pY[(size_t)js[u] * n + e];
-          acc[u] = __builtin_fma(Sj, gi, acc[u]);
-          acc[8 + u] = __builtin_fma(Yj, gw, acc[8 + u]);
-          acc[16 + u] = __builtin_fma(si, Yj, acc[16 + u]);
-          acc[24 + u] = __builtin_fma(Sj, yi, acc[24 + u]);
-          acc[32 + u] = __builtin_fma(yw, Yj, acc[32 + u]);
-        }
-      }
-      blk_sums<40>(acc, red);
-      if (threadIdx.x == 0) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (k0 + u >= L) continue;
-          const int jj = js[u];
-          Sg[jj] = acc[u];
-          Yg[jj] = acc[8 + u];
-          if (stored) {
-            gSY[put * M1 + jj] = acc[16 + u];
-            gSY[jj * M1 + put] = acc[24 + u];
-            gYY[put * M1 + jj] = acc[32 + u];
-            gYY[jj * M1 + put] = acc[32 + u];
-          }
-        }
-      }
-      __syncthreads();
-    }
+  // passes over up to 8 live slots: S^T g, Y^T g and, for a stored pair, its
+  // Gram row and column (s_new . y_j, s_j . y_new, y_new . y_j)
+  for (int k0 = 0; k0 < L;) {
+    const int rem = L - k0;
+    if (rem > 4) k0 += slot_pass<8>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
+    else if (rem > 2) k0 += slot_pass<4>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
+    else k0 += slot_pass<2>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
   }
   if (refresh) gram_yy(F, slot, L, gYY, red);
   if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
   __syncthreads();
   FIT_STAMP(F, 8);
   // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0:
-  // lane k holds alpha and beta of the k-th pair; each step is one DPP sum.
+  // lane j holds alpha_j and beta_j and the running sum of the terms of the
+  // pairs already done; each step broadcasts the finished alpha_k (beta_k) and
+  // every lane adds its term, with the Gram entries it needs held in registers.
   if (threadIdx.x < PD_WAVE) {
     const int lane = threadIdx.x;
-    const int jl = lane < L ? slot[lane] : 0;
-    double a = 0.0, b = 0.0;
-    for (int k = L - 1; k >= 0; --k) {
-      const int jk = slot[k];
-      const double c = (lane > k && lane < L) ? a * gSY[jk * M1 + jl] : 0.0;
-      const double sum = pd_wave_sum(c);
-      if (lane == k) a = rho[jk] * (Sg[jk] - sum);
+    const bool live = lane < L;
+    const int jl = live ? slot[lane] : 0;
+    const double rho_l = live ? rho[jl] : 0.0;
+    const double sg_l = live ? Sg[jl] : 0.0;
+    double row[FIT_MAX_HISTORY];
+    // alpha_j = rho_j (s_j.g - sum_{k>j} alpha_k s_j.y_k)
+#pragma unroll
+    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
+      const int sk = head + k >= M1 ? head + k - M1 : head + k;
+      row[k] = (live && k < L) ? gSY[jl * M1 + sk] : 0.0;
+    }
+    double a = 0.0, pa = 0.0;
+#pragma unroll
+    for (int k = FIT_MAX_HISTORY - 1; k >= 0; --k) {
+      if (k < L) {
+        const double ak = lane_bcast(rho_l * (sg_l - pa), k);
+        if (lane == k) a = ak;
+        pa = __builtin_fma(ak, row[k], pa);
+      }
     }
     const double gam = L > 0 ? F.gamma : 1.0;
-    // y_k . q_final for every k: sum over all pairs of alpha_k2 YY[k][k2]
-    double yq = lane < L ? Yg[jl] : 0.0;
-    for (int k2 = 0; k2 < L; ++k2) {
-      const double ak2 = __shfl(a, k2, PD_WAVE);
-      if (lane < L) yq -= ak2 * gYY[jl * M1 + slot[k2]];
+    // y_j . q_final = y_j.g - sum_k alpha_k y_j.y_k
+#pragma unroll
+    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
+      const int sk = head + k >= M1 ? head + k - M1 : head + k;
+      row[k] = (live && k < L) ? gYY[jl * M1 + sk] : 0.0;
     }
-    for (int k = 0; k < L; ++k) {
-      const int jk = slot[k];
-      const double c = (lane < k) ? (a - b) * gSY[jl * M1 + jk] : 0.0;
-      const double sum = pd_wave_sum(c);
-      const double yqk = __shfl(yq, k, PD_WAVE);
-      if (lane == k) b = rho[jk] * (gam * yqk + sum);
+    double yq = live ? Yg[jl] : 0.0;
+#pragma unroll
+    for (int k = 0; k < FIT_MAX_HISTORY; ++k)
+      if (k < L) yq = __builtin_fma(-lane_bcast(a, k), row[k], yq);
+    // beta_j = rho_j (gamma y_j.q_final + sum_{k<j} (alpha_k - beta_k) s_k.y_j)
+#pragma unroll
+    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
+      const int sk = head + k >= M1 ? head + k - M1 : head + k;
+      row[k] = (live && k < L) ? gSY[sk * M1 + jl] : 0.0;
     }
-    if (lane < L) {
+    double b = 0.0, pb = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
+      if (k < L) {
+        const double bk = lane_bcast(rho_l * __builtin_fma(gam, yq, pb), k);
+        if (lane == k) b = bk;
+        pb = __builtin_fma(lane_bcast(a, k) - bk, row[k], pb);
+      }
+    }
+    if (live) {
       coef[lane] = gam * a;            // on y_k
       coef[M1 + lane] = -(a - b);      // on s_k
     }
@@ -455,10 +506,11 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
   const double cg = coef[4 * M1];
   double v[2] = {0.0, 0.0};
   double mx = 0.0;
-  const double *__restrict__ pS = F.S;
-  const double *__restrict__ pY = F.Y;
-  const double *__restrict__ pg = F.g;
-  double *__restrict__ pdir = F.d;
+  const auto pS = pd_glb((const double *)F.S);
+  const auto pY = pd_glb((const double *)F.Y);
+  const auto pg = pd_glb((const double *)F.g);
+  const auto pdir = pd_glb(F.d);
+  const auto pw = pd_glb((const double *)F.Dinv);
   for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
     const double gi = pg[i];
     // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
@@ -479,7 +531,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
           ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
         }
     }
-    const double di = F.precond ? __builtin_fma(F.Dinv[i], dy, ds) : dy + ds;
+    const double di = F.precond ? __builtin_fma(pw[i], dy, ds) : dy + ds;
     pdir[i] = di;
     v[0] = __builtin_fma(gi, gi, v[0]);
     v[1] = __builtin_fma(gi, di, v[1]);
@@ -502,7 +554,7 @@ __device__ void accept_trial(FitDev &F, double ft, double *red, double **ja, dou
 
 // A search ended without a strong-Wolfe point.  Fall back to (t_res > 0), or
 // clear the memory and retry once, or stop.
-__device__ void ls_fail(FitDev &F, double t_res, double *red) {
+__device__ __attribute__((always_inline)) inline void ls_fail(FitDev &F, double t_res, double *red) {
   if (t_res > 0.0) {
     if (threadIdx.x == 0) {
       F.t = t_res;
@@ -526,7 +578,6 @@ __device__ void ls_fail(FitDev &F, double t_res, double *red) {
 }
 
 // Shared scratch of the decision kernel.
-#define FIT_MAX_HISTORY 32
 #define HS (FIT_MAX_HISTORY + 1)
 #define DEC_SHARED                                  \
   __shared__ double red[MAX_WAVES * 48 + 48];       \
@@ -537,7 +588,7 @@ __device__ void ls_fail(FitDev &F, double t_res, double *red) {
   __shared__ FitDev sF;                             \
   __shared__ int action;
 
-__device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
                             double *coef, double *gSY, double *gYY, int *action_p);
 
 // grid: one block per map.  Consumes one evaluation at xt.
@@ -556,7 +607,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
 }
 
-__device__ void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
                             double *coef, double *gSY, double *gYY, int *action_p) {
   int &action = *action_p;
   const int n = F.NK;
@@ -821,6 +872,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
   P.with_diag = opts->precondition > 0;
+  P.onehot_pre = true;  // indicator moments once per fit
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);
@@ -919,6 +971,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   const auto t_stamp = clk::now();
   k_fit_stamp<<<(n + 255) / 256, 256, 0, s>>>(dF, n);
   pd_plan_tables(P, s);
+  pd_plan_onehot(P, s);
   // block size: the largest per-map thread count (about 4 elements per thread)
   int vt = 64;
   for (int p = 0; p < n; ++p) vt = std::max(vt, F[p].vt);

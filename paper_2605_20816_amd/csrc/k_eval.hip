@@ -234,11 +234,15 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
 // ---------------------------------------------------------------------------
 // Kernel B: partial gradient moments per (pixel tile, 64-grain group).
 // Columns are processed 8 at a time so the wave-uniform column data (P_a(x1),
-// lse, label) arrives in a few wide scalar loads per chunk; the one-hot term
-// (delta_{i,G(x)}) is applied only when a label of the chunk falls in this
-// wave's grain group, tested on the scalar unit.
+// lse, label) arrives in a few wide scalar loads per chunk.  The one-hot part
+// of the gradient (minus the sum of psi over the grain's own pixels) does not
+// depend on theta: with HOT it is applied here, when a label of the chunk falls
+// in this wave's grain group (tested on the scalar unit); without HOT the
+// partials hold sum_x p psi only and the reduction subtracts the indicator
+// moments computed once per plan (k_onehot) -- the form a fit uses, since the
+// label test costs about a fifth of the kernel.
 // With DIAG, also w = p (1 - p) times P_a(x1)^2 per lane (Hessian diagonal).
-template <typename T, int D, int CH, bool DIAG>
+template <typename T, int D, int CH, bool DIAG, bool HOT>
 __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *lp,
                                  const PD_AS_CONST int32_t *gp, const T (&cf)[D + 1],
                                  T (&racc)[D + 1], T (&dacc)[D + 1], int gbase, int lane) {
@@ -251,11 +255,13 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
 #pragma unroll
     for (int a = 1; a < DP; ++a) px[j][a] = pxp[j * DP + a];
     l[j] = lp[j];
-    g[j] = gp[j];
+    if (HOT) g[j] = gp[j];
   }
   unsigned hit = 0;
+  if (HOT) {
 #pragma unroll
-  for (int j = 0; j < CH; ++j) hit |= ((unsigned)(g[j] - gbase) < (unsigned)PD_WAVE) ? (1u << j) : 0u;
+    for (int j = 0; j < CH; ++j) hit |= ((unsigned)(g[j] - gbase) < (unsigned)PD_WAVE) ? (1u << j) : 0u;
+  }
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     T s = cf[0];
@@ -272,7 +278,7 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
       for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(w, px[j][a] * px[j][a], dacc[a]);
     }
   }
-  if (hit) {
+  if (HOT && hit) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       if ((hit >> j) & 1u) {
@@ -286,7 +292,7 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
   }
 }
 
-template <typename T, int D, bool DIAG>
+template <typename T, int D, bool DIAG, bool HOT>
 __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
@@ -317,9 +323,9 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
     int c = c0;
     for (; c + CH <= c1; c += CH)
-      grad_cols<T, D, CH, DIAG>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, CH, DIAG, HOT>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
     for (; c < c1; ++c)
-      grad_cols<T, D, 1, DIAG>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, 1, DIAG, HOT>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -343,7 +349,7 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
   }
 }
 
-template <typename T, int DMAX>
+template <typename T, int DMAX, bool HOT>
 __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ maps,
                                                    const int32_t *__restrict__ off, int n_maps,
                                                    int total) {
@@ -356,13 +362,13 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ ma
   if (PD_GATED(M)) return;
   // evaluations that also want the Hessian diagonal go to k_grad_diag
   if (M.want_diag != nullptr && *pd_uni(M.want_diag) != 0) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, false>(M, item - off[m], lane)));
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, false, HOT>(M, item - off[m], lane)));
 }
 
 // The same work list, for maps whose want_diag is set: gradient partials plus
 // the partials of sum_x p (1 - p) psi^2 (a separate kernel, so the extra
 // accumulators do not raise k_grad's register count).
-template <typename T, int DMAX>
+template <typename T, int DMAX, bool HOT>
 __global__ __launch_bounds__(PD_BLOCK) void k_grad_diag(const MapDev *__restrict__ maps,
                                                         const int32_t *__restrict__ off,
                                                         int n_maps, int total) {
@@ -374,7 +380,93 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad_diag(const MapDev *__restrict
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   if (M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true>(M, item - off[m], lane)));
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true, HOT>(M, item - off[m], lane)));
+}
+
+// ---------------------------------------------------------------------------
+// Indicator moments onehot[i][k] = sum over the pixels x with G(x) = i of
+// psi_k(x), in FP64 from the canonical tables, as partials per (tile, 64-grain
+// group) in part_g (the gradient's work list and layout).  The wave takes the
+// tile 64 columns at a time (one per lane) and its rows 8 at a time (their
+// labels loaded together); for each grain of this group present in a row
+// segment, a wave sum of P_a(x1) over that grain's pixels goes to the grain's
+// lane and is folded with P_b(x2).  Labels outside [gbase, gbase + 64) are
+// skipped.  Every sum has a fixed order.
+template <int D>
+__device__ inline void onehot_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  constexpr int RB = 8;
+  const int groups = M.Npad / PD_WAVE;
+  const int tile = local / groups;
+  const int grp = local - tile * groups;
+  const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
+  const int r0 = tr * M.tile_rows, r1 = min(r0 + M.tile_rows, M.H);
+  const int c0 = tcol * M.tile_cols, c1 = min(c0 + M.tile_cols, M.W);
+  const int gbase = grp * PD_WAVE;
+  const int i = gbase + lane;
+  double q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q[k] = 0.0;
+  for (int cs = c0; cs < c1; cs += PD_WAVE) {
+    const int c = cs + lane;
+    const bool okc = c < c1;
+    double v[DP];
+    {
+      const auto t = pd_glb((const double *)M.tx64 + (size_t)(okc ? c : c0) * DP);
+#pragma unroll
+      for (int a = 0; a < DP; ++a) v[a] = t[a];
+    }
+    for (int rb = r0; rb < r1; rb += RB) {
+      int off[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u)
+        off[u] = (okc && rb + u < r1) ? pd_glb(M.labels)[(size_t)(rb + u) * M.W + c] - gbase : -1;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int o = off[u];
+        unsigned long long mask = __ballot((unsigned)o < (unsigned)PD_WAVE);
+        if (mask == 0) continue;
+        double acc[DP];
+#pragma unroll
+        for (int a = 0; a < DP; ++a) acc[a] = 0.0;
+        while (mask) {
+          const int tgt = __builtin_amdgcn_readlane(o, __builtin_ctzll(mask));
+          const bool mine = o == tgt;
+          mask &= ~__ballot(mine);
+#pragma unroll
+          for (int a = 0; a < DP; ++a) {
+            const double sa = pd_wave_sum(mine ? v[a] : 0.0);
+            if (lane == tgt) acc[a] = sa;
+          }
+        }
+        const auto ty = pd_uni(M.ty64 + (size_t)(rb + u) * DP);
+#pragma unroll
+        for (int a = 0; a <= D; ++a)
+#pragma unroll
+          for (int b = 0; a + b <= D; ++b) {
+            const int k = pd_alpha_index(a, b);
+            q[k] = __builtin_fma(acc[a], ty[b], q[k]);
+          }
+      }
+    }
+  }
+  const auto out = pd_glb(M.part_g + ((size_t)tile * M.Npad + i) * K);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = q[k];
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_onehot(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps,
+                                                     int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  PD_DISPATCH_UPTO(DMAX, M.d, (onehot_item<D>(M, item - off[m], lane)));
 }
 
 // ---------------------------------------------------------------------------
@@ -399,7 +491,7 @@ __device__ inline void reduce_phi_block(const MapDev &M) {
 #define RG_OUT 16
 #define RG_PH 16
 __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const double *part,
-                                         double *dst, double scale) {
+                                         const double *sub, double *dst, double scale) {
   __shared__ double red[RG_PH][RG_OUT + 1];
   const int ol = threadIdx.x % RG_OUT, ph = threadIdx.x / RG_OUT;
   const int o = chunk * RG_OUT + ol;
@@ -429,7 +521,7 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const doubl
     if (ph < w) red[ph][ol] += red[ph + w][ol];
     __syncthreads();
   }
-  if (ph == 0 && o < NK) dst[o] = red[0][ol] * scale;
+  if (ph == 0 && o < NK) dst[o] = (sub ? red[0][ol] - sub[o] : red[0][ol]) * scale;
 }
 
 // One launch for all reductions: blocks [0, n_maps) reduce Phi of map b; the
@@ -455,11 +547,21 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ 
   const MapDev &M = maps[m];
   if (M.grad == nullptr || PD_GATED(M)) return;
   if (!diag) {
-    reduce_grad_block(M, b - off[m], M.part_g, M.grad, M.grad_scale);
+    reduce_grad_block(M, b - off[m], M.part_g, M.onehot, M.grad, M.grad_scale);
   } else {
     if (M.diag == nullptr || M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
-    reduce_grad_block(M, b - off[m], M.part_d, M.diag, M.grad_scale / M.eps);
+    reduce_grad_block(M, b - off[m], M.part_d, nullptr, M.diag, M.grad_scale / M.eps);
   }
+}
+
+// The tiles' indicator-moment partials (k_onehot, in part_g) -> onehot.
+__global__ __launch_bounds__(PD_BLOCK) void k_reduce_onehot(const MapDev *__restrict__ maps,
+                                                            const int32_t *__restrict__ off,
+                                                            int n_maps) {
+  const int b = blockIdx.x;
+  const int m = pd_find_map(off, n_maps, b);
+  const MapDev &M = maps[m];
+  reduce_grad_block(M, b - off[m], M.part_g, nullptr, M.onehot, 1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,15 +630,38 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
   if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse, double, dmax, blocks, s, maps, off, n_maps, total); }
   else { PD_LAUNCH_BY_DMAX(k_lse, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
-void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                    int total, bool diag, hipStream_t s) {
-  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_grad, double, dmax, blocks, s, maps, off, n_maps, total); }
-  else { PD_LAUNCH_BY_DMAX(k_grad, float, dmax, blocks, s, maps, off, n_maps, total); }
-  if (diag) {
-    if (prec == 0) { PD_LAUNCH_BY_DMAX(k_grad_diag, double, dmax, blocks, s, maps, off, n_maps, total); }
-    else { PD_LAUNCH_BY_DMAX(k_grad_diag, float, dmax, blocks, s, maps, off, n_maps, total); }
+#define PD_LAUNCH_GRAD(KERNEL, T, dmax, hot, blocks, s, ...)                              \
+  do {                                                                                \
+    if (hot) { PD_LAUNCH_BY_DMAX_HOT(KERNEL, T, true, dmax, blocks, s, __VA_ARGS__); }   \
+    else { PD_LAUNCH_BY_DMAX_HOT(KERNEL, T, false, dmax, blocks, s, __VA_ARGS__); }      \
+  } while (0)
+#define PD_LAUNCH_BY_DMAX_HOT(KERNEL, T, H, dmax, blocks, s, ...)                     \
+  switch (dmax) {                                                                   \
+    case 2: KERNEL<T, 2, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
+    case 4: KERNEL<T, 4, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
+    case 6: KERNEL<T, 6, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
+    default: KERNEL<T, 8, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;         \
   }
+void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                    int total, bool diag, bool hot, hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (prec == 0) PD_LAUNCH_GRAD(k_grad, double, dmax, hot, blocks, s, maps, off, n_maps, total);
+  else PD_LAUNCH_GRAD(k_grad, float, dmax, hot, blocks, s, maps, off, n_maps, total);
+  if (diag) {
+    if (prec == 0) PD_LAUNCH_GRAD(k_grad_diag, double, dmax, hot, blocks, s, maps, off, n_maps, total);
+    else PD_LAUNCH_GRAD(k_grad_diag, float, dmax, hot, blocks, s, maps, off, n_maps, total);
+  }
+}
+void pd_launch_onehot(int dmax, const MapDev *maps, const int32_t *off_b, int n_maps, int total,
+                      const int32_t *off_r, int blocks_r, hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  switch (dmax) {
+    case 2: k_onehot<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
+    case 4: k_onehot<4><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
+    case 6: k_onehot<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
+    default: k_onehot<8><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
+  }
+  k_reduce_onehot<<<blocks_r, PD_BLOCK, 0, s>>>(maps, off_r, n_maps);
 }
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
                       bool grad, bool diag, hipStream_t s) {

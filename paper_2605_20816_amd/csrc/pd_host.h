@@ -42,7 +42,7 @@ struct Arena {
 };
 
 struct MapRegions {
-  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32, part_d;
+  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32, part_d, onehot;
 };
 
 // Everything one batched evaluation / assignment needs, laid out in an arena.
@@ -50,6 +50,9 @@ struct EvalPlan {
   int n = 0, prec = 0;
   bool any_grad = false;
   bool with_diag = false;  // FP64/FP32: room for Hessian-diagonal partials (set before layout)
+  // FP64/FP32: the indicator moments are computed once (pd_plan_onehot, after
+  // the tables) and the gradient kernel skips the one-hot term (set before bind)
+  bool onehot_pre = false;
   int target_waves = 8192;
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;
@@ -70,6 +73,8 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
                   double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
 void pd_plan_tables(const EvalPlan &P, hipStream_t s);
+// Indicator moments of every map when P.onehot_pre (after pd_plan_tables).
+void pd_plan_onehot(const EvalPlan &P, hipStream_t s);
 // center: run k_center (thc from theta); the fit driver forms thc itself.
 void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center);
 void pd_plan_assign(const EvalPlan &P, hipStream_t s);

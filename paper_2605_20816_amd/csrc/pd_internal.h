@@ -38,7 +38,10 @@ struct MapDev {
   void *C;                          // [H][Npad][DP] row coefficients, evaluation type
   void *lse;                        // [n] base-2 log-sum-exp per pixel, evaluation type
   double *part_l;                   // [a_items] per-wave partial sums of log2 p_G
-  double *part_g;                   // [tiles][Npad][K] partial sums of (p - delta) psi
+  double *part_g;                   // [tiles][Npad][K] partial sums of (p - delta) psi, or of
+                                    // p psi when onehot is set
+  double *onehot;                   // [N][K] sum of psi over each grain's pixels (FP64), or
+                                    // null when the gradient kernel applies the one-hot term
   // gradient tiling: tiles of tile_rows x tile_cols pixels, 64 grains per wave
   int32_t tile_rows, tile_cols, tiles_r, tiles_c;
   // work-item counts and offsets inside the batched launches
@@ -173,8 +176,14 @@ void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps
                     hipStream_t s);
 void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                    int total, hipStream_t s);
+// hot: apply the one-hot term in the kernel; otherwise MapDev::onehot must hold
+// the indicator moments (pd_launch_onehot) and the reduction subtracts them.
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                    int total, bool diag, hipStream_t s);
+                    int total, bool diag, bool hot, hipStream_t s);
+// k_onehot over the gradient work list, then its fixed-order tile reduction
+// into MapDev::onehot (part_g is the scratch).
+void pd_launch_onehot(int dmax, const MapDev *maps, const int32_t *off_b, int n_maps, int total,
+                      const int32_t *off_r, int blocks_r, hipStream_t s);
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
                       bool grad, bool diag, hipStream_t s);
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s);
