@@ -275,7 +275,7 @@ void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center)
 }
 
 void pd_plan_assign(const EvalPlan &P, hipStream_t s) {
-  pd_launch_assign(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  pd_launch_assign(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], true, s);
 }
 
 static std::tuple<int, int, int, int> tune_key(const pd_problem *probs, int n, int prec) {

@@ -46,7 +46,8 @@ struct FitDev {
   double *x, *g, *d, *xt, *graw, *S, *Y, *rho;
   double *SY, *YY, *Sg, *Yg;  // Gram matrices s_j.y_k, y_j.y_k over the m+1 ring slots; S^T g, Y^T g
   const double *phi_t;
-  const int64_t *n_correct;
+  const int64_t *part_c;  // per-wave correct counts of the last assignment
+  int32_t a_items;        // their number
   double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
   double cscale;     // -log2(e) / eps
   int32_t *active, *assign_pending;
@@ -349,6 +350,58 @@ __device__ inline double lane_bcast(double v, int k) {
   return __hiloint2double(hi, lo);
 }
 
+// Coefficients of the compact two-loop recursion on the lanes of wave 0: alpha
+// newest to oldest, then beta oldest to newest.  Lane j holds alpha_j, beta_j
+// and the running sum of the terms of the pairs already done; each step
+// broadcasts the finished alpha_k (beta_k) and every lane adds its term.  The
+// loops are not unrolled (this code runs once per launch, so its size, not its
+// instruction count, sets the time) and each step's Gram entry is loaded one
+// step ahead.
+__device__ __attribute__((always_inline)) inline void lbfgs_coef(
+    FitDev &F, int L, int head, int M1, const int *slot, const double *rho, const double *Sg,
+    const double *Yg, const double *gSY, const double *gYY, double *coef) {
+  const int lane = threadIdx.x;
+  const bool live = lane < L;
+  const int jl = live ? slot[lane] : 0;
+  const double rho_l = live ? rho[jl] : 0.0;
+  const double sg_l = live ? Sg[jl] : 0.0;
+  auto slot_of = [&](int k) { return head + k >= M1 ? head + k - M1 : head + k; };
+  // alpha_j = rho_j (s_j.g - sum_{k>j} alpha_k s_j.y_k)
+  double a = 0.0, pa = 0.0;
+  double nx = L > 0 ? gSY[jl * M1 + slot_of(L - 1)] : 0.0;
+  for (int k = L - 1; k >= 0; --k) {
+    const double e = live ? nx : 0.0;
+    if (k > 0) nx = gSY[jl * M1 + slot_of(k - 1)];
+    const double ak = lane_bcast(rho_l * (sg_l - pa), k);
+    if (lane == k) a = ak;
+    pa = __builtin_fma(ak, e, pa);
+  }
+  const double gam = L > 0 ? F.gamma : 1.0;
+  // y_j . q_final = y_j.g - sum_k alpha_k y_j.y_k
+  double yq = live ? Yg[jl] : 0.0;
+  nx = L > 0 ? gYY[jl * M1 + slot_of(0)] : 0.0;
+  for (int k = 0; k < L; ++k) {
+    const double e = live ? nx : 0.0;
+    if (k + 1 < L) nx = gYY[jl * M1 + slot_of(k + 1)];
+    yq = __builtin_fma(-lane_bcast(a, k), e, yq);
+  }
+  // beta_j = rho_j (gamma y_j.q_final + sum_{k<j} (alpha_k - beta_k) s_k.y_j)
+  double b = 0.0, pb = 0.0;
+  nx = L > 0 ? gSY[slot_of(0) * M1 + jl] : 0.0;
+  for (int k = 0; k < L; ++k) {
+    const double e = live ? nx : 0.0;
+    if (k + 1 < L) nx = gSY[slot_of(k + 1) * M1 + jl];
+    const double bk = lane_bcast(rho_l * __builtin_fma(gam, yq, pb), k);
+    if (lane == k) b = bk;
+    pb = __builtin_fma(lane_bcast(a, k) - bk, e, pb);
+  }
+  if (live) {
+    coef[lane] = gam * a;            // on y_k
+    coef[M1 + lane] = -(a - b);      // on s_k
+  }
+  if (lane == 0) coef[4 * M1] = -gam;  // on g
+}
+
 // Accept the trial point (xt, graw = gradient of f, ft); update the memory and
 // its Gram matrices, form the quasi-Newton direction d = -H g (the two-loop
 // recursion written through S^T g, Y^T g, S^T Y and Y^T Y) and start the next
@@ -437,63 +490,9 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
   if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
   __syncthreads();
   FIT_STAMP(F, 8);
-  // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0:
-  // lane j holds alpha_j and beta_j and the running sum of the terms of the
-  // pairs already done; each step broadcasts the finished alpha_k (beta_k) and
-  // every lane adds its term, with the Gram entries it needs held in registers.
+  // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0
   if (threadIdx.x < PD_WAVE) {
-    const int lane = threadIdx.x;
-    const bool live = lane < L;
-    const int jl = live ? slot[lane] : 0;
-    const double rho_l = live ? rho[jl] : 0.0;
-    const double sg_l = live ? Sg[jl] : 0.0;
-    double row[FIT_MAX_HISTORY];
-    // alpha_j = rho_j (s_j.g - sum_{k>j} alpha_k s_j.y_k)
-#pragma unroll
-    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
-      const int sk = head + k >= M1 ? head + k - M1 : head + k;
-      row[k] = (live && k < L) ? gSY[jl * M1 + sk] : 0.0;
-    }
-    double a = 0.0, pa = 0.0;
-#pragma unroll
-    for (int k = FIT_MAX_HISTORY - 1; k >= 0; --k) {
-      if (k < L) {
-        const double ak = lane_bcast(rho_l * (sg_l - pa), k);
-        if (lane == k) a = ak;
-        pa = __builtin_fma(ak, row[k], pa);
-      }
-    }
-    const double gam = L > 0 ? F.gamma : 1.0;
-    // y_j . q_final = y_j.g - sum_k alpha_k y_j.y_k
-#pragma unroll
-    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
-      const int sk = head + k >= M1 ? head + k - M1 : head + k;
-      row[k] = (live && k < L) ? gYY[jl * M1 + sk] : 0.0;
-    }
-    double yq = live ? Yg[jl] : 0.0;
-#pragma unroll
-    for (int k = 0; k < FIT_MAX_HISTORY; ++k)
-      if (k < L) yq = __builtin_fma(-lane_bcast(a, k), row[k], yq);
-    // beta_j = rho_j (gamma y_j.q_final + sum_{k<j} (alpha_k - beta_k) s_k.y_j)
-#pragma unroll
-    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
-      const int sk = head + k >= M1 ? head + k - M1 : head + k;
-      row[k] = (live && k < L) ? gSY[sk * M1 + jl] : 0.0;
-    }
-    double b = 0.0, pb = 0.0;
-#pragma unroll
-    for (int k = 0; k < FIT_MAX_HISTORY; ++k) {
-      if (k < L) {
-        const double bk = lane_bcast(rho_l * __builtin_fma(gam, yq, pb), k);
-        if (lane == k) b = bk;
-        pb = __builtin_fma(lane_bcast(a, k) - bk, row[k], pb);
-      }
-    }
-    if (live) {
-      coef[lane] = gam * a;            // on y_k
-      coef[M1 + lane] = -(a - b);      // on s_k
-    }
-    if (lane == 0) coef[4 * M1] = -gam;  // on g
+    lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
   }
   __syncthreads();
   FIT_STAMP(F, 9);
@@ -699,11 +698,11 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   else if (act == 3) ls_fail(F, F.prev_t, red);
 }
 
-// Consume a pending accuracy check of the last accepted iterate (thread 0).
-__device__ inline void consume_acc(FitDev &F) {
-  if (*F.assign_pending == 0) return;
+// Consume a pending accuracy check of the last accepted iterate (thread 0;
+// n_correct = the assignment's count).
+__device__ inline void consume_acc(FitDev &F, long long n_correct) {
   *F.assign_pending = 0;
-  F.acc = (double)*F.n_correct / (double)F.n_pix;
+  F.acc = (double)n_correct / (double)F.n_pix;
   if (F.acc >= F.target_acc) {
     F.status = ST_TARGET;
     *F.active = 0;
@@ -724,7 +723,20 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
   constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
-  if (threadIdx.x == 0) consume_acc(F);
+  if (*F.assign_pending != 0) {
+    // the assignment's per-wave counts, summed in a fixed order
+    long long c = 0;
+    for (int t = threadIdx.x; t < F.a_items; t += blockDim.x) c += F.part_c[t];
+    c = pd_wave_sum_i64(c);
+    long long *cw = (long long *)red;
+    if ((threadIdx.x & 63) == 0) cw[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += cw[w];
+      consume_acc(F, tot);
+    }
+  }
   __syncthreads();
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
   if (*F.active == 0) return;
@@ -930,14 +942,17 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.diag_floor = 1e-6;
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
-    f.n_correct = nc + p;
+    f.a_items = M.a_items;
     f.active = flags + p;
     f.assign_pending = flags + n + p;
     xt[p] = f.xt;
     graw[p] = f.graw;
   }
   pd_plan_bind(P, base, xt.data(), phi_t, graw.data(), nullptr, nullptr);
-  for (int p = 0; p < n; ++p) F[p].thc = P.maps[p].thc;
+  for (int p = 0; p < n; ++p) {
+    F[p].thc = P.maps[p].thc;
+    F[p].part_c = P.maps[p].part_c;
+  }
   for (int p = 0; p < n; ++p) P.maps[p].gate = flags + p;
   if (opts->precondition > 0)
     for (int p = 0; p < n; ++p) {
@@ -983,7 +998,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     k_fit_trial<<<n, vt, 0, ss>>>(dF);
     pd_fit_eval(ctx, P, eval_prec, ss);
     k_fit_decide<<<n, vt, 0, ss>>>(dF);
-    pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], ss);
+    pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], false, ss);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1023,7 +1038,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   std::vector<MapDev> fin = amaps;
   for (int p = 0; p < n; ++p) fin[p].gate = nullptr;
   FIT_HIP(ctx, hipMemcpyAsync(d_amaps, fin.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
-  pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], s);
+  pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], true, s);
   std::vector<int64_t> h_nc(n);
   FIT_HIP(ctx, hipMemcpyAsync(h_nc.data(), nc, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
   FIT_HIP(ctx, hipMemcpyAsync(F.data(), dF, sizeof(FitDev) * n, hipMemcpyDeviceToHost, s));

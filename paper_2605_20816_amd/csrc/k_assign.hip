@@ -41,7 +41,26 @@ __device__ inline void assign_block(const MapDev &M, int base, double *sth) {
     __syncthreads();
     for (int e = threadIdx.x; e < cnt * K; e += PD_BLOCK) sth[e] = th[(size_t)i0 * K + e];
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
+    // four grains at a time (independent FMA chains), compared in index order
+    int j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+      double f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[u] = sth[(j + u) * K];
+#pragma unroll
+      for (int k = 1; k < K; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f[u] = __builtin_fma(sth[(j + u) * K + k], psi[k], f[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bad |= __builtin_isnan(f[u]);
+        if (f[u] < fbest) {
+          fbest = f[u];
+          best = i0 + j + u;
+        }
+      }
+    }
+    for (; j < cnt; ++j) {
       const double *tj = sth + j * K;
       double f = tj[0];
 #pragma unroll
@@ -109,7 +128,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_validate(const MapDev *__restrict_
 }
 
 void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
-                      hipStream_t s) {
+                      bool count, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
   switch (dmax) {
     case 2: k_assign<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
@@ -117,7 +136,7 @@ void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_ma
     case 6: k_assign<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
     default: k_assign<8><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
   }
-  k_reduce_count<<<n_maps, PD_BLOCK, 0, s>>>(maps);
+  if (count) k_reduce_count<<<n_maps, PD_BLOCK, 0, s>>>(maps);
 }
 
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s) {
