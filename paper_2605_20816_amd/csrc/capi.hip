@@ -265,10 +265,14 @@ void pd_plan_onehot(const EvalPlan &P, hipStream_t s) {
   pd_launch_onehot(P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.d_offR, P.offR[P.n], s);
 }
 
-void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center) {
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center,
+                  const MapDev *assign_maps) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-  pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  if (assign_maps)
+    pd_launch_lse_assign(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], assign_maps, s);
+  else
+    pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
   if (with_grad)
     pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.with_diag, !P.onehot_pre, s);
   pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, with_grad && P.with_diag, s);

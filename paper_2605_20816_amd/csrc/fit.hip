@@ -576,6 +576,21 @@ __device__ __attribute__((always_inline)) inline void ls_fail(FitDev &F, double 
   __syncthreads();
 }
 
+// Consume a pending accuracy check of the last accepted iterate (thread 0;
+// n_correct = the assignment's count).
+__device__ inline void consume_acc(FitDev &F, long long n_correct) {
+  *F.assign_pending = 0;
+  F.acc = (double)n_correct / (double)F.n_pix;
+  if (F.acc >= F.target_acc) {
+    F.status = ST_TARGET;
+    *F.active = 0;
+    F.clk_target = wall_clock64();
+  } else if (F.phase == PH_STOP) {
+    F.status = ST_BUDGET;
+    *F.active = 0;
+  }
+}
+
 // Shared scratch of the decision kernel.
 #define HS (FIT_MAX_HISTORY + 1)
 #define DEC_SHARED                                  \
@@ -600,7 +615,25 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
   FIT_STAMP(sF, 0);
-  decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
+  // the accuracy check of the last accepted iterate (assigned in this step's
+  // objective launch): its per-wave counts, summed in a fixed order
+  if (*sF.assign_pending != 0) {
+    long long c = 0;
+    for (int t = threadIdx.x; t < sF.a_items; t += blockDim.x) c += sF.part_c[t];
+    c = pd_wave_sum_i64(c);
+    long long *cw = (long long *)red;
+    if ((threadIdx.x & 63) == 0) cw[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += cw[w];
+      consume_acc(sF, tot);
+    }
+    __syncthreads();
+  }
+  // a map that reached the target or its budget keeps its iterate; this
+  // step's evaluation is not used
+  if (sF.status == ST_RUNNING) decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
   __syncthreads();
   FIT_STAMP(sF, 12);
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
@@ -698,24 +731,8 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   else if (act == 3) ls_fail(F, F.prev_t, red);
 }
 
-// Consume a pending accuracy check of the last accepted iterate (thread 0;
-// n_correct = the assignment's count).
-__device__ inline void consume_acc(FitDev &F, long long n_correct) {
-  *F.assign_pending = 0;
-  F.acc = (double)n_correct / (double)F.n_pix;
-  if (F.acc >= F.target_acc) {
-    F.status = ST_TARGET;
-    *F.active = 0;
-    F.clk_target = wall_clock64();
-  } else if (F.phase == PH_STOP) {
-    F.status = ST_BUDGET;
-    *F.active = 0;
-  }
-}
-
-// grid: one block per map.  Finishes the previous step's accuracy check, then
-// forms the trial point xt = x + t d and the evaluation input
-// thc = -(log2 e / eps) (xt - mean_i xt_i).
+// grid: one block per map.  Forms the trial point xt = x + t d and the
+// evaluation input thc = -(log2 e / eps) (xt - mean_i xt_i).
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
   __shared__ double red[MAX_WAVES * 48 + 48];
   __shared__ FitDev sF;
@@ -723,22 +740,6 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
   constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
-  if (*F.assign_pending != 0) {
-    // the assignment's per-wave counts, summed in a fixed order
-    long long c = 0;
-    for (int t = threadIdx.x; t < F.a_items; t += blockDim.x) c += F.part_c[t];
-    c = pd_wave_sum_i64(c);
-    long long *cw = (long long *)red;
-    if ((threadIdx.x & 63) == 0) cw[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      long long tot = 0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += cw[w];
-      consume_acc(F, tot);
-    }
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
   if (*F.active == 0) return;
   const double t = F.t;
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
@@ -820,10 +821,16 @@ void pd_fit_release(pd_ctx *ctx) {
   }
 }
 
-// Objective + gradient of every running map at its trial point.
-static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, hipStream_t s) {
-  if (prec == 2) pd_bf16_plan_eval(ctx, P, s, false);
-  else pd_plan_eval(P, true, s, false);
+// Objective + gradient of every running map at its trial point, and the
+// pending accuracy check of its accepted iterate (amaps).
+static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *amaps,
+                        hipStream_t s) {
+  if (prec == 2) {
+    pd_launch_assign(P.dmax, amaps, P.d_offA, P.n, P.offA[P.n], false, s);
+    pd_bf16_plan_eval(ctx, P, s, false);
+  } else {
+    pd_plan_eval(P, true, s, false, amaps);
+  }
 }
 
 extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
@@ -996,9 +1003,8 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   // ---- one step, captured as a graph
   auto step = [&](hipStream_t ss) {
     k_fit_trial<<<n, vt, 0, ss>>>(dF);
-    pd_fit_eval(ctx, P, eval_prec, ss);
+    pd_fit_eval(ctx, P, eval_prec, d_amaps, ss);
     k_fit_decide<<<n, vt, 0, ss>>>(dF);
-    pd_launch_assign(P.dmax, d_amaps, P.d_offA, n, P.offA[n], false, ss);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -21,6 +21,7 @@
 //   and no atomics: partials per tile are summed in a fixed order by k_reduce_grad,
 //   so results are bitwise reproducible.
 #include "pd_internal.h"
+#include "assign_dev.h"
 
 #include <math.h>
 
@@ -229,6 +230,37 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   PD_DISPATCH_UPTO(DMAX, M.d, (lse_item<T, D>(M, item - off[m], lane)));
+}
+
+// The fit's objective launch: blocks [0, lse_blocks) are k_lse's; the next
+// lse_blocks blocks assign the pixels of the accepted iterate (amaps: theta = x,
+// gated by the pending accuracy check) on otherwise idle compute units, so the
+// check costs no launch of its own.  Both halves share the row-segment work list.
+template <typename T, int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_lse_assign(const MapDev *__restrict__ maps,
+                                                         const int32_t *__restrict__ off,
+                                                         int n_maps, int total,
+                                                         const MapDev *__restrict__ amaps,
+                                                         int lse_blocks) {
+  constexpr int KM = (DMAX + 1) * (DMAX + 2) / 2;
+  __shared__ double sth[AS_CHUNK * KM];
+  if ((int)blockIdx.x < lse_blocks) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+    const int lane = threadIdx.x % PD_WAVE;
+    const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+    if (item >= total) return;
+    const int m = pd_find_map(off, n_maps, item);
+    const MapDev &M = maps[m];
+    if (PD_GATED(M)) return;
+    PD_DISPATCH_UPTO(DMAX, M.d, (lse_item<T, D>(M, item - off[m], lane)));
+  } else {
+    const int item0 = (blockIdx.x - lse_blocks) * PD_WAVES_PER_BLOCK;
+    if (item0 >= total) return;
+    const int m = pd_find_map(off, n_maps, item0);
+    const MapDev &A = amaps[m];
+    if (PD_GATED(A)) return;
+    PD_DISPATCH_UPTO(DMAX, A.d, (assign_block<D>(A, item0 - off[m], sth)));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -642,6 +674,24 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
     case 6: KERNEL<T, 6, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
     default: KERNEL<T, 8, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;         \
   }
+void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                          int total, const MapDev *amaps, hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (dmax > 4) {
+    // the FP64 scores of degree > 4 would raise the objective half's register
+    // count: two launches instead
+    pd_launch_assign(dmax, amaps, off, n_maps, total, false, s);
+    pd_launch_lse(prec, dmax, maps, off, n_maps, total, s);
+    return;
+  }
+  if (prec == 0) {
+    if (dmax <= 2) k_lse_assign<double, 2><<<2 * blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total, amaps, blocks);
+    else k_lse_assign<double, 4><<<2 * blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total, amaps, blocks);
+  } else {
+    if (dmax <= 2) k_lse_assign<float, 2><<<2 * blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total, amaps, blocks);
+    else k_lse_assign<float, 4><<<2 * blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total, amaps, blocks);
+  }
+}
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                     int total, bool diag, bool hot, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;

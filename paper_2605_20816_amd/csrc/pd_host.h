@@ -76,7 +76,10 @@ void pd_plan_tables(const EvalPlan &P, hipStream_t s);
 // Indicator moments of every map when P.onehot_pre (after pd_plan_tables).
 void pd_plan_onehot(const EvalPlan &P, hipStream_t s);
 // center: run k_center (thc from theta); the fit driver forms thc itself.
-void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center);
+// assign_maps: also assign these maps' pixels (same work list) in the
+// objective launch (the fit's accuracy check).
+void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center,
+                  const MapDev *assign_maps = nullptr);
 void pd_plan_assign(const EvalPlan &P, hipStream_t s);
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,

@@ -176,6 +176,10 @@ void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps
                     hipStream_t s);
 void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                    int total, hipStream_t s);
+// k_lse plus, in as many more blocks, the assignment of amaps (same work list);
+// for dmax > 4, k_assign then k_lse.
+void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                          int total, const MapDev *amaps, hipStream_t s);
 // hot: apply the one-hot term in the kernel; otherwise MapDev::onehot must hold
 // the indicator moments (pd_launch_onehot) and the reduction subtracts them.
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
