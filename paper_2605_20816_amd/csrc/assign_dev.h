@@ -82,7 +82,16 @@ __device__ inline void assign_block(const MapDev &M, int base, double *sth) {
     if (M.labels_out) pd_glb(M.labels_out)[jx] = lab;
     correct = (lab == pd_glb(M.labels)[jx]) ? 1 : 0;
   }
+  // one count per block (its four row segments, in wave order)
+  __shared__ long long wcnt[PD_WAVES_PER_BLOCK];
   const long long tot = pd_wave_sum_i64(correct);
-  if (lane == 0) pd_glb(M.part_c)[local] = tot;
+  if (lane == 0) wcnt[wave] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long b = 0;
+#pragma unroll
+    for (int w = 0; w < PD_WAVES_PER_BLOCK; ++w) b += wcnt[w];
+    pd_glb(M.part_c)[base / PD_WAVES_PER_BLOCK] = b;
+  }
 }
 

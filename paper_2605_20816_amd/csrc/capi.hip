@@ -116,6 +116,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.segs = (q.width + PD_WAVE - 1) / PD_WAVE;
     M.eps = q.eps;
     M.grad_scale = 1.0 / (q.eps * (double)q.height * (double)q.width);
+    M.grad_sign = 1.0;
     M.labels = q.labels;
     choose_tiles(M.H, M.W, M.Npad, P.target_waves, M.tile_rows, M.tile_cols);
     M.tiles_r = (M.H + M.tile_rows - 1) / M.tile_rows;
@@ -151,7 +152,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
     R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
-    R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    R.part_c = L.take(sizeof(int64_t) * (M.a_items / PD_WAVES_PER_BLOCK));
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);

@@ -46,8 +46,8 @@ struct FitDev {
   double *x, *g, *d, *xt, *graw, *S, *Y, *rho;
   double *SY, *YY, *Sg, *Yg;  // Gram matrices s_j.y_k, y_j.y_k over the m+1 ring slots; S^T g, Y^T g
   const double *phi_t;
-  const int64_t *part_c;  // per-wave correct counts of the last assignment
-  int32_t a_items;        // their number
+  const int64_t *part_c;  // per-block correct counts of the last assignment
+  int32_t c_items;        // their number
   double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
   double cscale;     // -log2(e) / eps
   int32_t *active, *assign_pending;
@@ -89,21 +89,51 @@ struct FitState {
 #define VG 16
 #define MAX_WAVES (FIT_THREADS / PD_WAVE)
 
+// Per-wave transposition space of the many-value block sums: 8 values x 64
+// lanes per wave.
+__shared__ double fit_xs[MAX_WAVES * 8 * PD_WAVE];
+
 template <int G>
 __device__ __attribute__((always_inline)) inline void blk_sums(double (&v)[G], double *red) {
-#pragma unroll
-  for (int q = 0; q < G; ++q) v[q] = pd_wave_sum(v[q]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  if (nw == 1) return;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0)
+  if constexpr (G < 8) {
 #pragma unroll
-    for (int q = 0; q < G; ++q) red[(threadIdx.x >> 6) * G + q] = v[q];
+    for (int q = 0; q < G; ++q) v[q] = pd_wave_sum(v[q]);
+    if (nw == 1) return;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < G; ++q) red[w * G + q] = v[q];
+  } else {
+    // 8 values at a time: the wave's 64 x 8 values go to LDS; lane l adds the
+    // 8 entries (l & 7) * 8 .. +7 of value l >> 3, and a butterfly over the 8
+    // lanes of its group completes the wave sum (about 35 instructions per 8
+    // values instead of 160 for eight DPP wave sums).
+    double *xs = fit_xs + w * 8 * PD_WAVE;
+    const int q8 = lane >> 3, part = lane & 7;
+    __syncthreads();  // earlier readers of red are done
+#pragma unroll
+    for (int c = 0; c < G; c += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xs[u * PD_WAVE + lane] = c + u < G ? v[c + u] : 0.0;
+      __syncthreads();
+      const double *src = xs + q8 * PD_WAVE + part * 8;
+      double t = src[0];
+#pragma unroll
+      for (int e = 1; e < 8; ++e) t += src[e];
+      t += __shfl_xor(t, 1, PD_WAVE);
+      t += __shfl_xor(t, 2, PD_WAVE);
+      t += __shfl_xor(t, 4, PD_WAVE);
+      if (part == 0 && c + q8 < G) red[w * G + c + q8] = t;
+      __syncthreads();
+    }
+  }
   __syncthreads();
   // value q is summed over the waves (in wave order) by thread q, then shared
   if ((int)threadIdx.x < G) {
     double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[w * G + threadIdx.x];
+    for (int ww = 0; ww < nw; ++ww) t += red[ww * G + threadIdx.x];
     red[MAX_WAVES * 48 + threadIdx.x] = t;
   }
   __syncthreads();
@@ -111,9 +141,23 @@ __device__ __attribute__((always_inline)) inline void blk_sums(double (&v)[G], d
   for (int q = 0; q < G; ++q) v[q] = red[MAX_WAVES * 48 + q];
 }
 
+// Maximum over the wave of a non-negative value (DPP steps as in pd_wave_sum;
+// lanes outside a step's reach contribute 0).
+__device__ inline double wave_max_nonneg(double v) {
+  v = fmax(v, pd_dpp_f64<0x111, 0xf>(v));
+  v = fmax(v, pd_dpp_f64<0x112, 0xf>(v));
+  v = fmax(v, pd_dpp_f64<0x114, 0xf>(v));
+  v = fmax(v, pd_dpp_f64<0x118, 0xf>(v));
+  v = fmax(v, pd_dpp_f64<0x142, 0xa>(v));
+  v = fmax(v, pd_dpp_f64<0x143, 0xc>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Block maximum of a non-negative value.
 __device__ __attribute__((always_inline)) inline double blk_max(double v, double *red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, PD_WAVE));
+  v = wave_max_nonneg(v);
   const int nw = blockDim.x >> 6;
   if (nw == 1) return v;
   __syncthreads();
@@ -122,6 +166,33 @@ __device__ __attribute__((always_inline)) inline double blk_max(double v, double
   double t = 0.0;
   for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
   return t;
+}
+
+// Two block sums and the block maximum of a non-negative value, in one exchange.
+__device__ __attribute__((always_inline)) inline void blk_sums2_max(double (&v)[2], double &mx,
+                                                                    double *red) {
+  v[0] = pd_wave_sum(v[0]);
+  v[1] = pd_wave_sum(v[1]);
+  mx = wave_max_nonneg(mx);
+  const int nw = blockDim.x >> 6;
+  if (nw == 1) return;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    red[3 * w] = v[0];
+    red[3 * w + 1] = v[1];
+    red[3 * w + 2] = mx;
+  }
+  __syncthreads();
+  double a = 0.0, b = 0.0, m = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    a += red[3 * w];
+    b += red[3 * w + 1];
+    m = fmax(m, red[3 * w + 2]);
+  }
+  v[0] = a;
+  v[1] = b;
+  mx = m;
 }
 
 // v <- projection of v onto the gauge-fixed subspace (in place).
@@ -176,8 +247,7 @@ __device__ __attribute__((always_inline)) inline void pass_gstats(FitDev &F, dou
     v[1] = __builtin_fma(gi, F.d[i], v[1]);
     mx = fmax(mx, fabs(gi));
   }
-  blk_sums<2>(v, red);
-  mx = blk_max(mx, red);
+  blk_sums2_max(v, mx, red);
   if (threadIdx.x == 0) {
     F.gg = v[0];
     F.dphi0 = v[1];
@@ -323,7 +393,9 @@ __device__ __attribute__((always_inline)) inline int slot_pass(
       acc[4 * U + u] = __builtin_fma(yw, Yj, acc[4 * U + u]);
     }
   }
+  if (k0 == 0) FIT_STAMP(F, 13);
   blk_sums<5 * U>(acc, red);
+  if (k0 == 0) FIT_STAMP(F, 14);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -514,17 +586,17 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     const double gi = pg[i];
     // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
     double dy = cg * gi, ds = 0.0;
-    // slots in blocks of 8: the 16 loads of a block are issued before use
-    for (int k0 = 0; k0 < L; k0 += 8) {
-      double yv[8], sv[8];
+    // slots in blocks of 16: the 32 loads of a block are issued before use
+    for (int k0 = 0; k0 < L; k0 += 16) {
+      double yv[16], sv[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int j = slot[min(k0 + u, L - 1)];
         yv[u] = pY[(size_t)j * n + i];
         sv[u] = pS[(size_t)j * n + i];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 16; ++u)
         if (k0 + u < L) {
           dy = __builtin_fma(coef[k0 + u], yv[u], dy);
           ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
@@ -536,8 +608,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     v[1] = __builtin_fma(gi, di, v[1]);
     mx = fmax(mx, fabs(gi));
   }
-  blk_sums<2>(v, red);
-  mx = blk_max(mx, red);
+  blk_sums2_max(v, mx, red);
   if (threadIdx.x == 0) {
     F.gg = v[0];
     F.dphi0 = v[1];
@@ -616,10 +687,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   __syncthreads();
   FIT_STAMP(sF, 0);
   // the accuracy check of the last accepted iterate (assigned in this step's
-  // objective launch): its per-wave counts, summed in a fixed order
+  // objective launch): its per-block counts, summed in a fixed order
   if (*sF.assign_pending != 0) {
     long long c = 0;
-    for (int t = threadIdx.x; t < sF.a_items; t += blockDim.x) c += sF.part_c[t];
+    for (int t = threadIdx.x; t < sF.c_items; t += blockDim.x) c += sF.part_c[t];
     c = pd_wave_sum_i64(c);
     long long *cw = (long long *)red;
     if ((threadIdx.x & 63) == 0) cw[threadIdx.x >> 6] = c;
@@ -643,9 +714,8 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
                             double *coef, double *gSY, double *gYY, int *action_p) {
   int &action = *action_p;
   const int n = F.NK;
-  // gradient of f = -Phi at xt, gauge-projected, in graw
-  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) F.graw[i] = -F.graw[i];
-  __syncthreads();
+  // gradient of f = -Phi at xt (the reduction writes it with grad_sign = -1),
+  // gauge-projected, in graw
   blk_gauge(F, F.graw, red);
   FIT_STAMP(F, 1);
   const double ft = -*F.phi_t;
@@ -949,7 +1019,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.diag_floor = 1e-6;
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
-    f.a_items = M.a_items;
+    f.c_items = M.a_items / PD_WAVES_PER_BLOCK;
     f.active = flags + p;
     f.assign_pending = flags + n + p;
     xt[p] = f.xt;
@@ -960,7 +1030,10 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     F[p].thc = P.maps[p].thc;
     F[p].part_c = P.maps[p].part_c;
   }
-  for (int p = 0; p < n; ++p) P.maps[p].gate = flags + p;
+  for (int p = 0; p < n; ++p) {
+    P.maps[p].gate = flags + p;
+    P.maps[p].grad_sign = -1.0;  // the evaluation returns the gradient of f = -Phi
+  }
   if (opts->precondition > 0)
     for (int p = 0; p < n; ++p) {
       P.maps[p].diag = (double *)F[p].diag;

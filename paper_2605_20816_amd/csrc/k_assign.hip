@@ -23,7 +23,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce_count(const MapDev *__restr
   if (M.n_correct == nullptr || PD_GATED(M)) return;
   __shared__ long long red[PD_BLOCK];
   long long s = 0;
-  for (int t = threadIdx.x; t < M.a_items; t += PD_BLOCK) s += M.part_c[t];
+  for (int t = threadIdx.x; t < M.a_items / PD_WAVES_PER_BLOCK; t += PD_BLOCK) s += M.part_c[t];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {

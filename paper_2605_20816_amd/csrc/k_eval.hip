@@ -579,7 +579,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ 
   const MapDev &M = maps[m];
   if (M.grad == nullptr || PD_GATED(M)) return;
   if (!diag) {
-    reduce_grad_block(M, b - off[m], M.part_g, M.onehot, M.grad, M.grad_scale);
+    reduce_grad_block(M, b - off[m], M.part_g, M.onehot, M.grad, M.grad_scale * M.grad_sign);
   } else {
     if (M.diag == nullptr || M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
     reduce_grad_block(M, b - off[m], M.part_d, nullptr, M.diag, M.grad_scale / M.eps);

@@ -507,7 +507,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict_
     if (ph < w) red[ph][ol] += red[ph + w][ol];
     __syncthreads();
   }
-  if (ph == 0 && o < M.N * M.K) M.grad[o] = red[0][ol] * M.grad_scale;
+  if (ph == 0 && o < M.N * M.K) M.grad[o] = red[0][ol] * (M.grad_scale * M.grad_sign);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,7 @@ struct MapDev {
   int32_t segs;                     // ceil(W / 64): 64-pixel row segments
   double eps;
   double grad_scale;                // 1 / (eps * n)
+  double grad_sign;                 // +1: grad = dPhi/dtheta; -1: its negative (the fit's f = -Phi)
   const int32_t *labels;            // n
   const double *theta;              // N x K
   double *grad;                     // N x K or null
@@ -51,7 +52,7 @@ struct MapDev {
   // assignment
   int32_t *labels_out;              // n or null
   int64_t *n_correct;               // -> n_correct_out[map] or null
-  int64_t *part_c;                  // [a_items] per-wave correct counts
+  int64_t *part_c;                  // [a_items / 4] per-block correct counts
   // optional gate: when non-null and zero, every kernel skips this map
   const int32_t *gate;
   // FP32 row table and the BF16 matrix-core path
