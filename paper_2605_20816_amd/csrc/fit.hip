@@ -2,9 +2,11 @@
 //
 // Maximises Phi (minimises f = -Phi) for a batch of maps.  All vectors, the
 // L-BFGS memory and the line-search state live on the device; one "step" is a
-// fixed sequence of kernels -- trial point, objective+gradient, decision,
-// assignment, accuracy check -- captured once as a HIP graph and replayed.  The
-// host only polls a per-map activity flag every few replays.
+// fixed sequence of kernels -- objective+gradient at the trial point (with the
+// pending accuracy check of the accepted iterate in the same launch), then the
+// decision, which also forms the next trial point -- captured once as a HIP
+// graph and replayed.  The host only polls a per-map activity flag every few
+// replays.
 //
 // Algorithm (the paper names L-BFGS [Liu-Nocedal 1989] and nothing more; these
 // are the library's documented choices): memory m, H0 = gamma I with
@@ -34,6 +36,7 @@
 #define LS_MAX_EVALS 20
 #define CURV_EPS 1e-10
 #define FIT_MAX_HISTORY 32
+#define FIT_GRAPH_STEPS 4
 
 enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
 enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
@@ -647,6 +650,31 @@ __device__ __attribute__((always_inline)) inline void ls_fail(FitDev &F, double 
   __syncthreads();
 }
 
+// The trial point xt = x + t d and the evaluation input
+// thc = -(log2 e / eps) (xt - mean_i xt_i) (all threads of the map's block).
+__device__ __attribute__((always_inline)) inline void form_trial(FitDev &F, double t, double *red) {
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
+  __syncthreads();
+  for (int k0 = 0; k0 < F.K; k0 += VG) {
+    double sm[VG];
+#pragma unroll
+    for (int q = 0; q < VG; ++q) sm[q] = 0.0;
+    const int cnt = min(VG, F.K - k0);
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
+#pragma unroll
+      for (int q = 0; q < VG; ++q)
+        if (q < cnt) sm[q] += F.xt[(size_t)i * F.K + k0 + q];
+    blk_sums<VG>(sm, red);
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
+#pragma unroll
+      for (int q = 0; q < VG; ++q)
+        if (q < cnt) {
+          const size_t e = (size_t)i * F.K + k0 + q;
+          F.thc[e] = F.cscale * (F.xt[e] - sm[q] / (double)F.N);
+        }
+  }
+}
+
 // Consume a pending accuracy check of the last accepted iterate (thread 0;
 // n_correct = the assignment's count).
 __device__ inline void consume_acc(FitDev &F, long long n_correct) {
@@ -705,6 +733,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   // a map that reached the target or its budget keeps its iterate; this
   // step's evaluation is not used
   if (sF.status == ST_RUNNING) decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
+  __syncthreads();
+  // the next evaluation's input, while the state is at hand
+  if (sF.status == ST_RUNNING) form_trial(sF, sF.t, red);
   __syncthreads();
   FIT_STAMP(sF, 12);
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
@@ -801,39 +832,6 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   else if (act == 3) ls_fail(F, F.prev_t, red);
 }
 
-// grid: one block per map.  Forms the trial point xt = x + t d and the
-// evaluation input thc = -(log2 e / eps) (xt - mean_i xt_i).
-__global__ __launch_bounds__(FIT_THREADS) void k_fit_trial(FitDev *Fs) {
-  __shared__ double red[MAX_WAVES * 48 + 48];
-  __shared__ FitDev sF;
-  FitDev &F = sF;
-  constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
-  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
-  __syncthreads();
-  if (*F.active == 0) return;
-  const double t = F.t;
-  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
-  __syncthreads();
-  for (int k0 = 0; k0 < F.K; k0 += VG) {
-    double sm[VG];
-#pragma unroll
-    for (int q = 0; q < VG; ++q) sm[q] = 0.0;
-    const int cnt = min(VG, F.K - k0);
-    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
-#pragma unroll
-      for (int q = 0; q < VG; ++q)
-        if (q < cnt) sm[q] += F.xt[(size_t)i * F.K + k0 + q];
-    blk_sums<VG>(sm, red);
-    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
-#pragma unroll
-      for (int q = 0; q < VG; ++q)
-        if (q < cnt) {
-          const size_t e = (size_t)i * F.K + k0 + q;
-          F.thc[e] = F.cscale * (F.xt[e] - sm[q] / (double)F.N);
-        }
-  }
-}
-
 // Start of the fit on the device clock (before any warm start work).
 __global__ void k_fit_stamp(FitDev *Fs, int n_maps) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -872,6 +870,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     *F.assign_pending = 0;
     if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
   }
+  // the first evaluation is at the start itself
+  form_trial(F, 0.0, red);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1073,16 +1073,16 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   k_fit_init<<<n, vt, 0, s>>>(dF, zero_start ? 1 : 0);
   FIT_HIP(ctx, hipGetLastError());
 
-  // ---- one step, captured as a graph
+  // ---- FIT_GRAPH_STEPS steps, captured as one graph (a graph launch has a
+  // fixed cost at its boundary; the steps after a map stops are gated off)
   auto step = [&](hipStream_t ss) {
-    k_fit_trial<<<n, vt, 0, ss>>>(dF);
     pd_fit_eval(ctx, P, eval_prec, d_amaps, ss);
     k_fit_decide<<<n, vt, 0, ss>>>(dF);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   FIT_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  step(s);
+  for (int k = 0; k < FIT_GRAPH_STEPS; ++k) step(s);
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (ce != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
   ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1095,10 +1095,11 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   FIT_HIP(ctx, hipHostMalloc((void **)&h_flags, sizeof(int32_t) * n, hipHostMallocDefault));
   const long long max_steps = (long long)(opts->max_iter + 2) * (2 * LS_MAX_EVALS + 4) + 8;
   long long steps = 0;
-  int poll = 2;
+  int poll = 1;
   hipError_t le = hipSuccess;
   while (steps < max_steps) {
-    for (int k = 0; k < poll && le == hipSuccess; ++k, ++steps) le = hipGraphLaunch(exec, s);
+    for (int k = 0; k < poll && le == hipSuccess; ++k, steps += FIT_GRAPH_STEPS)
+      le = hipGraphLaunch(exec, s);
     if (le != hipSuccess) break;
     le = hipMemcpyAsync(h_flags, flags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
     if (le != hipSuccess) break;
@@ -1107,7 +1108,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     bool any = false;
     for (int p = 0; p < n; ++p) any |= h_flags[p] != 0;
     if (!any) break;
-    if (poll < 16) poll *= 2;
+    if (poll * FIT_GRAPH_STEPS < 16) poll *= 2;
   }
   (void)hipGraphExecDestroy(exec);
   (void)hipGraphDestroy(graph);

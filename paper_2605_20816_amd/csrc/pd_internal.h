@@ -192,8 +192,8 @@ void pd_launch_onehot(int dmax, const MapDev *maps, const int32_t *off_b, int n_
 void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int blocks_r,
                       bool grad, bool diag, hipStream_t s);
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s);
-// count: also sum the per-wave counts into n_correct (k_reduce_count); the fit
-// step sums them in its next trial kernel instead.
+// count: also sum the per-block counts into n_correct (k_reduce_count); the
+// fit's decision kernel sums them itself.
 void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       bool count, hipStream_t s);
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);
