@@ -534,16 +534,14 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const doubl
     const int i = o / M.K, k = o - i * M.K;
     const auto src = pd_glb(part + (size_t)i * M.K + k);
     const size_t stride = (size_t)M.Npad * M.K;
+    // 8 loads in flight per thread, added in tile order
     int t = ph;
-    for (; t + 3 * RG_PH < tiles; t += 4 * RG_PH) {
-      const double v0 = src[(size_t)t * stride];
-      const double v1 = src[(size_t)(t + RG_PH) * stride];
-      const double v2 = src[(size_t)(t + 2 * RG_PH) * stride];
-      const double v3 = src[(size_t)(t + 3 * RG_PH) * stride];
-      s += v0;
-      s += v1;
-      s += v2;
-      s += v3;
+    for (; t + 7 * RG_PH < tiles; t += 8 * RG_PH) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(t + u * RG_PH) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
     }
     for (; t < tiles; t += RG_PH) s += src[(size_t)t * stride];
   }
