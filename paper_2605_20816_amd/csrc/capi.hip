@@ -123,7 +123,13 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.tiles_c = (M.W + M.tile_cols - 1) / M.tile_cols;
     // row-segment items, padded to whole blocks so a block never spans two maps
     M.a_items = (M.H * M.segs + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
-    M.b_items = M.tiles_r * M.tiles_c * (M.Npad / PD_WAVE);
+    // gradient work list: super-tiles of 4 tiles (block-summed partials) for
+    // degree <= 4, else one tile per partial (a property of the map alone, so a
+    // map's result does not depend on its batch)
+    M.st_size = q.degree <= 4 ? PD_WAVES_PER_BLOCK : 1;
+    M.stiles = (M.tiles_r * M.tiles_c + M.st_size - 1) / M.st_size;
+    M.b_items = (M.stiles * M.st_size * (M.Npad / PD_WAVE) + PD_WAVES_PER_BLOCK - 1) /
+                PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
     M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
     const long long n_px = (long long)M.H * M.W;
     const bool mf = prec == 2;
@@ -150,8 +156,8 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.C = L.take(mf ? 0 : tsz * (size_t)M.H * M.Npad * M.DP);
     R.lse = L.take(mf ? 0 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
-    R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
-    R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.tiles_r * M.tiles_c * M.Npad * M.K);
+    R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
+    R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
     R.part_c = L.take(sizeof(int64_t) * (M.a_items / PD_WAVES_PER_BLOCK));
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);

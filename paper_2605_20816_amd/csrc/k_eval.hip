@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 template <typename T> __device__ inline T pd_exp2(T x);
 template <> __device__ inline float pd_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 // FP64 2^t for t <= 0 (the only arguments the kernels form: a logit minus a
@@ -264,6 +266,77 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse_assign(const MapDev *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Gradient work list.  With M.st_size = 4 (maps of degree <= 4), a block's
+// four waves take four consecutive pixel tiles (a "super-tile") of one 64-grain
+// group; each wave parks its per-lane moments in LDS and the block adds them as
+// ((w0 + w2) + (w1 + w3)) before one write, so the partials hold one entry per
+// super-tile.  With st_size = 1 every wave writes its tile's partial itself.
+// Waves past the last tile add zeros.
+#define PD_ST_KMAX 15  // K of degree 4: the largest that uses super-tiles
+template <int DMAX>
+constexpr int pd_st_k() { return (DMAX + 1) * (DMAX + 2) / 2 < PD_ST_KMAX ? (DMAX + 1) * (DMAX + 2) / 2 : PD_ST_KMAX; }
+
+struct GradItem {
+  int st;      // super-tile (the tile when st_size = 1)
+  int gbase;   // first grain of the group
+  int r0, r1, c0, c1;
+};
+__device__ inline GradItem grad_item_of(const MapDev &M, int local) {
+  const int groups = M.Npad / PD_WAVE;
+  const int S = M.st_size;
+  const int bl = local / S;
+  const int w = local - bl * S;
+  GradItem g;
+  g.st = bl / groups;
+  g.gbase = (bl - g.st * groups) * PD_WAVE;
+  const int tile = g.st * S + w;
+  if (tile >= M.tiles_r * M.tiles_c) {
+    g.r0 = g.r1 = g.c0 = g.c1 = 0;
+    return g;
+  }
+  const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
+  g.r0 = tr * M.tile_rows;
+  g.r1 = min(g.r0 + M.tile_rows, M.H);
+  g.c0 = tcol * M.tile_cols;
+  g.c1 = min(g.c0 + M.tile_cols, M.W);
+  return g;
+}
+
+// One wave's K moments: to its LDS slot (st_size 4, sh = 4 * 64 * K doubles)
+// or straight to the partials (st_size 1).
+template <int K>
+__device__ inline void grad_emit(const MapDev &M, const GradItem &it, const double (&q)[K],
+                                 double *part, double *sh, int lane) {
+  if (K > PD_ST_KMAX || M.st_size == 1) {
+    if (it.st >= M.stiles) return;  // padding items at the end of the map's list
+    const auto out = pd_glb(part + ((size_t)it.st * M.Npad + it.gbase + lane) * K);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = q[k];
+  } else if constexpr (K <= PD_ST_KMAX) {
+    const int w = threadIdx.x / PD_WAVE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[(w * K + k) * PD_WAVE + lane] = q[k];
+  }
+}
+
+// The block's sum of the four waves' slots, written by wave 0 (st_size 4; every
+// wave of the block calls it).
+__device__ inline void grad_block_sum(const MapDev &M, int local, double *part, const double *sh,
+                                      int lane) {
+  __syncthreads();
+  if (threadIdx.x >= PD_WAVE) return;
+  const GradItem it = grad_item_of(M, local);
+  if (it.st >= M.stiles) return;
+  const int K = M.K;
+  const auto out = pd_glb(part + ((size_t)it.st * M.Npad + it.gbase + lane) * K);
+  for (int k = 0; k < K; ++k) {
+    const double a = sh[(0 * K + k) * PD_WAVE + lane] + sh[(2 * K + k) * PD_WAVE + lane];
+    const double b = sh[(1 * K + k) * PD_WAVE + lane] + sh[(3 * K + k) * PD_WAVE + lane];
+    out[k] = a + b;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel B: partial gradient moments per (pixel tile, 64-grain group).
 // Columns are processed 8 at a time so the wave-uniform column data (P_a(x1),
 // lse, label) arrives in a few wide scalar loads per chunk.  The one-hot part
@@ -325,17 +398,13 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
 }
 
 template <typename T, int D, bool DIAG, bool HOT>
-__device__ inline void grad_item(const MapDev &M, int local, int lane) {
+__device__ inline void grad_item(const MapDev &M, int local, int lane, double *sh) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
   constexpr int CH = 8;
-  const int groups = M.Npad / PD_WAVE;
-  const int tile = local / groups;
-  const int grp = local - tile * groups;
-  const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
-  const int r0 = tr * M.tile_rows, r1 = min(r0 + M.tile_rows, M.H);
-  const int c0 = tcol * M.tile_cols, c1 = min(c0 + M.tile_cols, M.W);
-  const int gbase = grp * PD_WAVE;
+  const GradItem it = grad_item_of(M, local);
+  const int r0 = it.r0, r1 = it.r1, c0 = it.c0, c1 = it.c1;
+  const int gbase = it.gbase;
   const int i = gbase + lane;
   double q[K], qd[DIAG ? K : 1];
 #pragma unroll
@@ -371,13 +440,10 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane) {
       }
     }
   }
-  const auto out = pd_glb(M.part_g + ((size_t)tile * M.Npad + i) * K);
-#pragma unroll
-  for (int k = 0; k < K; ++k) out[k] = q[k];
-  if (DIAG) {
-    const auto outd = pd_glb(M.part_d + ((size_t)tile * M.Npad + i) * K);
-#pragma unroll
-    for (int k = 0; k < K; ++k) outd[k] = qd[k];
+  grad_emit<K>(M, it, q, M.part_g, sh, lane);
+  if constexpr (DIAG) {
+    const double (&qdk)[K] = qd;
+    grad_emit<K>(M, it, qdk, M.part_d, sh + 4 * PD_WAVE * K, lane);
   }
 }
 
@@ -394,7 +460,9 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ ma
   if (PD_GATED(M)) return;
   // evaluations that also want the Hessian diagonal go to k_grad_diag
   if (M.want_diag != nullptr && *pd_uni(M.want_diag) != 0) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, false, HOT>(M, item - off[m], lane)));
+  __shared__ double sh[4 * PD_WAVE * pd_st_k<DMAX>()];
+  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, false, HOT>(M, item - off[m], lane, sh)));
+  if (M.st_size == 4) grad_block_sum(M, item - off[m], M.part_g, sh, lane);
 }
 
 // The same work list, for maps whose want_diag is set: gradient partials plus
@@ -404,40 +472,45 @@ template <typename T, int DMAX, bool HOT>
 __global__ __launch_bounds__(PD_BLOCK) void k_grad_diag(const MapDev *__restrict__ maps,
                                                         const int32_t *__restrict__ off,
                                                         int n_maps, int total) {
+  // A small grid strides over the work list: most steps refresh no map, and
+  // the LDS of this kernel would make a full grid of idle blocks expensive.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
-  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
-  if (item >= total) return;
-  const int m = pd_find_map(off, n_maps, item);
-  const MapDev &M = maps[m];
-  if (PD_GATED(M)) return;
-  if (M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true, HOT>(M, item - off[m], lane)));
+  __shared__ double sh[8 * PD_WAVE * pd_st_k<DMAX>()];
+  const int nblocks = total / PD_WAVES_PER_BLOCK;  // every map's list is whole blocks
+  for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int item = b * PD_WAVES_PER_BLOCK + wave;
+    const int m = pd_find_map(off, n_maps, item);
+    const MapDev &M = maps[m];
+    if (PD_GATED(M)) continue;
+    if (M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) continue;
+    PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true, HOT>(M, item - off[m], lane, sh)));
+    if (M.st_size == 4) {
+      grad_block_sum(M, item - off[m], M.part_g, sh, lane);
+      grad_block_sum(M, item - off[m], M.part_d, sh + 4 * PD_WAVE * M.K, lane);
+      __syncthreads();  // sh is reused by the next block of the list
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Indicator moments onehot[i][k] = sum over the pixels x with G(x) = i of
-// psi_k(x), in FP64 from the canonical tables, as partials per (tile, 64-grain
-// group) in part_g (the gradient's work list and layout).  The wave takes the
+// psi_k(x), in FP64 from the canonical tables, as partials per (super-tile,
+// 64-grain group) in part_g (the gradient's work list and layout).  The wave takes the
 // tile 64 columns at a time (one per lane) and its rows 8 at a time (their
 // labels loaded together); for each grain of this group present in a row
 // segment, a wave sum of P_a(x1) over that grain's pixels goes to the grain's
 // lane and is folded with P_b(x2).  Labels outside [gbase, gbase + 64) are
 // skipped.  Every sum has a fixed order.
 template <int D>
-__device__ inline void onehot_item(const MapDev &M, int local, int lane) {
+__device__ inline void onehot_item(const MapDev &M, int local, int lane, double *sh) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
   constexpr int RB = 8;
-  const int groups = M.Npad / PD_WAVE;
-  const int tile = local / groups;
-  const int grp = local - tile * groups;
-  const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
-  const int r0 = tr * M.tile_rows, r1 = min(r0 + M.tile_rows, M.H);
-  const int c0 = tcol * M.tile_cols, c1 = min(c0 + M.tile_cols, M.W);
-  const int gbase = grp * PD_WAVE;
-  const int i = gbase + lane;
-  double q[K];
+  const GradItem it = grad_item_of(M, local);
+  const int r0 = it.r0, r1 = it.r1, c0 = it.c0, c1 = it.c1;
+  const int gbase = it.gbase;
+    double q[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) q[k] = 0.0;
   for (int cs = c0; cs < c1; cs += PD_WAVE) {
@@ -483,9 +556,7 @@ __device__ inline void onehot_item(const MapDev &M, int local, int lane) {
       }
     }
   }
-  const auto out = pd_glb(M.part_g + ((size_t)tile * M.Npad + i) * K);
-#pragma unroll
-  for (int k = 0; k < K; ++k) out[k] = q[k];
+  grad_emit<K>(M, it, q, M.part_g, sh, lane);
 }
 
 template <int DMAX>
@@ -498,7 +569,9 @@ __global__ __launch_bounds__(PD_BLOCK) void k_onehot(const MapDev *__restrict__ 
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
-  PD_DISPATCH_UPTO(DMAX, M.d, (onehot_item<D>(M, item - off[m], lane)));
+  __shared__ double sh[4 * PD_WAVE * pd_st_k<DMAX>()];
+  PD_DISPATCH_UPTO(DMAX, M.d, (onehot_item<D>(M, item - off[m], lane, sh)));
+  if (M.st_size == 4) grad_block_sum(M, item - off[m], M.part_g, sh, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +601,7 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const doubl
   const int ol = threadIdx.x % RG_OUT, ph = threadIdx.x / RG_OUT;
   const int o = chunk * RG_OUT + ol;
   const int NK = M.N * M.K;
-  const int tiles = M.tiles_r * M.tiles_c;
+  const int tiles = M.stiles;  // one partial per super-tile (per tile if st_size = 1)
   double s = 0.0;
   if (o < NK) {
     const int i = o / M.K, k = o - i * M.K;
@@ -696,8 +769,9 @@ void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, 
   if (prec == 0) PD_LAUNCH_GRAD(k_grad, double, dmax, hot, blocks, s, maps, off, n_maps, total);
   else PD_LAUNCH_GRAD(k_grad, float, dmax, hot, blocks, s, maps, off, n_maps, total);
   if (diag) {
-    if (prec == 0) PD_LAUNCH_GRAD(k_grad_diag, double, dmax, hot, blocks, s, maps, off, n_maps, total);
-    else PD_LAUNCH_GRAD(k_grad_diag, float, dmax, hot, blocks, s, maps, off, n_maps, total);
+    const int dblocks = std::min(blocks, 1024);
+    if (prec == 0) PD_LAUNCH_GRAD(k_grad_diag, double, dmax, hot, dblocks, s, maps, off, n_maps, total);
+    else PD_LAUNCH_GRAD(k_grad_diag, float, dmax, hot, dblocks, s, maps, off, n_maps, total);
   }
 }
 void pd_launch_onehot(int dmax, const MapDev *maps, const int32_t *off_b, int n_maps, int total,

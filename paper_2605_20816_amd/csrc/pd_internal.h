@@ -39,7 +39,7 @@ struct MapDev {
   void *C;                          // [H][Npad][DP] row coefficients, evaluation type
   void *lse;                        // [n] base-2 log-sum-exp per pixel, evaluation type
   double *part_l;                   // [a_items] per-wave partial sums of log2 p_G
-  double *part_g;                   // [tiles][Npad][K] partial sums of (p - delta) psi, or of
+  double *part_g;                   // [stiles][Npad][K] partial sums of (p - delta) psi, or of
                                     // p psi when onehot is set
   double *onehot;                   // [N][K] sum of psi over each grain's pixels (FP64), or
                                     // null when the gradient kernel applies the one-hot term
@@ -47,7 +47,8 @@ struct MapDev {
   int32_t tile_rows, tile_cols, tiles_r, tiles_c;
   // work-item counts and offsets inside the batched launches
   int32_t a_items, a_off;           // row-segment items (objective, assignment)
-  int32_t b_items, b_off;           // gradient items: tiles * (Npad / 64)
+  int32_t b_items, b_off;           // gradient items: st_size * stiles * (Npad / 64)
+  int32_t st_size, stiles;          // tiles per super-tile (4 for degree <= 4, else 1); super-tiles
   int32_t r_items, r_off;           // reduction items: ceil(N*K / 256) blocks
   // assignment
   int32_t *labels_out;              // n or null
@@ -67,7 +68,7 @@ struct MapDev {
   // computed by the gradient kernels when want_diag is non-null and set
   const int32_t *want_diag;
   double *diag;                     // N x K or null
-  double *part_d;                   // [tiles][Npad][K] partial sums (FP64/FP32 paths)
+  double *part_d;                   // [stiles][Npad][K] partial sums (FP64/FP32 paths)
 };
 
 
