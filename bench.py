@@ -66,8 +66,8 @@ def traffic_from_profile(kernel: str):
 def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
     """Plain (FP64, theta = 0, history 10, one map per call) against accelerated
     (one batched call with autotuned tiles; reduced precision; longer memory; the
-    diagonal preconditioner where the precision allows it; accuracy checked every
-    4 iterations; with and without the learned warm start) fits of c4-style maps
+    diagonal preconditioner; accuracy checked every 4 iterations; with and
+    without the learned warm start) fits of c4-style maps
     to 99% pixel accuracy.  Times are from each fit call's start to the iterate
     that reaches 99% (for the batch: the last of the maps the plain method also
     brings to 99%)."""
@@ -106,7 +106,7 @@ def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
            "plain": "FP64, theta0=0, L-BFGS memory 10, one map per pd_fit call",
            "target_acc": 0.99, "budget_iters": 2000}
     # accelerated: one batched call; tiles autotuned for the batch; longer memory;
-    # the diagonal preconditioner (FP32/FP64 only); accuracy checked every 4 iterations
+    # the diagonal preconditioner; accuracy checked every 4 iterations
     tune_s = {}
     for prec in ("fp32", "bf16"):
         t0 = time.perf_counter()
@@ -116,11 +116,10 @@ def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
     out["autotune_seconds_included"] = tune_s
     fast = dict(history=16, precondition=20, check_every=4)
     variants = [("accelerated_fp32", "fp32", "zero", None, fast),
-                ("accelerated_bf16", "bf16", "zero", None, dict(history=32, check_every=4))]
+                ("accelerated_bf16", "bf16", "zero", None, fast)]
     if with_net:
         variants.append(("accelerated_fp32_mlp", "fp32", "mlp", pdl.Mlp(nets), fast))
-        variants.append(("accelerated_bf16_mlp", "bf16", "mlp", pdl.Mlp(nets),
-                         dict(history=32, check_every=4)))
+        variants.append(("accelerated_bf16_mlp", "bf16", "mlp", pdl.Mlp(nets), fast))
     for name, prec, init, mlp, kw in variants:
         reps = ctx.fit(probs, zeros(probs), prec, init=init, mlp=mlp, max_iter=2000,
                        target_acc=0.99, **kw)

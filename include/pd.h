@@ -261,7 +261,8 @@ typedef struct {
                              diagonal of pd_hessian_diag taken at the start and at
                              every T-th accepted iterate, gamma = s.y / y.Dinv y of
                              the newest pair, every search starting at t = 1.
-                             Gauge PD_GAUGE_LAST_ZERO, PD_FP64 or PD_FP32.         */
+                             Gauge PD_GAUGE_LAST_ZERO.  With PD_BF16, D comes
+                             from an FP32 evaluation at the refresh iterates.      */
 } pd_fit_opts;
 
 typedef struct {

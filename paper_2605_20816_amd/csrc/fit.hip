@@ -238,6 +238,7 @@ __device__ inline double cubic_min(double a, double fa, double da, double b, dou
 __device__ inline void fit_stop(FitDev &F, int status) {
   F.status = status;
   *F.active = 0;
+  if (F.want_diag) *F.want_diag = 0;
 }
 
 // ||g||^2, ||g||_inf and g.d of the current iterate (one pass).
@@ -684,9 +685,11 @@ __device__ inline void consume_acc(FitDev &F, long long n_correct) {
     F.status = ST_TARGET;
     *F.active = 0;
     F.clk_target = wall_clock64();
+    if (F.want_diag) *F.want_diag = 0;
   } else if (F.phase == PH_STOP) {
     F.status = ST_BUDGET;
     *F.active = 0;
+    if (F.want_diag) *F.want_diag = 0;
   }
 }
 
@@ -894,10 +897,13 @@ void pd_fit_release(pd_ctx *ctx) {
 // Objective + gradient of every running map at its trial point, and the
 // pending accuracy check of its accepted iterate (amaps).
 static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *amaps,
-                        hipStream_t s) {
+                        const EvalPlan *Pdiag, hipStream_t s) {
   if (prec == 2) {
     pd_launch_assign(P.dmax, amaps, P.d_offA, P.n, P.offA[P.n], false, s);
     pd_bf16_plan_eval(ctx, P, s, false);
+    // the preconditioner's Hessian diagonal: an FP32 evaluation of the maps
+    // whose refresh flag is set (its gate), at the same trial point
+    if (Pdiag) pd_plan_eval(*Pdiag, true, s, false);
   } else {
     pd_plan_eval(P, true, s, false, amaps);
   }
@@ -936,8 +942,6 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     for (int p = 0; p < n; ++p)
       if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
   if (opts->precondition < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "precondition must be >= 0");
-  if (opts->precondition > 0 && prec == 2)
-    return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the diagonal preconditioner needs PD_FP64 or PD_FP32");
   if (opts->precondition > 0 && opts->gauge != PD_GAUGE_LAST_ZERO)
     return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the diagonal preconditioner keeps PD_GAUGE_LAST_ZERO");
   pd_status st = pd_validate(ctx, probs, n, stream);
@@ -975,6 +979,19 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   const size_t o_phi = L.take(sizeof(double) * n);
   const size_t o_nc = L.take(sizeof(int64_t) * n);
   const size_t o_amaps = L.take(sizeof(MapDev) * n);
+  // BF16 with the preconditioner: an FP32 plan for the Hessian diagonal, gated
+  // by each map's refresh flag (its gradient and objective go to scratch)
+  const bool diag_plan = prec == 2 && opts->precondition > 0;
+  EvalPlan P2;
+  size_t o_phi2 = 0;
+  std::vector<size_t> o_g2(n);
+  if (diag_plan) {
+    P2.target_waves = pd_tuned_waves(ctx, probs, n, 1);
+    P2.with_diag = true;
+    pd_plan_layout(P2, L, probs, n, 1);
+    o_phi2 = L.take(sizeof(double) * n);
+    for (int p = 0; p < n; ++p) o_g2[p] = L.take(sizeof(double) * (size_t)P2.maps[p].N * P2.maps[p].K);
+  }
   st = pd_reserve(ctx, L.off);
   if (st != PD_OK) return st;
   char *base = ctx->ws;
@@ -1039,6 +1056,19 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
       P.maps[p].diag = (double *)F[p].diag;
       P.maps[p].want_diag = F[p].want_diag;
     }
+  const EvalPlan *Pd = nullptr;
+  if (diag_plan) {
+    std::vector<double *> g2(n);
+    for (int p = 0; p < n; ++p) g2[p] = (double *)(base + o_g2[p]);
+    pd_plan_bind(P2, base, xt.data(), (double *)(base + o_phi2), g2.data(), nullptr, nullptr);
+    for (int p = 0; p < n; ++p) {
+      P2.maps[p].thc = P.maps[p].thc;        // the trial point's logit input
+      P2.maps[p].gate = F[p].want_diag;      // only maps that refresh this step
+      P2.maps[p].diag = (double *)F[p].diag;
+      P2.maps[p].want_diag = F[p].want_diag;
+    }
+    Pd = &P2;
+  }
   // assignment view of the same maps: theta = x, gate = assign_pending
   std::vector<MapDev> amaps = P.maps;
   for (int p = 0; p < n; ++p) {
@@ -1056,6 +1086,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   for (int p = 0; p < n; ++p) F[p].trace = trace_buf + (size_t)p * 256 * 16;
 #endif
   FIT_HIP(ctx, pd_plan_upload(ctx, P, s));
+  if (diag_plan) FIT_HIP(ctx, pd_plan_upload(ctx, P2, s));
   FIT_HIP(ctx, hipMemcpyAsync(d_amaps, amaps.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
   FIT_HIP(ctx, hipMemcpyAsync(dF, F.data(), sizeof(FitDev) * n, hipMemcpyHostToDevice, s));
   const bool zero_start = opts->init == PD_INIT_ZERO;
@@ -1067,6 +1098,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   k_fit_stamp<<<(n + 255) / 256, 256, 0, s>>>(dF, n);
   pd_plan_tables(P, s);
   pd_plan_onehot(P, s);
+  if (diag_plan) pd_plan_tables(P2, s);
   // block size: the largest per-map thread count (about 4 elements per thread)
   int vt = 64;
   for (int p = 0; p < n; ++p) vt = std::max(vt, F[p].vt);
@@ -1076,7 +1108,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   // ---- FIT_GRAPH_STEPS steps, captured as one graph (a graph launch has a
   // fixed cost at its boundary; the steps after a map stops are gated off)
   auto step = [&](hipStream_t ss) {
-    pd_fit_eval(ctx, P, eval_prec, d_amaps, ss);
+    pd_fit_eval(ctx, P, eval_prec, d_amaps, Pd, ss);
     k_fit_decide<<<n, vt, 0, ss>>>(dF);
   };
   hipGraph_t graph = nullptr;
