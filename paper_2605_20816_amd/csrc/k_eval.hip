@@ -472,23 +472,26 @@ template <typename T, int DMAX, bool HOT>
 __global__ __launch_bounds__(PD_BLOCK) void k_grad_diag(const MapDev *__restrict__ maps,
                                                         const int32_t *__restrict__ off,
                                                         int n_maps, int total) {
-  // A small grid strides over the work list: most steps refresh no map, and
-  // the LDS of this kernel would make a full grid of idle blocks expensive.
+  // A small grid strides over the maps that refresh this step (most steps
+  // refresh none), block by block of each map's work list; the LDS of this
+  // kernel would make a full grid of idle blocks expensive.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
   __shared__ double sh[8 * PD_WAVE * pd_st_k<DMAX>()];
-  const int nblocks = total / PD_WAVES_PER_BLOCK;  // every map's list is whole blocks
-  for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
-    const int item = b * PD_WAVES_PER_BLOCK + wave;
-    const int m = pd_find_map(off, n_maps, item);
+  (void)total;
+  for (int m = 0; m < n_maps; ++m) {
     const MapDev &M = maps[m];
     if (PD_GATED(M)) continue;
     if (M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) continue;
-    PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true, HOT>(M, item - off[m], lane, sh)));
-    if (M.st_size == 4) {
-      grad_block_sum(M, item - off[m], M.part_g, sh, lane);
-      grad_block_sum(M, item - off[m], M.part_d, sh + 4 * PD_WAVE * M.K, lane);
-      __syncthreads();  // sh is reused by the next block of the list
+    const int b1 = off[m + 1] / PD_WAVES_PER_BLOCK;  // every map's list is whole blocks
+    for (int b = off[m] / PD_WAVES_PER_BLOCK + (int)blockIdx.x; b < b1; b += gridDim.x) {
+      const int local = b * PD_WAVES_PER_BLOCK + wave - off[m];
+      PD_DISPATCH_UPTO(DMAX, M.d, (grad_item<T, D, true, HOT>(M, local, lane, sh)));
+      if (M.st_size == 4) {
+        grad_block_sum(M, local, M.part_g, sh, lane);
+        grad_block_sum(M, local, M.part_d, sh + 4 * PD_WAVE * M.K, lane);
+        __syncthreads();  // sh is reused by the next block of the list
+      }
     }
   }
 }
