@@ -37,6 +37,11 @@
 #define CURV_EPS 1e-10
 #define FIT_MAX_HISTORY 32
 #define FIT_GRAPH_STEPS 4
+// maps with at least this many unknowns run the n-length passes of an accepted
+// step on several blocks (FIT_SPLIT_CHUNK elements each)
+#define FIT_SPLIT_MIN_NK 1024
+#define FIT_SPLIT_CHUNK 512
+#define FIT_PART_W (5 * FIT_MAX_HISTORY + 8)
 
 enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
 enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
@@ -67,6 +72,13 @@ struct FitDev {
   double prev_t, prev_f, prev_d, lo_t, lo_f, lo_d, hi_t, hi_f, hi_d;
   uint64_t clk_start, clk_target;
   uint64_t *trace;  // optional stage stamps of the decision kernel (PD_FIT_TRACE builds)
+  // multi-block passes of an accepted step (maps with N K >= FIT_SPLIT_MIN_NK):
+  // phase 1 = the memory's dot products are pending (k_fit_dots, k_fit_rec),
+  // phase 2 = the direction is pending (k_fit_dir, k_fit_start)
+  int32_t split, split_phase, sp_put, sp_stored, sp_refresh, nchunk;
+  double sp_sy;
+  double *coef_g;  // [8 * (FIT_MAX_HISTORY + 1)] recursion coefficients
+  double *part;    // [nchunk][FIT_PART_W] per-block partial sums
 };
 
 #ifdef PD_FIT_TRACE
@@ -362,12 +374,14 @@ __device__ __attribute__((always_inline)) inline void gram_yy(FitDev &F, const i
 // One pass over the memory for the live slots k0 .. k0+U-1 (clipped to L):
 // S^T g, Y^T g (in the metric of H0) and, when the new pair is stored, its Gram
 // row and column.  Returns U.
+// The 5 U dot products of the live slots k0 .. k0+U-1 over the elements
+// e0 + tid, e0 + tid + nthr, ... < e1: S^T g, Y^T g (in the metric of H0:
+// Dinv, or the identity), s_new . Y, S . y_new, y_new . Y (same metric).
 template <int U>
-__device__ __attribute__((always_inline)) inline int slot_pass(
-    FitDev &F, const int *slot, int k0, int L, bool stored, int put, const double *s,
-    const double *y, double *Sg, double *Yg, double *gSY, double *gYY, double *red) {
+__device__ __attribute__((always_inline)) inline void dots_accumulate(
+    const FitDev &F, const int (&js)[U], const double *s, const double *y, int e0, int e1,
+    int tid, int nthr, double (&acc)[5 * U]) {
   const int n = F.NK;
-  const int M1 = F.m + 1;
   const auto pS = pd_glb((const double *)F.S);
   const auto pY = pd_glb((const double *)F.Y);
   const auto pg = pd_glb((const double *)F.g);
@@ -375,15 +389,10 @@ __device__ __attribute__((always_inline)) inline int slot_pass(
   const auto pny = pd_glb(y);
   const auto pw = pd_glb((const double *)F.Dinv);
   const bool pre = F.precond != 0;
-  double acc[5 * U];
 #pragma unroll
   for (int q = 0; q < 5 * U; ++q) acc[q] = 0.0;
-  int js[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) js[u] = slot[min(k0 + u, L - 1)];
-  for (int e = (int)threadIdx.x; e < n && (int)threadIdx.x < F.vt; e += F.vt) {
+  for (int e = e0 + tid; e < e1; e += nthr) {
     const double gi = pg[e], si = pns[e], yi = pny[e];
-    // Y^T g and Y^T y_new in the metric of H0 (Dinv, or the identity)
     const double w = pre ? pw[e] : 1.0;
     const double gw = pre ? gi * w : gi, yw = pre ? yi * w : yi;
 #pragma unroll
@@ -397,6 +406,36 @@ __device__ __attribute__((always_inline)) inline int slot_pass(
       acc[4 * U + u] = __builtin_fma(yw, Yj, acc[4 * U + u]);
     }
   }
+}
+
+// The dot products of slot k (oldest first, ring slot jj) into the LDS copies:
+// v = (S^T g, Y^T g, s_new . y_jj, s_jj . y_new, y_new . y_jj).
+__device__ inline void put_slot_dots(int jj, bool stored, int put, int M1, double v0, double v1,
+                                     double v2, double v3, double v4, double *Sg, double *Yg,
+                                     double *gSY, double *gYY) {
+  Sg[jj] = v0;
+  Yg[jj] = v1;
+  if (stored) {
+    gSY[put * M1 + jj] = v2;
+    gSY[jj * M1 + put] = v3;
+    gYY[put * M1 + jj] = v4;
+    gYY[jj * M1 + put] = v4;
+  }
+}
+
+// One pass over the memory for the live slots k0 .. k0+U-1 (clipped to L) on
+// this block.  Returns U.
+template <int U>
+__device__ __attribute__((always_inline)) inline int slot_pass(
+    FitDev &F, const int *slot, int k0, int L, bool stored, int put, const double *s,
+    const double *y, double *Sg, double *Yg, double *gSY, double *gYY, double *red) {
+  const int M1 = F.m + 1;
+  double acc[5 * U];
+  int js[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) js[u] = slot[min(k0 + u, L - 1)];
+  const int tid = (int)threadIdx.x < F.vt ? (int)threadIdx.x : F.NK;  // threads past vt add zeros
+  dots_accumulate<U>(F, js, s, y, 0, F.NK, tid, F.vt, acc);
   if (k0 == 0) FIT_STAMP(F, 13);
   blk_sums<5 * U>(acc, red);
   if (k0 == 0) FIT_STAMP(F, 14);
@@ -404,15 +443,8 @@ __device__ __attribute__((always_inline)) inline int slot_pass(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (k0 + u >= L) continue;
-      const int jj = js[u];
-      Sg[jj] = acc[u];
-      Yg[jj] = acc[U + u];
-      if (stored) {
-        gSY[put * M1 + jj] = acc[2 * U + u];
-        gSY[jj * M1 + put] = acc[3 * U + u];
-        gYY[put * M1 + jj] = acc[4 * U + u];
-        gYY[jj * M1 + put] = acc[4 * U + u];
-      }
+      put_slot_dots(js[u], stored, put, M1, acc[u], acc[U + u], acc[2 * U + u], acc[3 * U + u],
+                    acc[4 * U + u], Sg, Yg, gSY, gYY);
     }
   }
   __syncthreads();
@@ -482,6 +514,145 @@ __device__ __attribute__((always_inline)) inline void lbfgs_coef(
 // its Gram matrices, form the quasi-Newton direction d = -H g (the two-loop
 // recursion written through S^T g, Y^T g, S^T Y and Y^T Y) and start the next
 // search.
+// d = H0 (cg g + sum coef_y y) + sum coef_s s over the elements e0 + tid,
+// e0 + tid + nthr, ... < e1 (written to F.d), with the partial statistics g.g,
+// g.d and max |g| of those elements.  Slot k of the live pairs is ring slot
+// (head + k) mod M1; coef as written by lbfgs_coef.
+__device__ __attribute__((always_inline)) inline void dir_accumulate(
+    const FitDev &F, int head, int L, int M1, const double *coef, int e0, int e1, int tid,
+    int nthr, double (&v)[2], double &mx) {
+  const int n = F.NK;
+  const double cg = coef[4 * M1];
+  const auto pS = pd_glb((const double *)F.S);
+  const auto pY = pd_glb((const double *)F.Y);
+  const auto pg = pd_glb((const double *)F.g);
+  const auto pdir = pd_glb(F.d);
+  const auto pw = pd_glb((const double *)F.Dinv);
+  for (int i = e0 + tid; i < e1; i += nthr) {
+    const double gi = pg[i];
+    // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
+    double dy = cg * gi, ds = 0.0;
+    // slots in blocks of 16: the 32 loads of a block are issued before use
+    for (int k0 = 0; k0 < L; k0 += 16) {
+      double yv[16], sv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        int j = head + min(k0 + u, L - 1);
+        if (j >= M1) j -= M1;
+        yv[u] = pY[(size_t)j * n + i];
+        sv[u] = pS[(size_t)j * n + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < L) {
+          dy = __builtin_fma(coef[k0 + u], yv[u], dy);
+          ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
+        }
+    }
+    const double di = F.precond ? __builtin_fma(pw[i], dy, ds) : dy + ds;
+    pdir[i] = di;
+    v[0] = __builtin_fma(gi, gi, v[0]);
+    v[1] = __builtin_fma(gi, di, v[1]);
+    mx = fmax(mx, fabs(gi));
+  }
+}
+
+// Second part of an accepted step: the memory's dot products (one block, or
+// from the blocks' partials of k_fit_dots), the preconditioner's Y-Grams on a
+// refresh, gamma, and the recursion's coefficients (in coef; also to F.coef_g
+// for k_fit_dir when parts).
+__device__ __attribute__((always_inline)) inline void accept_mid(
+    FitDev &F, double *red, double **ja, double *coef, double *gSY, double *gYY, bool stored,
+    int put, bool refresh, double sy, bool parts) {
+  const int n = F.NK;
+  const int M1 = F.m + 1;
+  const double *s = F.S + (size_t)put * n;
+  const double *y = F.Y + (size_t)put * n;
+  const int L = F.hist_len, head = F.hist_head;
+  // slot of the k-th live pair (oldest first), kept in LDS
+  int *slot = (int *)ja;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) slot[k] = (head + k) % M1;
+  double *Sg = coef + 4 * M1 + 1, *Yg = Sg + M1, *rho = Yg + M1;
+  for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
+    gSY[e] = F.SY[e];
+    gYY[e] = F.YY[e];
+  }
+  for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
+  __syncthreads();
+  FIT_STAMP(F, 7);
+  if (!parts) {
+    // passes over up to 8 live slots: S^T g, Y^T g and, for a stored pair, its
+    // Gram row and column (s_new . y_j, s_j . y_new, y_new . y_j)
+    for (int k0 = 0; k0 < L;) {
+      const int rem = L - k0;
+      if (rem > 4) k0 += slot_pass<8>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
+      else if (rem > 2) k0 += slot_pass<4>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
+      else k0 += slot_pass<2>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
+    }
+  } else {
+    // the blocks' partials (5 values per live slot), added in block order
+    for (int v = threadIdx.x; v < 5 * L; v += blockDim.x) {
+      double t = 0.0;
+      for (int c = 0; c < F.nchunk; ++c) t += F.part[(size_t)c * FIT_PART_W + v];
+      red[v] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < L; ++k)
+        put_slot_dots(slot[k], stored, put, M1, red[5 * k], red[5 * k + 1], red[5 * k + 2],
+                      red[5 * k + 3], red[5 * k + 4], Sg, Yg, gSY, gYY);
+    __syncthreads();
+  }
+  if (refresh) gram_yy(F, slot, L, gYY, red);
+  if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
+  __syncthreads();
+  FIT_STAMP(F, 8);
+  // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0
+  if (threadIdx.x < PD_WAVE) {
+    lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
+  }
+  __syncthreads();
+  FIT_STAMP(F, 9);
+  if (parts)
+    for (int e = threadIdx.x; e <= 4 * M1; e += blockDim.x) F.coef_g[e] = coef[e];
+  if (stored || refresh)
+    for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
+      F.SY[e] = gSY[e];
+      F.YY[e] = gYY[e];
+    }
+}
+
+// Last part of an accepted step: the direction and its statistics (one block,
+// or from the blocks' partials of k_fit_dir), then the next search's start.
+__device__ __attribute__((always_inline)) inline void accept_tail(FitDev &F, double *red,
+                                                                  const double *coef, bool parts) {
+  const int M1 = F.m + 1;
+  double v[2] = {0.0, 0.0};
+  double mx = 0.0;
+  if (!parts) {
+    const int tid = (int)threadIdx.x < F.vt ? (int)threadIdx.x : F.NK;
+    dir_accumulate(F, F.hist_head, F.hist_len, M1, coef, 0, F.NK, tid, F.vt, v, mx);
+    blk_sums2_max(v, mx, red);
+  } else if (threadIdx.x == 0) {
+    for (int c = 0; c < F.nchunk; ++c) {
+      v[0] += F.part[(size_t)c * FIT_PART_W];
+      v[1] += F.part[(size_t)c * FIT_PART_W + 1];
+      mx = fmax(mx, F.part[(size_t)c * FIT_PART_W + 2]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    F.gg = v[0];
+    F.dphi0 = v[1];
+    F.gmax = mx;
+  }
+  if (threadIdx.x == 0 && F.precond)
+    *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
+  __syncthreads();
+  FIT_STAMP(F, 10);
+  start_ls(F, red);
+  FIT_STAMP(F, 11);
+}
+
 __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, double ft, double *red, double **ja, double **jb,
                              double *res, double *coef, double *gSY, double *gYY) {
   const int n = F.NK;
@@ -542,88 +713,20 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
   if (threadIdx.x == 0 && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
   const bool refresh = F.precond > 0 && (F.iters % F.precond) == 0;
   if (refresh) refresh_dinv(F, red);
-  const int L = F.hist_len, head = F.hist_head;
-  // slot of the k-th live pair (oldest first), kept in LDS
-  int *slot = (int *)ja;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) slot[k] = (head + k) % M1;
-  double *Sg = coef + 4 * M1 + 1, *Yg = Sg + M1, *rho = Yg + M1;
-  for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
-    gSY[e] = F.SY[e];
-    gYY[e] = F.YY[e];
-  }
-  for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
-  __syncthreads();
-  FIT_STAMP(F, 7);
-  // passes over up to 8 live slots: S^T g, Y^T g and, for a stored pair, its
-  // Gram row and column (s_new . y_j, s_j . y_new, y_new . y_j)
-  for (int k0 = 0; k0 < L;) {
-    const int rem = L - k0;
-    if (rem > 4) k0 += slot_pass<8>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-    else if (rem > 2) k0 += slot_pass<4>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-    else k0 += slot_pass<2>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-  }
-  if (refresh) gram_yy(F, slot, L, gYY, red);
-  if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
-  __syncthreads();
-  FIT_STAMP(F, 8);
-  // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0
-  if (threadIdx.x < PD_WAVE) {
-    lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
-  }
-  __syncthreads();
-  FIT_STAMP(F, 9);
-  if (stored || refresh)
-    for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
-      F.SY[e] = gSY[e];
-      F.YY[e] = gYY[e];
+  if (F.split) {
+    // the rest runs as k_fit_dots, k_fit_rec, k_fit_dir and k_fit_start
+    if (threadIdx.x == 0) {
+      F.split_phase = 1;
+      F.sp_put = put;
+      F.sp_stored = stored ? 1 : 0;
+      F.sp_refresh = refresh ? 1 : 0;
+      F.sp_sy = sy;
     }
-  // d, and the statistics of the new iterate for the search start
-  const double cg = coef[4 * M1];
-  double v[2] = {0.0, 0.0};
-  double mx = 0.0;
-  const auto pS = pd_glb((const double *)F.S);
-  const auto pY = pd_glb((const double *)F.Y);
-  const auto pg = pd_glb((const double *)F.g);
-  const auto pdir = pd_glb(F.d);
-  const auto pw = pd_glb((const double *)F.Dinv);
-  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
-    const double gi = pg[i];
-    // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
-    double dy = cg * gi, ds = 0.0;
-    // slots in blocks of 16: the 32 loads of a block are issued before use
-    for (int k0 = 0; k0 < L; k0 += 16) {
-      double yv[16], sv[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int j = slot[min(k0 + u, L - 1)];
-        yv[u] = pY[(size_t)j * n + i];
-        sv[u] = pS[(size_t)j * n + i];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (k0 + u < L) {
-          dy = __builtin_fma(coef[k0 + u], yv[u], dy);
-          ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
-        }
-    }
-    const double di = F.precond ? __builtin_fma(pw[i], dy, ds) : dy + ds;
-    pdir[i] = di;
-    v[0] = __builtin_fma(gi, gi, v[0]);
-    v[1] = __builtin_fma(gi, di, v[1]);
-    mx = fmax(mx, fabs(gi));
+    __syncthreads();
+    return;
   }
-  blk_sums2_max(v, mx, red);
-  if (threadIdx.x == 0) {
-    F.gg = v[0];
-    F.dphi0 = v[1];
-    F.gmax = mx;
-  }
-  if (threadIdx.x == 0 && F.precond)
-    *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
-  __syncthreads();
-  FIT_STAMP(F, 10);
-  start_ls(F, red);
-  FIT_STAMP(F, 11);
+  accept_mid(F, red, ja, coef, gSY, gYY, stored, put, refresh, sy, false);
+  accept_tail(F, red, coef, false);
 }
 
 // A search ended without a strong-Wolfe point.  Fall back to (t_res > 0), or
@@ -737,8 +840,9 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   // step's evaluation is not used
   if (sF.status == ST_RUNNING) decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
   __syncthreads();
-  // the next evaluation's input, while the state is at hand
-  if (sF.status == ST_RUNNING) form_trial(sF, sF.t, red);
+  // the next evaluation's input, while the state is at hand (an accepted step
+  // on the multi-block path forms it in k_fit_start)
+  if (sF.status == ST_RUNNING && sF.split_phase == 0) form_trial(sF, sF.t, red);
   __syncthreads();
   FIT_STAMP(sF, 12);
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
@@ -833,6 +937,102 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   if (act == 1) accept_trial(F, ft, red, ja, jb, res, coef, gSY, gYY);
   else if (act == 2) ls_fail(F, F.lo_t, red);
   else if (act == 3) ls_fail(F, F.prev_t, red);
+}
+
+// ---- the multi-block path of an accepted step (maps with split set)
+//
+// grid of k_fit_dots / k_fit_dir: the FIT_SPLIT_CHUNK-element chunks of every
+// map (chunk offsets in coff, n_maps + 1); block sums in fixed order, one
+// partial row per chunk.
+
+// The memory's dot products of this chunk (after the decision kernel's first
+// part stored the new pair).
+__global__ __launch_bounds__(PD_BLOCK) void k_fit_dots(FitDev *Fs, const int32_t *coff, int n_maps) {
+  __shared__ double red[MAX_WAVES * 48 + 48];
+  const int m = pd_find_map(coff, n_maps, blockIdx.x);
+  const FitDev &F = Fs[m];
+  if (*F.active == 0 || F.split_phase != 1) return;
+  const int c = blockIdx.x - coff[m];
+  const int e0 = c * FIT_SPLIT_CHUNK, e1 = min(F.NK, e0 + FIT_SPLIT_CHUNK);
+  const int M1 = F.m + 1, L = F.hist_len, head = F.hist_head;
+  const double *s = F.S + (size_t)F.sp_put * F.NK;
+  const double *y = F.Y + (size_t)F.sp_put * F.NK;
+  double *row = F.part + (size_t)c * FIT_PART_W;
+  for (int k0 = 0; k0 < L; k0 += 8) {
+    int js[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int j = head + min(k0 + u, L - 1);
+      if (j >= M1) j -= M1;
+      js[u] = j;
+    }
+    double acc[40];
+    dots_accumulate<8>(F, js, s, y, e0, e1, threadIdx.x, blockDim.x, acc);
+    blk_sums<40>(acc, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < L)
+#pragma unroll
+          for (int q = 0; q < 5; ++q) row[5 * (k0 + u) + q] = acc[q * 8 + u];
+  }
+}
+
+// grid: one block per map.  The memory update and the recursion from the dot
+// products' partials.
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_rec(FitDev *Fs) {
+  if (*Fs[blockIdx.x].active == 0 || Fs[blockIdx.x].split_phase != 1) return;
+  DEC_SHARED
+  constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
+  __syncthreads();
+  accept_mid(sF, red, ja, coef, gSY, gYY, sF.sp_stored != 0, sF.sp_put, sF.sp_refresh != 0,
+             sF.sp_sy, true);
+  if (threadIdx.x == 0) sF.split_phase = 2;
+  __syncthreads();
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
+  (void)jb;
+  (void)res;
+  (void)action;
+}
+
+// The direction on this chunk and its partial statistics.
+__global__ __launch_bounds__(PD_BLOCK) void k_fit_dir(FitDev *Fs, const int32_t *coff, int n_maps) {
+  __shared__ double red[MAX_WAVES * 48 + 48];
+  const int m = pd_find_map(coff, n_maps, blockIdx.x);
+  const FitDev &F = Fs[m];
+  if (*F.active == 0 || F.split_phase != 2) return;
+  const int c = blockIdx.x - coff[m];
+  const int e0 = c * FIT_SPLIT_CHUNK, e1 = min(F.NK, e0 + FIT_SPLIT_CHUNK);
+  double v[2] = {0.0, 0.0};
+  double mx = 0.0;
+  dir_accumulate(F, F.hist_head, F.hist_len, F.m + 1, F.coef_g, e0, e1, threadIdx.x, blockDim.x,
+                 v, mx);
+  blk_sums2_max(v, mx, red);
+  if (threadIdx.x == 0) {
+    double *row = F.part + (size_t)c * FIT_PART_W;
+    row[0] = v[0];
+    row[1] = v[1];
+    row[2] = mx;
+  }
+}
+
+// grid: one block per map.  The search start from the direction's statistics,
+// then the next trial point.
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_start(FitDev *Fs) {
+  if (*Fs[blockIdx.x].active == 0 || Fs[blockIdx.x].split_phase != 2) return;
+  __shared__ double red[MAX_WAVES * 48 + 48];
+  __shared__ double coef[8 * HS];
+  __shared__ FitDev sF;
+  constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
+  __syncthreads();
+  accept_tail(sF, red, coef, true);
+  if (threadIdx.x == 0) sF.split_phase = 0;
+  __syncthreads();
+  if (sF.status == ST_RUNNING) form_trial(sF, sF.t, red);
+  __syncthreads();
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
 }
 
 // Start of the fit on the device clock (before any warm start work).
@@ -974,6 +1174,19 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     o_vec[p] = L.take(sizeof(double) * (7 * NK + 2 * (size_t)(m + 1) * NK + (size_t)(m + 1) +
                                         2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)));
   }
+  // multi-block passes for the large maps (PD_FIT_SPLIT_MIN overrides the size)
+  int split_min = FIT_SPLIT_MIN_NK;
+  if (const char *e = getenv("PD_FIT_SPLIT_MIN")) split_min = std::max(1, atoi(e));
+  std::vector<int32_t> coff(n + 1, 0);
+  std::vector<size_t> o_split(n, 0);
+  for (int p = 0; p < n; ++p) {
+    const int NK = P.maps[p].N * P.maps[p].K;
+    const int nch = NK >= split_min ? (NK + FIT_SPLIT_CHUNK - 1) / FIT_SPLIT_CHUNK : 0;
+    coff[p + 1] = coff[p] + nch;
+    if (nch) o_split[p] = L.take(sizeof(double) * (8 * (FIT_MAX_HISTORY + 1) + (size_t)nch * FIT_PART_W));
+  }
+  const int total_chunks = coff[n];
+  const size_t o_coff = L.take(sizeof(int32_t) * (n + 1));
   const size_t o_F = L.take(sizeof(FitDev) * n);
   const size_t o_flags = L.take(sizeof(int32_t) * 3 * n);
   const size_t o_phi = L.take(sizeof(double) * n);
@@ -1037,6 +1250,12 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
     f.c_items = M.a_items / PD_WAVES_PER_BLOCK;
+    f.nchunk = coff[p + 1] - coff[p];
+    f.split = f.nchunk > 0 ? 1 : 0;
+    if (f.split) {
+      f.coef_g = (double *)(base + o_split[p]);
+      f.part = f.coef_g + 8 * (FIT_MAX_HISTORY + 1);
+    }
     f.active = flags + p;
     f.assign_pending = flags + n + p;
     xt[p] = f.xt;
@@ -1079,6 +1298,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   }
   MapDev *d_amaps = (MapDev *)(base + o_amaps);
   FitDev *dF = (FitDev *)(base + o_F);
+  int32_t *d_coff = (int32_t *)(base + o_coff);
 #ifdef PD_FIT_TRACE
   uint64_t *trace_buf = nullptr;
   FIT_HIP(ctx, hipMalloc((void **)&trace_buf, sizeof(uint64_t) * 256 * 16 * n));
@@ -1089,6 +1309,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (diag_plan) FIT_HIP(ctx, pd_plan_upload(ctx, P2, s));
   FIT_HIP(ctx, hipMemcpyAsync(d_amaps, amaps.data(), sizeof(MapDev) * n, hipMemcpyHostToDevice, s));
   FIT_HIP(ctx, hipMemcpyAsync(dF, F.data(), sizeof(FitDev) * n, hipMemcpyHostToDevice, s));
+  FIT_HIP(ctx, hipMemcpyAsync(d_coff, coff.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
   const bool zero_start = opts->init == PD_INIT_ZERO;
   if (!zero_start)
     for (int p = 0; p < n; ++p)
@@ -1110,6 +1331,12 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   auto step = [&](hipStream_t ss) {
     pd_fit_eval(ctx, P, eval_prec, d_amaps, Pd, ss);
     k_fit_decide<<<n, vt, 0, ss>>>(dF);
+    if (total_chunks > 0) {
+      k_fit_dots<<<total_chunks, PD_BLOCK, 0, ss>>>(dF, d_coff, n);
+      k_fit_rec<<<n, vt, 0, ss>>>(dF);
+      k_fit_dir<<<total_chunks, PD_BLOCK, 0, ss>>>(dF, d_coff, n);
+      k_fit_start<<<n, vt, 0, ss>>>(dF);
+    }
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -263,3 +263,56 @@ def test_preconditioner_argument_checks(pd):
         prec = args.pop("prec")
         with pytest.raises(pdl.PdError, match=status):
             ctx.fit([p], [th], prec, **args)
+
+
+@pytest.fixture
+def split_path():
+    """Every map takes the multi-block path of an accepted step (the dot
+    products and the direction on several blocks, from per-block partials)."""
+    import os
+    old = os.environ.get("PD_FIT_SPLIT_MIN")
+    os.environ["PD_FIT_SPLIT_MIN"] = "1"
+    yield
+    if old is None:
+        del os.environ["PD_FIT_SPLIT_MIN"]
+    else:
+        os.environ["PD_FIT_SPLIT_MIN"] = old
+
+
+@pytest.mark.parametrize("iters,pre", [(1, 0), (8, 0), (4, 5), (12, 5)])
+def test_split_path_iterates_match_oracle(pd, orc, split_path, iters, pre):
+    """N K = 1300 (three 512-element chunks): the multi-block path runs the same
+    state machine as the oracle's L-BFGS (with the preconditioner, 12 iterations
+    cross two refreshes)."""
+    pdl, ctx = pd
+    gm = poly_map(7, 96, 96, 130, 3)
+    d, eps = 3, 1e-3
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    kw = {}
+    if pre:
+        kw = dict(precondition=lambda th: orc.hessian_diag(th, gm.labels, gm.H, gm.W, d, eps),
+                  diag_every=pre)
+    ref = orc.lbfgs_fit(obj, np.zeros((gm.N, 10)), target_acc=2.0, max_iter=iters, **kw)
+    th = dev(np.zeros((gm.N, 10)))
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "fp64", init="zero", max_iter=iters,
+                  target_acc=2.0, precondition=pre)[0]
+    assert rep["iters"] == ref["iters"] == iters
+    assert rep["evals"] == ref["evals"]
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x - ref["theta"])) <= 1e-7 * np.max(np.abs(ref["theta"]))
+    assert abs(rep["phi"] - ref["phi"]) <= 1e-9 * abs(ref["phi"])
+
+
+def test_split_path_batch_reaches_99(pd, orc, split_path):
+    """A batch where every map takes the multi-block path reaches 99% like the
+    single-block path, and the accuracy the fit reports is the oracle's."""
+    pdl, ctx = pd
+    maps = [(poly_map(), 3), (poly_map(5, 128, 128, 40, 4), 4)]
+    probs = [problem(pdl, gm, d, 1e-3) for gm, d in maps]
+    ths = [dev(np.zeros((gm.N, pdl.num_features(d)))) for gm, d in maps]
+    reps = ctx.fit(probs, ths, "fp32", init="zero", max_iter=2000, target_acc=0.99, history=16,
+                   precondition=10, check_every=4)
+    for (gm, d), r, t in zip(maps, reps, ths):
+        assert r["status"] == "target"
+        _, nc, _ = orc.assign(t.cpu().numpy(), gm.H, gm.W, d, gm.labels)
+        assert nc / gm.labels.size == r["acc"] and r["acc"] >= 0.99
