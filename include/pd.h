@@ -277,7 +277,10 @@ typedef struct {
 /* theta_inout: host array of DEVICE N_p x K_p FP64 pointers (start if
  * PD_INIT_GIVEN; result on return).  reports: host array of n_probs.
  * PD_INIT_MLP / PD_INIT_HEURISTIC run pd_warm_start first (its time counts in
- * seconds_to_target). */
+ * seconds_to_target).  Maps with N K >= 1024 run the long vector passes of an
+ * accepted step on several blocks; the environment variable PD_FIT_SPLIT_MIN
+ * (read at each call) sets that size.  A map's result does not depend on the
+ * other maps of its batch. */
 pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);
@@ -289,11 +292,12 @@ pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
  * entries, in the order of pd_stage).  Gradient stages are included.  Synchronous.
  * PD_BF16 times its matrix-core stages in the PD_STAGE_LSE / PD_STAGE_GRAD slots. */
 typedef enum {
-  PD_STAGE_TABLES = 0,  /* 1-D Legendre tables                                  */
+  PD_STAGE_TABLES = 0,  /* 1-D Legendre tables (and the one-hot term's moments) */
   PD_STAGE_CENTER = 1,  /* grain-mean removal and eps scaling of theta          */
   PD_STAGE_PREP = 2,    /* row coefficients C[r][i][a]                          */
   PD_STAGE_LSE = 3,     /* per-pixel log-sum-exp and partial sums of log p_G    */
-  PD_STAGE_GRAD = 4,    /* partial sums of (p - delta) psi                      */
+  PD_STAGE_GRAD = 4,    /* partial sums of p psi (the one-hot term precomputed,
+                           as in pd_fit)                                        */
   PD_STAGE_REDUCE = 5,  /* fixed-order reductions to Phi and grad Phi           */
   PD_NUM_STAGES = 6
 } pd_stage;

@@ -562,7 +562,7 @@ __device__ __attribute__((always_inline)) inline void dir_accumulate(
 // refresh, gamma, and the recursion's coefficients (in coef; also to F.coef_g
 // for k_fit_dir when parts).
 __device__ __attribute__((always_inline)) inline void accept_mid(
-    FitDev &F, double *red, double **ja, double *coef, double *gSY, double *gYY, bool stored,
+    FitDev &F, double *red, int *slot, double *coef, double *gSY, double *gYY, bool stored,
     int put, bool refresh, double sy, bool parts) {
   const int n = F.NK;
   const int M1 = F.m + 1;
@@ -570,7 +570,6 @@ __device__ __attribute__((always_inline)) inline void accept_mid(
   const double *y = F.Y + (size_t)put * n;
   const int L = F.hist_len, head = F.hist_head;
   // slot of the k-th live pair (oldest first), kept in LDS
-  int *slot = (int *)ja;
   for (int k = threadIdx.x; k < L; k += blockDim.x) slot[k] = (head + k) % M1;
   double *Sg = coef + 4 * M1 + 1, *Yg = Sg + M1, *rho = Yg + M1;
   for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
@@ -653,8 +652,8 @@ __device__ __attribute__((always_inline)) inline void accept_tail(FitDev &F, dou
   FIT_STAMP(F, 11);
 }
 
-__device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, double ft, double *red, double **ja, double **jb,
-                             double *res, double *coef, double *gSY, double *gYY) {
+__device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, double ft, double *red, int *slots,
+                                                                   double *coef, double *gSY, double *gYY) {
   const int n = F.NK;
   const int m = F.m;
   const int M1 = m + 1;  // ring slots: a candidate never overwrites a stored pair
@@ -725,7 +724,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     __syncthreads();
     return;
   }
-  accept_mid(F, red, ja, coef, gSY, gYY, stored, put, refresh, sy, false);
+  accept_mid(F, red, slots, coef, gSY, gYY, stored, put, refresh, sy, false);
   accept_tail(F, red, coef, false);
 }
 
@@ -800,14 +799,13 @@ __device__ inline void consume_acc(FitDev &F, long long n_correct) {
 #define HS (FIT_MAX_HISTORY + 1)
 #define DEC_SHARED                                  \
   __shared__ double red[MAX_WAVES * 48 + 48];       \
-  __shared__ double *ja[5 * HS], *jb[5 * HS];       \
-  __shared__ double res[5 * HS];                    \
+  __shared__ int slots[HS];                         \
   __shared__ double coef[8 * HS];                   \
   __shared__ double gSY[HS * HS], gYY[HS * HS];     \
   __shared__ FitDev sF;                             \
   __shared__ int action;
 
-__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, int *slots,
                             double *coef, double *gSY, double *gYY, int *action_p);
 
 // grid: one block per map.  Consumes one evaluation at xt.
@@ -838,7 +836,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   }
   // a map that reached the target or its budget keeps its iterate; this
   // step's evaluation is not used
-  if (sF.status == ST_RUNNING) decide_body(sF, red, ja, jb, res, coef, gSY, gYY, &action);
+  if (sF.status == ST_RUNNING) decide_body(sF, red, slots, coef, gSY, gYY, &action);
   __syncthreads();
   // the next evaluation's input, while the state is at hand (an accepted step
   // on the multi-block path forms it in k_fit_start)
@@ -848,7 +846,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
 }
 
-__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, double **ja, double **jb, double *res,
+__device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, int *slots,
                             double *coef, double *gSY, double *gYY, int *action_p) {
   int &action = *action_p;
   const int n = F.NK;
@@ -883,7 +881,7 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
     return;
   }
   if (F.phase == PH_ACCEPT_NEXT) {
-    accept_trial(F, ft, red, ja, jb, res, coef, gSY, gYY);
+    accept_trial(F, ft, red, slots, coef, gSY, gYY);
     return;
   }
   double dv[1] = {0.0};
@@ -934,7 +932,7 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   __syncthreads();
   FIT_STAMP(F, 3);
   const int act = action;
-  if (act == 1) accept_trial(F, ft, red, ja, jb, res, coef, gSY, gYY);
+  if (act == 1) accept_trial(F, ft, red, slots, coef, gSY, gYY);
   else if (act == 2) ls_fail(F, F.lo_t, red);
   else if (act == 3) ls_fail(F, F.prev_t, red);
 }
@@ -982,18 +980,19 @@ __global__ __launch_bounds__(PD_BLOCK) void k_fit_dots(FitDev *Fs, const int32_t
 // products' partials.
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_rec(FitDev *Fs) {
   if (*Fs[blockIdx.x].active == 0 || Fs[blockIdx.x].split_phase != 1) return;
-  DEC_SHARED
+  __shared__ double red[MAX_WAVES * 48 + 48];
+  __shared__ int slots[HS];
+  __shared__ double coef[8 * HS];
+  __shared__ double gSY[HS * HS], gYY[HS * HS];
+  __shared__ FitDev sF;
   constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
-  accept_mid(sF, red, ja, coef, gSY, gYY, sF.sp_stored != 0, sF.sp_put, sF.sp_refresh != 0,
+  accept_mid(sF, red, slots, coef, gSY, gYY, sF.sp_stored != 0, sF.sp_put, sF.sp_refresh != 0,
              sF.sp_sy, true);
   if (threadIdx.x == 0) sF.split_phase = 2;
   __syncthreads();
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
-  (void)jb;
-  (void)res;
-  (void)action;
 }
 
 // The direction on this chunk and its partial statistics.

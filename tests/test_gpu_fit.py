@@ -316,3 +316,20 @@ def test_split_path_batch_reaches_99(pd, orc, split_path):
         assert r["status"] == "target"
         _, nc, _ = orc.assign(t.cpu().numpy(), gm.H, gm.W, d, gm.labels)
         assert nc / gm.labels.size == r["acc"] and r["acc"] >= 0.99
+
+
+def test_split_path_batched_equals_single(pd, split_path):
+    """On the multi-block path too, a map's fit does not depend on its batch:
+    the chunking and every partial sum are the map's own."""
+    pdl, ctx = pd
+    maps = [(poly_map(7, 96, 96, 130, 3), 3), (poly_map(), 3)]
+    probs = [problem(pdl, gm, d, 1e-3) for gm, d in maps]
+    ths = [dev(np.zeros((gm.N, pdl.num_features(d)))) for gm, d in maps]
+    reps = ctx.fit(probs, ths, "fp32", init="zero", max_iter=60, target_acc=2.0, history=16,
+                   precondition=10)
+    for k, (p, (gm, d)) in enumerate(zip(probs, maps)):
+        t1 = dev(np.zeros((gm.N, pdl.num_features(d))))
+        r1 = ctx.fit([p], [t1], "fp32", init="zero", max_iter=60, target_acc=2.0, history=16,
+                     precondition=10)[0]
+        assert torch.equal(t1, ths[k])
+        assert (r1["iters"], r1["evals"]) == (reps[k]["iters"], reps[k]["evals"])
