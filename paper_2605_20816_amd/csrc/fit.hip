@@ -1225,7 +1225,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.max_iter = opts->max_iter;
     f.check_every = opts->check_every;
     f.gauge = (int)opts->gauge;
-    f.vt = std::min(FIT_THREADS, std::max(64, ((int)NK / 4 + 63) / 64 * 64));
+    f.vt = std::min(FIT_THREADS, std::max(64, ((int)NK + 63) / 64 * 64));
     f.n_pix = (int64_t)M.H * M.W;
     f.target_acc = opts->target_acc;
     f.gtol = opts->gtol;
