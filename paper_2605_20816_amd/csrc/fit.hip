@@ -36,7 +36,7 @@
 #define LS_MAX_EVALS 20
 #define CURV_EPS 1e-10
 #define FIT_MAX_HISTORY 32
-#define FIT_GRAPH_STEPS 4
+#define FIT_GRAPH_STEPS 8
 // maps with at least this many unknowns run the n-length passes of an accepted
 // step on several blocks (FIT_SPLIT_CHUNK elements each)
 #define FIT_SPLIT_MIN_NK 1024
