@@ -9,7 +9,7 @@
             theta = 0 (FP32 and BF16).
   c4_fit    the first 16 maps of the 64-map c4 batch: one batched FP32 fit
             (tiles autotuned for the batch, memory 16, diagonal preconditioner
-            refreshed every 20 iterations, accuracy checked every 4 iterations)
+            refreshed every 40 iterations, accuracy checked every 8 iterations)
             to 99% pixel accuracy or 2000 iterations.
 
 The maps are the repository's seeded synthetic grain maps (module `synth`).
@@ -61,8 +61,8 @@ def main():
         zeros = lambda: [torch.zeros((q.N, num_features(q.d)), dtype=torch.float64,
                                      device="cuda") for q in probs]
         ctx.autotune(probs, zeros(), "fp32")
-        reps = ctx.fit(probs, zeros(), "fp32", init="zero", history=16, precondition=20,
-                       check_every=4, max_iter=2000, target_acc=0.99)
+        reps = ctx.fit(probs, zeros(), "fp32", init="zero", history=16, precondition=40,
+                       check_every=8, max_iter=2000, target_acc=0.99)
         torch.cuda.synchronize()
         print(f"c4_fit: {sum(r['status'] == 'target' for r in reps)} of 16 maps at 99%, "
               f"longest time to 99% {max(r['seconds_to_target'] for r in reps):.3f} s", flush=True)
