@@ -108,6 +108,16 @@ struct FitState {
 // lanes per wave.
 __shared__ double fit_xs[MAX_WAVES * 8 * PD_WAVE];
 
+// Per-element vectors of a single-block map (N K < FIT_SPLIT_MIN_NK) during an
+// accepted step, kept in LDS: the new gradient, s, y and the metric weights
+// Dinv (or 1) (read by every wave's dot products), the new iterate and
+// direction (read when the next trial point is formed) and that trial point
+// (read for its grain means).
+enum { FV_G = 0, FV_S, FV_Y, FV_W, FV_X, FV_D, FV_XT, FV_ROWS };
+__shared__ double fit_vec[FV_ROWS][FIT_SPLIT_MIN_NK];
+// nonzero while fit_vec's x and d rows hold the iterate and the search direction
+__shared__ int fit_staged;
+
 template <int G>
 __device__ __attribute__((always_inline)) inline void blk_sums(double (&v)[G], double *red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -282,7 +292,10 @@ __device__ __attribute__((always_inline)) inline void set_steepest(FitDev &F, do
     v[0] = __builtin_fma(gi, di, v[0]);
   }
   blk_sums<1>(v, red);
-  if (threadIdx.x == 0) F.dphi0 = v[0];
+  if (threadIdx.x == 0) {
+    F.dphi0 = v[0];
+    fit_staged = 0;  // the LDS copy of d (if any) is stale
+  }
   __syncthreads();
 }
 
@@ -319,8 +332,11 @@ __device__ __attribute__((always_inline)) inline void refresh_dinv(FitDev &F, do
   mx = blk_max(mx, red);
   const double fl = F.diag_floor * mx;
   const int last = (F.N - 1) * F.K;
-  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt)
-    F.Dinv[i] = (F.gauge == 0 && i >= last) ? 0.0 : 1.0 / (F.diag[i] + fl);
+  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
+    const double w = (F.gauge == 0 && i >= last) ? 0.0 : 1.0 / (F.diag[i] + fl);
+    F.Dinv[i] = w;
+    if (F.NK < FIT_SPLIT_MIN_NK) fit_vec[FV_W][i] = w;
+  }
   __syncthreads();
 }
 
@@ -421,34 +437,6 @@ __device__ inline void put_slot_dots(int jj, bool stored, int put, int M1, doubl
     gYY[put * M1 + jj] = v4;
     gYY[jj * M1 + put] = v4;
   }
-}
-
-// One pass over the memory for the live slots k0 .. k0+U-1 (clipped to L) on
-// this block.  Returns U.
-template <int U>
-__device__ __attribute__((always_inline)) inline int slot_pass(
-    FitDev &F, const int *slot, int k0, int L, bool stored, int put, const double *s,
-    const double *y, double *Sg, double *Yg, double *gSY, double *gYY, double *red) {
-  const int M1 = F.m + 1;
-  double acc[5 * U];
-  int js[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) js[u] = slot[min(k0 + u, L - 1)];
-  const int tid = (int)threadIdx.x < F.vt ? (int)threadIdx.x : F.NK;  // threads past vt add zeros
-  dots_accumulate<U>(F, js, s, y, 0, F.NK, tid, F.vt, acc);
-  if (k0 == 0) FIT_STAMP(F, 13);
-  blk_sums<5 * U>(acc, red);
-  if (k0 == 0) FIT_STAMP(F, 14);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (k0 + u >= L) continue;
-      put_slot_dots(js[u], stored, put, M1, acc[u], acc[U + u], acc[2 * U + u], acc[3 * U + u],
-                    acc[4 * U + u], Sg, Yg, gSY, gYY);
-    }
-  }
-  __syncthreads();
-  return U;
 }
 
 // v of lane k (k wave-uniform) on every lane.
@@ -557,17 +545,14 @@ __device__ __attribute__((always_inline)) inline void dir_accumulate(
   }
 }
 
-// Second part of an accepted step: the memory's dot products (one block, or
-// from the blocks' partials of k_fit_dots), the preconditioner's Y-Grams on a
-// refresh, gamma, and the recursion's coefficients (in coef; also to F.coef_g
-// for k_fit_dir when parts).
+// Second part of an accepted step of a multi-block map (k_fit_rec): the
+// memory's dot products from the blocks' partials of k_fit_dots, the
+// preconditioner's Y-Grams on a refresh, gamma, and the recursion's
+// coefficients (in coef and F.coef_g, for k_fit_dir).
 __device__ __attribute__((always_inline)) inline void accept_mid(
     FitDev &F, double *red, int *slot, double *coef, double *gSY, double *gYY, bool stored,
-    int put, bool refresh, double sy, bool parts) {
-  const int n = F.NK;
+    int put, bool refresh, double sy) {
   const int M1 = F.m + 1;
-  const double *s = F.S + (size_t)put * n;
-  const double *y = F.Y + (size_t)put * n;
   const int L = F.hist_len, head = F.hist_head;
   // slot of the k-th live pair (oldest first), kept in LDS
   for (int k = threadIdx.x; k < L; k += blockDim.x) slot[k] = (head + k) % M1;
@@ -577,43 +562,25 @@ __device__ __attribute__((always_inline)) inline void accept_mid(
     gYY[e] = F.YY[e];
   }
   for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
-  __syncthreads();
-  FIT_STAMP(F, 7);
-  if (!parts) {
-    // passes over up to 8 live slots: S^T g, Y^T g and, for a stored pair, its
-    // Gram row and column (s_new . y_j, s_j . y_new, y_new . y_j)
-    for (int k0 = 0; k0 < L;) {
-      const int rem = L - k0;
-      if (rem > 4) k0 += slot_pass<8>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-      else if (rem > 2) k0 += slot_pass<4>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-      else k0 += slot_pass<2>(F, slot, k0, L, stored, put, s, y, Sg, Yg, gSY, gYY, red);
-    }
-  } else {
-    // the blocks' partials (5 values per live slot), added in block order
-    for (int v = threadIdx.x; v < 5 * L; v += blockDim.x) {
-      double t = 0.0;
-      for (int c = 0; c < F.nchunk; ++c) t += F.part[(size_t)c * FIT_PART_W + v];
-      red[v] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int k = 0; k < L; ++k)
-        put_slot_dots(slot[k], stored, put, M1, red[5 * k], red[5 * k + 1], red[5 * k + 2],
-                      red[5 * k + 3], red[5 * k + 4], Sg, Yg, gSY, gYY);
-    __syncthreads();
+  // the blocks' partials (5 values per live slot), added in block order
+  for (int v = threadIdx.x; v < 5 * L; v += blockDim.x) {
+    double t = 0.0;
+    for (int c = 0; c < F.nchunk; ++c) t += F.part[(size_t)c * FIT_PART_W + v];
+    red[v] = t;
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < L; ++k)
+      put_slot_dots(slot[k], stored, put, M1, red[5 * k], red[5 * k + 1], red[5 * k + 2],
+                    red[5 * k + 3], red[5 * k + 4], Sg, Yg, gSY, gYY);
+  __syncthreads();
   if (refresh) gram_yy(F, slot, L, gYY, red);
   if (F.precond && stored && threadIdx.x == 0) F.gamma = sy / gYY[put * M1 + put];
   __syncthreads();
-  FIT_STAMP(F, 8);
   // alpha (newest to oldest) and beta (oldest to newest) on the lanes of wave 0
-  if (threadIdx.x < PD_WAVE) {
-    lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
-  }
+  if (threadIdx.x < PD_WAVE) lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
   __syncthreads();
-  FIT_STAMP(F, 9);
-  if (parts)
-    for (int e = threadIdx.x; e <= 4 * M1; e += blockDim.x) F.coef_g[e] = coef[e];
+  for (int e = threadIdx.x; e <= 4 * M1; e += blockDim.x) F.coef_g[e] = coef[e];
   if (stored || refresh)
     for (int e = threadIdx.x; e < M1 * M1; e += blockDim.x) {
       F.SY[e] = gSY[e];
@@ -621,31 +588,215 @@ __device__ __attribute__((always_inline)) inline void accept_mid(
     }
 }
 
-// Last part of an accepted step: the direction and its statistics (one block,
-// or from the blocks' partials of k_fit_dir), then the next search's start.
-__device__ __attribute__((always_inline)) inline void accept_tail(FitDev &F, double *red,
-                                                                  const double *coef, bool parts) {
-  const int M1 = F.m + 1;
-  double v[2] = {0.0, 0.0};
-  double mx = 0.0;
-  if (!parts) {
-    const int tid = (int)threadIdx.x < F.vt ? (int)threadIdx.x : F.NK;
-    dir_accumulate(F, F.hist_head, F.hist_len, M1, coef, 0, F.NK, tid, F.vt, v, mx);
-    blk_sums2_max(v, mx, red);
-  } else if (threadIdx.x == 0) {
+// Last part of an accepted step of a multi-block map (k_fit_start): the
+// direction's statistics from the blocks' partials of k_fit_dir, then the next
+// search's start.
+__device__ __attribute__((always_inline)) inline void accept_tail(FitDev &F, double *red) {
+  if (threadIdx.x == 0) {
+    double v0 = 0.0, v1 = 0.0, mx = 0.0;
     for (int c = 0; c < F.nchunk; ++c) {
-      v[0] += F.part[(size_t)c * FIT_PART_W];
-      v[1] += F.part[(size_t)c * FIT_PART_W + 1];
+      v0 += F.part[(size_t)c * FIT_PART_W];
+      v1 += F.part[(size_t)c * FIT_PART_W + 1];
       mx = fmax(mx, F.part[(size_t)c * FIT_PART_W + 2]);
     }
+    F.gg = v0;
+    F.dphi0 = v1;
+    F.gmax = mx;
+    if (F.precond) *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
   }
-  if (threadIdx.x == 0) {
+  __syncthreads();
+  start_ls(F, red);
+}
+
+// The five dot products of accept_mid for a single-block map, wave by wave:
+// wave w takes the live slots k = w, w + nw, ... (US at a time) over all
+// elements (UE per lane; the new vectors and the metric from LDS), adds them
+// across its lanes and writes them to res[5 k .. 5 k + 4] in put_slot_dots'
+// order.
+template <int UE, int US>
+__device__ __attribute__((always_inline)) inline void wave_slot_dots(const FitDev &F, int L,
+                                                                     int head, int M1, double *res) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int n = F.NK;
+  const auto pS = pd_glb((const double *)F.S);
+  const auto pY = pd_glb((const double *)F.Y);
+  for (int k0 = w; k0 < L; k0 += US * nw) {
+    int js[US];
+#pragma unroll
+    for (int u = 0; u < US; ++u) {
+      int j = head + min(k0 + u * nw, L - 1);
+      js[u] = j >= M1 ? j - M1 : j;
+    }
+    double sv[US][UE], yv[US][UE];
+#pragma unroll
+    for (int c = 0; c < UE; ++c) {
+      const int e = lane + PD_WAVE * c;
+      const bool ok = e < n;
+#pragma unroll
+      for (int u = 0; u < US; ++u) {
+        sv[u][c] = ok ? pS[(size_t)js[u] * n + e] : 0.0;
+        yv[u][c] = ok ? pY[(size_t)js[u] * n + e] : 0.0;
+      }
+    }
+    double acc[5 * US];
+#pragma unroll
+    for (int q = 0; q < 5 * US; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < UE; ++c) {
+      const int e = lane + PD_WAVE * c;
+      const bool ok = e < n;
+      const double gi = ok ? fit_vec[FV_G][e] : 0.0;
+      const double si = ok ? fit_vec[FV_S][e] : 0.0;
+      const double yi = ok ? fit_vec[FV_Y][e] : 0.0;
+      const double wi = ok ? fit_vec[FV_W][e] : 0.0;
+      const double gw = gi * wi, yw = yi * wi;
+#pragma unroll
+      for (int u = 0; u < US; ++u) {
+        acc[u] = __builtin_fma(sv[u][c], gi, acc[u]);
+        acc[US + u] = __builtin_fma(yv[u][c], gw, acc[US + u]);
+        acc[2 * US + u] = __builtin_fma(si, yv[u][c], acc[2 * US + u]);
+        acc[3 * US + u] = __builtin_fma(sv[u][c], yi, acc[3 * US + u]);
+        acc[4 * US + u] = __builtin_fma(yw, yv[u][c], acc[4 * US + u]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5 * US; ++q) acc[q] = pd_wave_sum(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < US; ++u) {
+        const int k = k0 + u * nw;
+        if (k < L)
+#pragma unroll
+          for (int q = 0; q < 5; ++q) res[5 * k + q] = acc[q * US + u];
+      }
+    }
+  }
+}
+
+// An accepted step of a single-block map (everything after the new pair is
+// formed): the dot products wave by wave, the recursion, the direction (its
+// memory loads for the thread's first element issued before the recursion)
+// and the next search's start.  x and d end in fit_vec for form_trial.
+__device__ __attribute__((always_inline)) inline void accept_small(
+    FitDev &F, double *red, int *slot, double *coef, double *gSY, double *gYY, bool stored,
+    int put, bool refresh, double sy) {
+  const int n = F.NK;
+  const int M1 = F.m + 1;
+  const int L = F.hist_len, head = F.hist_head;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  double *Sg = coef + 4 * M1 + 1, *Yg = Sg + M1, *rho = Yg + M1;
+  // the Gram matrices and rho: loaded here, stored to LDS once the dot
+  // products' loads (issued after these) have arrived
+  const int MM = M1 * M1;
+  const double q0 = tid < MM ? F.SY[tid] : 0.0;
+  const double q1 = tid < MM ? F.YY[tid] : 0.0;
+  const double q2 = tid + bd < MM ? F.SY[tid + bd] : 0.0;
+  const double q3 = tid + bd < MM ? F.YY[tid + bd] : 0.0;
+  const double qr = tid < M1 ? F.rho[tid] : 0.0;
+  const int E = (n + PD_WAVE - 1) / PD_WAVE;
+  if (E <= 4) wave_slot_dots<4, 4>(F, L, head, M1, red);
+  else if (E <= 8) wave_slot_dots<8, 2>(F, L, head, M1, red);
+  else wave_slot_dots<16, 1>(F, L, head, M1, red);
+  FIT_STAMP(F, 7);
+  for (int k = tid; k < L; k += bd) slot[k] = (head + k) % M1;
+  if (tid < MM) {
+    gSY[tid] = q0;
+    gYY[tid] = q1;
+  }
+  if (tid + bd < MM) {
+    gSY[tid + bd] = q2;
+    gYY[tid + bd] = q3;
+  }
+  for (int e = tid + 2 * bd; e < MM; e += bd) {
+    gSY[e] = F.SY[e];
+    gYY[e] = F.YY[e];
+  }
+  if (tid < M1) rho[tid] = qr;
+  __syncthreads();
+  // the new dot products into the Gram copies (distinct entries per slot)
+  for (int k = tid; k < L; k += bd)
+    put_slot_dots(slot[k], stored, put, M1, red[5 * k], red[5 * k + 1], red[5 * k + 2],
+                  red[5 * k + 3], red[5 * k + 4], Sg, Yg, gSY, gYY);
+  __syncthreads();
+  FIT_STAMP(F, 13);
+  if (refresh) gram_yy(F, slot, L, gYY, red);
+  if (F.precond && stored && tid == 0) F.gamma = sy / gYY[put * M1 + put];
+  // the direction's memory rows for this thread's first element, in flight
+  // during the recursion
+  const auto pS = pd_glb((const double *)F.S);
+  const auto pY = pd_glb((const double *)F.Y);
+  const bool own = tid < F.vt && tid < n;
+  double yv[16], sv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    int j = head + min(u, L - 1);
+    if (j >= M1) j -= M1;
+    const bool ok = own && u < L;
+    yv[u] = ok ? pY[(size_t)j * n + tid] : 0.0;
+    sv[u] = ok ? pS[(size_t)j * n + tid] : 0.0;
+  }
+  FIT_STAMP(F, 14);
+  __syncthreads();
+  FIT_STAMP(F, 8);
+  if (tid < PD_WAVE) lbfgs_coef(F, L, head, M1, slot, rho, Sg, Yg, gSY, gYY, coef);
+  __syncthreads();
+  FIT_STAMP(F, 9);
+  if (stored || refresh)
+    for (int e = tid; e < MM; e += bd) {
+      F.SY[e] = gSY[e];
+      F.YY[e] = gYY[e];
+    }
+  // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
+  const double cg = coef[4 * M1];
+  const auto pdir = pd_glb(F.d);
+  double v[2] = {0.0, 0.0};
+  double mx = 0.0;
+  for (int i = tid; i < n && tid < F.vt; i += F.vt) {
+    const double gi = fit_vec[FV_G][i];
+    double dy = cg * gi, ds = 0.0;
+    int k0 = 0;
+    if (i == tid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u < L) {
+          dy = __builtin_fma(coef[u], yv[u], dy);
+          ds = __builtin_fma(coef[M1 + u], sv[u], ds);
+        }
+      k0 = 16;
+    }
+    for (; k0 < L; k0 += 16) {
+      double ya[16], sa[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        int j = head + min(k0 + u, L - 1);
+        if (j >= M1) j -= M1;
+        ya[u] = pY[(size_t)j * n + i];
+        sa[u] = pS[(size_t)j * n + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < L) {
+          dy = __builtin_fma(coef[k0 + u], ya[u], dy);
+          ds = __builtin_fma(coef[M1 + k0 + u], sa[u], ds);
+        }
+    }
+    const double di = F.precond ? __builtin_fma(fit_vec[FV_W][i], dy, ds) : dy + ds;
+    pdir[i] = di;
+    fit_vec[FV_D][i] = di;
+    v[0] = __builtin_fma(gi, gi, v[0]);
+    v[1] = __builtin_fma(gi, di, v[1]);
+    mx = fmax(mx, fabs(gi));
+  }
+  blk_sums2_max(v, mx, red);
+  if (tid == 0) {
     F.gg = v[0];
     F.dphi0 = v[1];
     F.gmax = mx;
+    if (F.precond) *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
+    fit_staged = 1;  // x (from the new pair's pass) and d are in fit_vec
   }
-  if (threadIdx.x == 0 && F.precond)
-    *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
   __syncthreads();
   FIT_STAMP(F, 10);
   start_ls(F, red);
@@ -671,6 +822,8 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     const auto pd = pd_glb((const double *)F.d);
     const auto pgr = pd_glb((const double *)F.graw);
     const auto pxt = pd_glb((const double *)F.xt);
+    const auto pw = pd_glb((const double *)F.Dinv);
+    const bool pre = F.precond != 0;
     for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
       const double di = pd[i], gri = pgr[i], gi = pg[i], xti = pxt[i];
       const double si = t * di;
@@ -682,6 +835,13 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
       v3[2] = __builtin_fma(yi, yi, v3[2]);
       px[i] = xti;
       pg[i] = gri;
+      if (!F.split) {
+        fit_vec[FV_G][i] = gri;
+        fit_vec[FV_S][i] = si;
+        fit_vec[FV_Y][i] = yi;
+        fit_vec[FV_W][i] = pre ? pw[i] : 1.0;
+        fit_vec[FV_X][i] = xti;
+      }
     }
   }
   blk_sums<3>(v3, red);
@@ -724,8 +884,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     __syncthreads();
     return;
   }
-  accept_mid(F, red, slots, coef, gSY, gYY, stored, put, refresh, sy, false);
-  accept_tail(F, red, coef, false);
+  accept_small(F, red, slots, coef, gSY, gYY, stored, put, refresh, sy);
 }
 
 // A search ended without a strong-Wolfe point.  Fall back to (t_res > 0), or
@@ -755,7 +914,33 @@ __device__ __attribute__((always_inline)) inline void ls_fail(FitDev &F, double 
 
 // The trial point xt = x + t d and the evaluation input
 // thc = -(log2 e / eps) (xt - mean_i xt_i) (all threads of the map's block).
-__device__ __attribute__((always_inline)) inline void form_trial(FitDev &F, double t, double *red) {
+// Maps with N K < FIT_SPLIT_MIN_NK keep xt in LDS for the grain means, and take
+// x and d from LDS when staged (right after an accepted step).
+__device__ __attribute__((always_inline)) inline void form_trial(FitDev &F, double t, double *red,
+                                                                 bool staged) {
+  if (F.NK < FIT_SPLIT_MIN_NK) {
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) {
+      const double xi = staged ? fit_vec[FV_X][i] : F.x[i];
+      const double di = staged ? fit_vec[FV_D][i] : F.d[i];
+      const double v = xi + t * di;
+      F.xt[i] = v;
+      fit_vec[FV_XT][i] = v;
+    }
+    __syncthreads();
+    // column sums over the grains, wave w taking columns w, w + nw, ...
+    for (int k = w; k < F.K; k += nw) {
+      double sm = 0.0;
+      for (int i = lane; i < F.N; i += PD_WAVE) sm += fit_vec[FV_XT][i * F.K + k];
+      sm = pd_wave_sum(sm);
+      if (lane == 0) red[k] = sm;
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt)
+      F.thc[i] = F.cscale * (fit_vec[FV_XT][i] - red[i % F.K] / (double)F.N);
+    return;
+  }
   for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
   __syncthreads();
   for (int k0 = 0; k0 < F.K; k0 += VG) {
@@ -806,21 +991,29 @@ __device__ inline void consume_acc(FitDev &F, long long n_correct) {
   __shared__ int action;
 
 __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, int *slots,
-                            double *coef, double *gSY, double *gYY, int *action_p);
+                            double *coef, double *gSY, double *gYY, int *action_p, double ft);
 
-// grid: one block per map.  Consumes one evaluation at xt.
-__global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
-  if (*Fs[blockIdx.x].active == 0) return;
+// grid: one block per map.  Consumes one evaluation at xt.  flags: the maps'
+// activity flags, then their pending-check flags (n_maps each).
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs, const int32_t *flags,
+                                                            int n_maps) {
   DEC_SHARED
-  // the state record lives in LDS while the kernel runs (thread 0's line-search
-  // logic touches it many times), and is written back at the end
+  // one round trip for both flags and the state record (which lives in LDS
+  // while the kernel runs -- thread 0's line-search logic touches it many
+  // times -- and is written back at the end)
+  const int active = flags[blockIdx.x];
+  const int pending = flags[n_maps + blockIdx.x];
   constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
+  if (threadIdx.x == 0) fit_staged = 0;
   __syncthreads();
+  if (active == 0) return;
   FIT_STAMP(sF, 0);
-  // the accuracy check of the last accepted iterate (assigned in this step's
-  // objective launch): its per-block counts, summed in a fixed order
-  if (*sF.assign_pending != 0) {
+  // and one more for the objective at xt and, with a pending accuracy check of
+  // the last accepted iterate (assigned in this step's objective launch), its
+  // per-block counts, summed in a fixed order
+  const double ft = -*sF.phi_t;
+  if (pending != 0) {
     long long c = 0;
     for (int t = threadIdx.x; t < sF.c_items; t += blockDim.x) c += sF.part_c[t];
     c = pd_wave_sum_i64(c);
@@ -836,25 +1029,24 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs) {
   }
   // a map that reached the target or its budget keeps its iterate; this
   // step's evaluation is not used
-  if (sF.status == ST_RUNNING) decide_body(sF, red, slots, coef, gSY, gYY, &action);
+  if (sF.status == ST_RUNNING) decide_body(sF, red, slots, coef, gSY, gYY, &action, ft);
   __syncthreads();
   // the next evaluation's input, while the state is at hand (an accepted step
   // on the multi-block path forms it in k_fit_start)
-  if (sF.status == ST_RUNNING && sF.split_phase == 0) form_trial(sF, sF.t, red);
+  if (sF.status == ST_RUNNING && sF.split_phase == 0) form_trial(sF, sF.t, red, fit_staged != 0);
   __syncthreads();
   FIT_STAMP(sF, 12);
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
 }
 
 __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, int *slots,
-                            double *coef, double *gSY, double *gYY, int *action_p) {
+                            double *coef, double *gSY, double *gYY, int *action_p, double ft) {
   int &action = *action_p;
   const int n = F.NK;
   // gradient of f = -Phi at xt (the reduction writes it with grad_sign = -1),
   // gauge-projected, in graw
   blk_gauge(F, F.graw, red);
   FIT_STAMP(F, 1);
-  const double ft = -*F.phi_t;
   if (threadIdx.x == 0) F.evals++;
   if (F.phase == PH_INIT) {
     if (F.precond) refresh_dinv(F, red);
@@ -880,61 +1072,61 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
     }
     return;
   }
+  // one call site each for the accept and failure paths (they are large)
   if (F.phase == PH_ACCEPT_NEXT) {
-    accept_trial(F, ft, red, slots, coef, gSY, gYY);
-    return;
-  }
-  double dv[1] = {0.0};
-  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
-  blk_sums<1>(dv, red);
-  FIT_STAMP(F, 2);
-  const double dt = dv[0];
-  if (threadIdx.x == 0) {
-    const double t = F.t;
-    // a non-finite objective counts as no sufficient decrease
-    const bool too_big = !(ft <= F.f0 + LS_C1 * t * F.dphi0) || !isfinite(ft);
-    F.ls_evals++;
-    int act = 0;
-    if (F.phase == PH_BRACKET) {
-      if (too_big || (F.ls_evals > 1 && ft >= F.prev_f)) {
-        F.lo_t = F.prev_t; F.lo_f = F.prev_f; F.lo_d = F.prev_d;
-        F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
-        F.phase = PH_ZOOM;
-      } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
-        act = 1;
-      } else if (dt >= 0.0) {
-        F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
-        F.hi_t = F.prev_t; F.hi_f = F.prev_f; F.hi_d = F.prev_d;
-        F.phase = PH_ZOOM;
-      } else {
-        F.prev_t = t; F.prev_f = ft; F.prev_d = dt;
-        F.t = 2.0 * t;
-        if (F.ls_evals >= LS_MAX_EVALS) act = 3;
-      }
-    } else {  // PH_ZOOM
-      if (too_big || ft >= F.lo_f) {
-        F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
-      } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
-        act = 1;
-      } else {
-        if (dt * (F.hi_t - F.lo_t) >= 0.0) {
-          F.hi_t = F.lo_t; F.hi_f = F.lo_f; F.hi_d = F.lo_d;
+    if (threadIdx.x == 0) action = 1;
+  } else {
+    double dv[1] = {0.0};
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
+    blk_sums<1>(dv, red);
+    FIT_STAMP(F, 2);
+    const double dt = dv[0];
+    if (threadIdx.x == 0) {
+      const double t = F.t;
+      // a non-finite objective counts as no sufficient decrease
+      const bool too_big = !(ft <= F.f0 + LS_C1 * t * F.dphi0) || !isfinite(ft);
+      F.ls_evals++;
+      int act = 0;
+      if (F.phase == PH_BRACKET) {
+        if (too_big || (F.ls_evals > 1 && ft >= F.prev_f)) {
+          F.lo_t = F.prev_t; F.lo_f = F.prev_f; F.lo_d = F.prev_d;
+          F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
+          F.phase = PH_ZOOM;
+        } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
+          act = 1;
+        } else if (dt >= 0.0) {
+          F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
+          F.hi_t = F.prev_t; F.hi_f = F.prev_f; F.hi_d = F.prev_d;
+          F.phase = PH_ZOOM;
+        } else {
+          F.prev_t = t; F.prev_f = ft; F.prev_d = dt;
+          F.t = 2.0 * t;
+          if (F.ls_evals >= LS_MAX_EVALS) act = 3;
         }
-        F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
+      } else {  // PH_ZOOM
+        if (too_big || ft >= F.lo_f) {
+          F.hi_t = t; F.hi_f = ft; F.hi_d = dt;
+        } else if (fabs(dt) <= -LS_C2 * F.dphi0) {
+          act = 1;
+        } else {
+          if (dt * (F.hi_t - F.lo_t) >= 0.0) {
+            F.hi_t = F.lo_t; F.hi_f = F.lo_f; F.hi_d = F.lo_d;
+          }
+          F.lo_t = t; F.lo_f = ft; F.lo_d = dt;
+        }
       }
+      if (act == 0 && F.phase == PH_ZOOM) {
+        if (F.ls_evals >= LS_MAX_EVALS) act = 2;
+        else F.t = cubic_min(F.lo_t, F.lo_f, F.lo_d, F.hi_t, F.hi_f, F.hi_d);
+      }
+      action = act;
     }
-    if (act == 0 && F.phase == PH_ZOOM) {
-      if (F.ls_evals >= LS_MAX_EVALS) act = 2;
-      else F.t = cubic_min(F.lo_t, F.lo_f, F.lo_d, F.hi_t, F.hi_f, F.hi_d);
-    }
-    action = act;
   }
   __syncthreads();
   FIT_STAMP(F, 3);
   const int act = action;
   if (act == 1) accept_trial(F, ft, red, slots, coef, gSY, gYY);
-  else if (act == 2) ls_fail(F, F.lo_t, red);
-  else if (act == 3) ls_fail(F, F.prev_t, red);
+  else if (act >= 2) ls_fail(F, act == 2 ? F.lo_t : F.prev_t, red);
 }
 
 // ---- the multi-block path of an accepted step (maps with split set)
@@ -989,7 +1181,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_rec(FitDev *Fs) {
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
   accept_mid(sF, red, slots, coef, gSY, gYY, sF.sp_stored != 0, sF.sp_put, sF.sp_refresh != 0,
-             sF.sp_sy, true);
+             sF.sp_sy);
   if (threadIdx.x == 0) sF.split_phase = 2;
   __syncthreads();
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
@@ -1021,15 +1213,14 @@ __global__ __launch_bounds__(PD_BLOCK) void k_fit_dir(FitDev *Fs, const int32_t 
 __global__ __launch_bounds__(FIT_THREADS) void k_fit_start(FitDev *Fs) {
   if (*Fs[blockIdx.x].active == 0 || Fs[blockIdx.x].split_phase != 2) return;
   __shared__ double red[MAX_WAVES * 48 + 48];
-  __shared__ double coef[8 * HS];
   __shared__ FitDev sF;
   constexpr int NW = (int)(sizeof(FitDev) / sizeof(int));
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&sF)[w] = ((const int *)&Fs[blockIdx.x])[w];
   __syncthreads();
-  accept_tail(sF, red, coef, true);
+  accept_tail(sF, red);
   if (threadIdx.x == 0) sF.split_phase = 0;
   __syncthreads();
-  if (sF.status == ST_RUNNING) form_trial(sF, sF.t, red);
+  if (sF.status == ST_RUNNING) form_trial(sF, sF.t, red, false);
   __syncthreads();
   for (int w = threadIdx.x; w < NW; w += blockDim.x) ((int *)&Fs[blockIdx.x])[w] = ((const int *)&sF)[w];
 }
@@ -1073,7 +1264,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
   }
   // the first evaluation is at the start itself
-  form_trial(F, 0.0, red);
+  form_trial(F, 0.0, red, false);
 }
 
 // ------------------------------------------------------------------ host side
@@ -1175,7 +1366,8 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   }
   // multi-block passes for the large maps (PD_FIT_SPLIT_MIN overrides the size)
   int split_min = FIT_SPLIT_MIN_NK;
-  if (const char *e = getenv("PD_FIT_SPLIT_MIN")) split_min = std::max(1, atoi(e));
+  if (const char *e = getenv("PD_FIT_SPLIT_MIN"))
+    split_min = std::min(FIT_SPLIT_MIN_NK, std::max(1, atoi(e)));  // never above: LDS sizes
   std::vector<int32_t> coff(n + 1, 0);
   std::vector<size_t> o_split(n, 0);
   for (int p = 0; p < n; ++p) {
@@ -1329,7 +1521,7 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   // fixed cost at its boundary; the steps after a map stops are gated off)
   auto step = [&](hipStream_t ss) {
     pd_fit_eval(ctx, P, eval_prec, d_amaps, Pd, ss);
-    k_fit_decide<<<n, vt, 0, ss>>>(dF);
+    k_fit_decide<<<n, vt, 0, ss>>>(dF, flags, n);
     if (total_chunks > 0) {
       k_fit_dots<<<total_chunks, PD_BLOCK, 0, ss>>>(dF, d_coff, n);
       k_fit_rec<<<n, vt, 0, ss>>>(dF);
