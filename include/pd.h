@@ -279,8 +279,8 @@ typedef struct {
  * PD_INIT_MLP / PD_INIT_HEURISTIC run pd_warm_start first (its time counts in
  * seconds_to_target).  Maps with N K >= 1024 run the long vector passes of an
  * accepted step on several blocks; the environment variable PD_FIT_SPLIT_MIN
- * (read at each call) sets that size.  A map's result does not depend on the
- * other maps of its batch. */
+ * (read at each call) lowers that size (values above 1024 act as 1024).  A
+ * map's result does not depend on the other maps of its batch. */
 pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);
@@ -309,9 +309,12 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t
 /* Autotuner of the work decomposition (tile shapes of the gradient kernels:
  * pixel-tile size per 64-grain wave on the FP64/FP32 path, pixel-chunk length
  * per grain group on the BF16 path).  Times one evaluation of the given batch
- * for each candidate (waves per map: 1024 .. 32768), keeps the fastest for the
- * batch's key (precision, largest degree, log2 of the pixel-grain pairs, number
- * of maps) in the context, and uses it in every later plan with that key.  If
+ * for each candidate (waves per map: 1024 .. 32768; five evaluations each),
+ * keeps the fastest for the batch's key (precision, largest degree, log2 of the
+ * pixel-grain pairs, number of maps) in the context -- the default 8192 unless
+ * another is more than 2% faster, so that timing noise does not change the
+ * tiling, and with it the rounding of the gradient sums, between runs -- and
+ * uses it in every later plan with that key.  If
  * the environment variable PD_AUTOTUNE_CACHE names a file, results are read
  * from and appended to it (one "prec dmax size_log2 n_maps waves" line each).
  * Synchronous.  best_waves_out (host, may be NULL) receives the choice. */

@@ -628,9 +628,13 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   PD_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   tune_load(ctx);
+  // candidates timed over five evaluations each; the default (8192) is kept
+  // unless another is more than 2% faster, so timing noise does not flip the
+  // tiling (and with it the rounding of the gradient sums) from run to run
   static const int cand[] = {1024, 2048, 4096, 8192, 16384, 32768};
-  float best_ms = 1e30f;
-  int best = 8192;
+  constexpr int kDefault = 8192;
+  float best_ms = 1e30f, default_ms = 1e30f;
+  int best = kDefault;
   hipEvent_t e0, e1;
   PD_HIP(ctx, hipEventCreate(&e0));
   PD_HIP(ctx, hipEventCreate(&e1));
@@ -663,11 +667,13 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     PD_HIP(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     PD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (w == kDefault) default_ms = ms;
     if (ms < best_ms) {
       best_ms = ms;
       best = w;
     }
   }
+  if (default_ms <= 1.02f * best_ms) best = kDefault;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const auto key = tune_key(probs, n_probs, code);
