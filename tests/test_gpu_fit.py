@@ -201,6 +201,34 @@ def test_preconditioned_iterates_match_oracle(pd, orc, iters):
     assert np.all(x[-1] == 0)
 
 
+@pytest.mark.parametrize("N,side", [(20, 64), (40, 64), (90, 96)])
+@pytest.mark.parametrize("pre", [0, 5])
+def test_single_block_iterates_match_oracle(pd, orc, N, side, pre):
+    """One block per map (N K < 1024): N K = 200, 400 and 900 at d = 3 put up to
+    4, 8 and 16 elements on each lane of the per-wave dot products of the
+    memory; 12 iterations fill the memory past the number of waves, and with the
+    preconditioner cross two refreshes.  Same state machine as the oracle's."""
+    pdl, ctx = pd
+    gm = poly_map(11, side, side, N, 3)
+    d, eps = 3, 1e-3
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    kw = {}
+    if pre:
+        kw = dict(precondition=lambda th: orc.hessian_diag(th, gm.labels, gm.H, gm.W, d, eps),
+                  diag_every=pre)
+    iters = 12
+    ref = orc.lbfgs_fit(obj, np.zeros((gm.N, 10)), target_acc=2.0, max_iter=iters, **kw)
+    th = dev(np.zeros((gm.N, 10)))
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "fp64", init="zero", max_iter=iters,
+                  target_acc=2.0, precondition=pre)[0]
+    assert rep["iters"] == ref["iters"] == iters
+    assert rep["evals"] == ref["evals"]
+    x = th.cpu().numpy()
+    assert np.max(np.abs(x - ref["theta"])) <= 1e-7 * np.max(np.abs(ref["theta"]))
+    assert abs(rep["phi"] - ref["phi"]) <= 1e-9 * abs(ref["phi"])
+    assert np.all(x[-1] == 0)
+
+
 def test_preconditioned_fit_needs_fewer_iterations(pd, orc):
     pdl, ctx = pd
     gm = poly_map(5, 128, 128, 40, 4)
