@@ -42,6 +42,8 @@
 #define FIT_SPLIT_MIN_NK 1024
 #define FIT_SPLIT_CHUNK 512
 #define FIT_PART_W (5 * FIT_MAX_HISTORY + 8)
+// elements per thread whose loads a one-block vector pass issues together
+#define FIT_UNROLL 4
 
 enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
 enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
@@ -387,9 +389,6 @@ __device__ __attribute__((always_inline)) inline void gram_yy(FitDev &F, const i
   }
 }
 
-// One pass over the memory for the live slots k0 .. k0+U-1 (clipped to L):
-// S^T g, Y^T g (in the metric of H0) and, when the new pair is stored, its Gram
-// row and column.  Returns U.
 // The 5 U dot products of the live slots k0 .. k0+U-1 over the elements
 // e0 + tid, e0 + tid + nthr, ... < e1: S^T g, Y^T g (in the metric of H0:
 // Dinv, or the identity), s_new . Y, S . y_new, y_new . Y (same metric).
@@ -407,19 +406,35 @@ __device__ __attribute__((always_inline)) inline void dots_accumulate(
   const bool pre = F.precond != 0;
 #pragma unroll
   for (int q = 0; q < 5 * U; ++q) acc[q] = 0.0;
-  for (int e = e0 + tid; e < e1; e += nthr) {
-    const double gi = pg[e], si = pns[e], yi = pny[e];
-    const double w = pre ? pw[e] : 1.0;
-    const double gw = pre ? gi * w : gi, yw = pre ? yi * w : yi;
+  // two elements per thread at a time, all their loads issued together
+  for (int e = e0 + tid; e < e1; e += 2 * nthr) {
+    double gi[2], si[2], yi[2], w[2], Sj[2][U], Yj[2][U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double Sj = pS[(size_t)js[u] * n + e];
-      const double Yj = pY[(size_t)js[u] * n + e];
-      acc[u] = __builtin_fma(Sj, gi, acc[u]);
-      acc[U + u] = __builtin_fma(Yj, gw, acc[U + u]);
-      acc[2 * U + u] = __builtin_fma(si, Yj, acc[2 * U + u]);
-      acc[3 * U + u] = __builtin_fma(Sj, yi, acc[3 * U + u]);
-      acc[4 * U + u] = __builtin_fma(yw, Yj, acc[4 * U + u]);
+    for (int h = 0; h < 2; ++h) {
+      const int i = e + h * nthr;
+      const bool ok = i < e1;
+      gi[h] = ok ? pg[i] : 0.0;
+      si[h] = ok ? pns[i] : 0.0;
+      yi[h] = ok ? pny[i] : 0.0;
+      w[h] = (ok && pre) ? pw[i] : 1.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        Sj[h][u] = ok ? pS[(size_t)js[u] * n + i] : 0.0;
+        Yj[h][u] = ok ? pY[(size_t)js[u] * n + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (e + h * nthr >= e1) continue;
+      const double gw = pre ? gi[h] * w[h] : gi[h], yw = pre ? yi[h] * w[h] : yi[h];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc[u] = __builtin_fma(Sj[h][u], gi[h], acc[u]);
+        acc[U + u] = __builtin_fma(Yj[h][u], gw, acc[U + u]);
+        acc[2 * U + u] = __builtin_fma(si[h], Yj[h][u], acc[2 * U + u]);
+        acc[3 * U + u] = __builtin_fma(Sj[h][u], yi[h], acc[3 * U + u]);
+        acc[4 * U + u] = __builtin_fma(yw, Yj[h][u], acc[4 * U + u]);
+      }
     }
   }
 }
@@ -516,32 +531,52 @@ __device__ __attribute__((always_inline)) inline void dir_accumulate(
   const auto pg = pd_glb((const double *)F.g);
   const auto pdir = pd_glb(F.d);
   const auto pw = pd_glb((const double *)F.Dinv);
-  for (int i = e0 + tid; i < e1; i += nthr) {
-    const double gi = pg[i];
-    // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
-    double dy = cg * gi, ds = 0.0;
-    // slots in blocks of 16: the 32 loads of a block are issued before use
-    for (int k0 = 0; k0 < L; k0 += 16) {
-      double yv[16], sv[16];
+  const bool pre = F.precond != 0;
+  // two elements per thread at a time: their loads are issued before the stores
+  for (int e = e0 + tid; e < e1; e += 2 * nthr) {
+    double gi[2], w[2], dy[2], ds[2];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        int j = head + min(k0 + u, L - 1);
-        if (j >= M1) j -= M1;
-        yv[u] = pY[(size_t)j * n + i];
-        sv[u] = pS[(size_t)j * n + i];
+    for (int h = 0; h < 2; ++h) {
+      const int i = e + h * nthr;
+      gi[h] = i < e1 ? pg[i] : 0.0;
+      w[h] = (i < e1 && pre) ? pw[i] : 0.0;
+      // d = H0 (cg g + sum coef_y y) + sum coef_s s, H0 = Dinv or the identity
+      dy[h] = cg * gi[h];
+      ds[h] = 0.0;
+    }
+    // slots in blocks of 16: the loads of a block are issued before use
+    for (int k0 = 0; k0 < L; k0 += 16) {
+      double yv[2][16], sv[2][16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = e + h * nthr;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          int j = head + min(k0 + u, L - 1);
+          if (j >= M1) j -= M1;
+          yv[h][u] = i < e1 ? pY[(size_t)j * n + i] : 0.0;
+          sv[h][u] = i < e1 ? pS[(size_t)j * n + i] : 0.0;
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (k0 + u < L) {
-          dy = __builtin_fma(coef[k0 + u], yv[u], dy);
-          ds = __builtin_fma(coef[M1 + k0 + u], sv[u], ds);
-        }
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (k0 + u < L) {
+            dy[h] = __builtin_fma(coef[k0 + u], yv[h][u], dy[h]);
+            ds[h] = __builtin_fma(coef[M1 + k0 + u], sv[h][u], ds[h]);
+          }
     }
-    const double di = F.precond ? __builtin_fma(pw[i], dy, ds) : dy + ds;
-    pdir[i] = di;
-    v[0] = __builtin_fma(gi, gi, v[0]);
-    v[1] = __builtin_fma(gi, di, v[1]);
-    mx = fmax(mx, fabs(gi));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = e + h * nthr;
+      if (i >= e1) continue;
+      const double di = pre ? __builtin_fma(w[h], dy[h], ds[h]) : dy[h] + ds[h];
+      pdir[i] = di;
+      v[0] = __builtin_fma(gi[h], gi[h], v[0]);
+      v[1] = __builtin_fma(gi[h], di, v[1]);
+      mx = fmax(mx, fabs(gi[h]));
+    }
   }
 }
 
@@ -563,9 +598,18 @@ __device__ __attribute__((always_inline)) inline void accept_mid(
   }
   for (int e = threadIdx.x; e < M1; e += blockDim.x) rho[e] = F.rho[e];
   // the blocks' partials (5 values per live slot), added in block order
+  const auto pp = pd_glb((const double *)F.part);
   for (int v = threadIdx.x; v < 5 * L; v += blockDim.x) {
     double t = 0.0;
-    for (int c = 0; c < F.nchunk; ++c) t += F.part[(size_t)c * FIT_PART_W + v];
+    int c = 0;
+    for (; c + 8 <= F.nchunk; c += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = pp[(size_t)(c + u) * FIT_PART_W + v];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += a[u];
+    }
+    for (; c < F.nchunk; ++c) t += pp[(size_t)c * FIT_PART_W + v];
     red[v] = t;
   }
   __syncthreads();
@@ -593,11 +637,30 @@ __device__ __attribute__((always_inline)) inline void accept_mid(
 // search's start.
 __device__ __attribute__((always_inline)) inline void accept_tail(FitDev &F, double *red) {
   if (threadIdx.x == 0) {
+    const auto pp = pd_glb((const double *)F.part);
     double v0 = 0.0, v1 = 0.0, mx = 0.0;
-    for (int c = 0; c < F.nchunk; ++c) {
-      v0 += F.part[(size_t)c * FIT_PART_W];
-      v1 += F.part[(size_t)c * FIT_PART_W + 1];
-      mx = fmax(mx, F.part[(size_t)c * FIT_PART_W + 2]);
+    int c = 0;
+    for (; c + 8 <= F.nchunk; c += 8) {
+      double a[8], b[8], m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const auto row = pp + (size_t)(c + u) * FIT_PART_W;
+        a[u] = row[0];
+        b[u] = row[1];
+        m[u] = row[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v0 += a[u];
+        v1 += b[u];
+        mx = fmax(mx, m[u]);
+      }
+    }
+    for (; c < F.nchunk; ++c) {
+      const auto row = pp + (size_t)c * FIT_PART_W;
+      v0 += row[0];
+      v1 += row[1];
+      mx = fmax(mx, row[2]);
     }
     F.gg = v0;
     F.dphi0 = v1;
@@ -824,23 +887,42 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     const auto pxt = pd_glb((const double *)F.xt);
     const auto pw = pd_glb((const double *)F.Dinv);
     const bool pre = F.precond != 0;
-    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
-      const double di = pd[i], gri = pgr[i], gi = pg[i], xti = pxt[i];
-      const double si = t * di;
-      const double yi = gri - gi;
-      ps[i] = si;
-      py[i] = yi;
-      v3[0] = __builtin_fma(si, yi, v3[0]);
-      v3[1] = __builtin_fma(si, si, v3[1]);
-      v3[2] = __builtin_fma(yi, yi, v3[2]);
-      px[i] = xti;
-      pg[i] = gri;
-      if (!F.split) {
-        fit_vec[FV_G][i] = gri;
-        fit_vec[FV_S][i] = si;
-        fit_vec[FV_Y][i] = yi;
-        fit_vec[FV_W][i] = pre ? pw[i] : 1.0;
-        fit_vec[FV_X][i] = xti;
+    const bool small = !F.split;
+    // FIT_UNROLL elements per thread at a time: every load is issued before
+    // the stores (which the compiler could not otherwise move them past)
+    for (int i0 = (int)threadIdx.x; i0 < n && (int)threadIdx.x < F.vt; i0 += FIT_UNROLL * F.vt) {
+      double dd[FIT_UNROLL], gr[FIT_UNROLL], go[FIT_UNROLL], xx[FIT_UNROLL], ww[FIT_UNROLL];
+#pragma unroll
+      for (int u = 0; u < FIT_UNROLL; ++u) {
+        const int i = i0 + u * F.vt;
+        const bool ok = i < n;
+        dd[u] = ok ? pd[i] : 0.0;
+        gr[u] = ok ? pgr[i] : 0.0;
+        go[u] = ok ? pg[i] : 0.0;
+        xx[u] = ok ? pxt[i] : 0.0;
+        ww[u] = (ok && small && pre) ? pw[i] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < FIT_UNROLL; ++u) {
+        const int i = i0 + u * F.vt;
+        if (i < n) {
+          const double si = t * dd[u];
+          const double yi = gr[u] - go[u];
+          ps[i] = si;
+          py[i] = yi;
+          v3[0] = __builtin_fma(si, yi, v3[0]);
+          v3[1] = __builtin_fma(si, si, v3[1]);
+          v3[2] = __builtin_fma(yi, yi, v3[2]);
+          px[i] = xx[u];
+          pg[i] = gr[u];
+          if (small) {
+            fit_vec[FV_G][i] = gr[u];
+            fit_vec[FV_S][i] = si;
+            fit_vec[FV_Y][i] = yi;
+            fit_vec[FV_W][i] = ww[u];
+            fit_vec[FV_X][i] = xx[u];
+          }
+        }
       }
     }
   }
@@ -941,25 +1023,47 @@ __device__ __attribute__((always_inline)) inline void form_trial(FitDev &F, doub
       F.thc[i] = F.cscale * (fit_vec[FV_XT][i] - red[i % F.K] / (double)F.N);
     return;
   }
-  for (int i = (int)threadIdx.x; i < F.NK && (int)threadIdx.x < F.vt; i += F.vt) F.xt[i] = F.x[i] + t * F.d[i];
+  const auto px = pd_glb((const double *)F.x);
+  const auto pd = pd_glb((const double *)F.d);
+  const auto pxt = pd_glb(F.xt);
+  const auto pth = pd_glb(F.thc);
+  for (int i0 = (int)threadIdx.x; i0 < F.NK && (int)threadIdx.x < F.vt; i0 += FIT_UNROLL * F.vt) {
+    double a[FIT_UNROLL], b[FIT_UNROLL];
+#pragma unroll
+    for (int u = 0; u < FIT_UNROLL; ++u) {
+      const int i = i0 + u * F.vt;
+      a[u] = i < F.NK ? px[i] : 0.0;
+      b[u] = i < F.NK ? pd[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < FIT_UNROLL; ++u)
+      if (i0 + u * F.vt < F.NK) pxt[i0 + u * F.vt] = a[u] + t * b[u];
+  }
   __syncthreads();
+  // column sums over the grains, VG columns at a time (loads of a grain's row
+  // clamped to its last column, so all of them are issued together)
   for (int k0 = 0; k0 < F.K; k0 += VG) {
     double sm[VG];
 #pragma unroll
     for (int q = 0; q < VG; ++q) sm[q] = 0.0;
     const int cnt = min(VG, F.K - k0);
-    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt) {
+      double v[VG];
+#pragma unroll
+      for (int q = 0; q < VG; ++q) v[q] = pxt[(size_t)i * F.K + k0 + min(q, cnt - 1)];
 #pragma unroll
       for (int q = 0; q < VG; ++q)
-        if (q < cnt) sm[q] += F.xt[(size_t)i * F.K + k0 + q];
+        if (q < cnt) sm[q] += v[q];
+    }
     blk_sums<VG>(sm, red);
-    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt)
+    for (int i = (int)threadIdx.x; i < F.N && (int)threadIdx.x < F.vt; i += F.vt) {
+      double v[VG];
+#pragma unroll
+      for (int q = 0; q < VG; ++q) v[q] = pxt[(size_t)i * F.K + k0 + min(q, cnt - 1)];
 #pragma unroll
       for (int q = 0; q < VG; ++q)
-        if (q < cnt) {
-          const size_t e = (size_t)i * F.K + k0 + q;
-          F.thc[e] = F.cscale * (F.xt[e] - sm[q] / (double)F.N);
-        }
+        if (q < cnt) pth[(size_t)i * F.K + k0 + q] = F.cscale * (v[q] - sm[q] / (double)F.N);
+    }
   }
 }
 
@@ -1077,7 +1181,22 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
     if (threadIdx.x == 0) action = 1;
   } else {
     double dv[1] = {0.0};
-    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) dv[0] = __builtin_fma(F.graw[i], F.d[i], dv[0]);
+    {
+      const auto pgr = pd_glb((const double *)F.graw);
+      const auto pd = pd_glb((const double *)F.d);
+      for (int i0 = (int)threadIdx.x; i0 < n && (int)threadIdx.x < F.vt; i0 += FIT_UNROLL * F.vt) {
+        double a[FIT_UNROLL], b[FIT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < FIT_UNROLL; ++u) {
+          const int i = i0 + u * F.vt;
+          a[u] = i < n ? pgr[i] : 0.0;
+          b[u] = i < n ? pd[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < FIT_UNROLL; ++u)
+          if (i0 + u * F.vt < n) dv[0] = __builtin_fma(a[u], b[u], dv[0]);
+      }
+    }
     blk_sums<1>(dv, red);
     FIT_STAMP(F, 2);
     const double dt = dv[0];
