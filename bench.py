@@ -44,6 +44,38 @@ def flops_per_pair(stage: str, d: int) -> int:
     return 2 * d + 4 if stage == "lse" else 4 * d + 3
 
 
+def valu_per_pair(stage: str, d: int):
+    """Vector instructions per (pixel, grain) pair in the FP32 inner loops as
+    compiled for gfx950 (counted in the assembly; one of them the exponential):
+      k_lse,  8 grains per pass: 40 + 8 d (8 d FMAs, 8 moves of the first row
+              coefficient into a vector register -- one scalar operand per
+              instruction --, 4 max3, 9 subtract + 9 exp + 1 multiply for the
+              running rescale, 8 adds)                     -> 5 + d per pair,
+              of which 9/8 exponentials
+      k_grad, per pixel column: d FMAs logit, 1 subtract, 1 exp, 1 add, d FMAs
+              accumulate                                   -> 2 d + 3, 1 exp
+    """
+    if stage == "lse":
+        return 5 + d, 9 / 8
+    return 2 * d + 3, 1.0
+
+
+def issue_ceiling(stage: str, d: int, peaks: dict) -> float:
+    """Pairs/s that the vector issue rate allows: every instruction takes one FMA
+    slot except the exponential, which takes fma_rate / exp_rate slots (measured:
+    the two do not overlap)."""
+    n, n_exp = valu_per_pair(stage, d)
+    fma_rate = peaks["fp32_fma"] / 2  # FMAs per second over all lanes
+    exp_cost = fma_rate / peaks["exp2"]
+    return fma_rate / (n + n_exp * (exp_cost - 1.0))
+
+
+def measured_peaks(pdl, ctx) -> dict:
+    """The unit rates of pd_probe_peak (flop/s; exponentials/s for exp2 and
+    fp32_fma4_exp2, which runs four FMAs per exponential)."""
+    return {k: ctx.probe_peak(k) for k in pdl.Context.PEAK_KINDS}
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch of `kernel` from profiles/traffic_<kernel>.md (FETCH_SIZE
     and WRITE_SIZE per dispatch, each scaled by its copy-kernel calibration
@@ -137,7 +169,7 @@ def time_to_99(pdl, ctx, n_maps, with_net, torch, synth):
     return out
 
 
-def roofline_at_scale(pdl, ctx, torch, synth, n_maps=16):
+def roofline_at_scale(pdl, ctx, torch, synth, peaks, n_maps=16):
     """The evaluation kernels at scale: the c4-style batch (about 6e8 pairs per
     evaluation) at theta = 0, FP32, with its autotuned tiles; flops per pair as in
     flops_per_pair with each map's own degree."""
@@ -154,8 +186,11 @@ def roofline_at_scale(pdl, ctx, torch, synth, n_maps=16):
     for stage in ("lse", "grad"):
         fl = sum(flops_per_pair(stage, p.d) * p.H * p.W * p.N for p in probs)
         ach = fl / (st[stage] * 1e-3) / 1e12
+        # issue-bound time of the batch: each map's pairs at its own degree's ceiling
+        t_min = sum(p.H * p.W * p.N / issue_ceiling(stage, p.d, peaks) for p in probs)
         out[f"k_{stage}"] = {"achieved_tflops": round(ach, 2), "frac": round(ach / PEAK_TFLOPS["fp32"], 4),
-                             "frac_of_nonpacked_fp32": round(ach / (PEAK_TFLOPS["fp32"] / 2), 4)}
+                             "frac_of_nonpacked_fp32": round(ach / (PEAK_TFLOPS["fp32"] / 2), 4),
+                             "frac_of_issue_ceiling": round(t_min / (st[stage] * 1e-3), 4)}
     return out
 
 
@@ -215,6 +250,7 @@ def main():
     run_fit(args.warmup, other)
     secs_o, rep_o, _ = run_fit(args.steps, other)
 
+    peaks = measured_peaks(pdl, ctx)
     # live roofline of the dominant kernel, at the fitted parameters
     st = ctx.profile_eval([prob], [th], args.prec, reps=50)
     dom = max(("lse", "grad"), key=lambda s: st[s])
@@ -225,9 +261,13 @@ def main():
             "traffic": traffic_from_profile(f"k_{dom}"), "kernel": f"k_{dom}",
             "ms_per_launch": round(st[dom], 5), "flops_per_pair": flops_per_pair(dom, d),
             "frac_of_nonpacked": round(achieved / (PEAK_TFLOPS[args.prec] / (2 if args.prec == "fp32" else 1)), 4),
-            "stage_ms": {k: round(v, 5) for k, v in st.items()}}
+            "stage_ms": {k: round(v, 5) for k, v in st.items()},
+            "measured_peaks": {k: float(f"{v:.4g}") for k, v in peaks.items()}}
+    if args.prec == "fp32":
+        roof["frac_of_issue_ceiling"] = round(
+            pairs / issue_ceiling(dom, d, peaks) / (st[dom] * 1e-3), 4)
     t99 = time_to_99(pdl, ctx, args.t99_maps, not args.no_net, torch, synth) if args.t99_maps else None
-    at_scale = roofline_at_scale(pdl, ctx, torch, synth) if args.t99_maps else None
+    at_scale = roofline_at_scale(pdl, ctx, torch, synth, peaks) if args.t99_maps else None
 
     cpu = None
     if not args.no_cpu:

@@ -322,6 +322,17 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_p
                       const double *const *theta /*host*/, pd_precision prec,
                       int32_t *best_waves_out /*host*/, void *stream);
 
+/* Microbenchmark of one unit that bounds the evaluation kernels (measurement
+ * support; not part of the method).  kind: 0 = FP32 FMA (not packed), 1 = the
+ * hardware base-2 exponential v_exp_f32, 2 = four FP32 FMAs per exponential
+ * (shows whether the two overlap), 3 = FP64 FMA, 4 = BF16 matrix-core product
+ * v_mfma_f32_32x32x16_bf16.  rate_out (host): flop/s for kinds 0, 3 and 4 (two
+ * flops per multiply-add), exponentials/s for kinds 1 and 2.  Independent
+ * dependency chains in every thread and a full grid, best of five launches
+ * timed with HIP events.  Uses the evaluation workspace; synchronous.
+ * PD_ERR_INVALID_ARG for another kind. */
+pd_status pd_probe_peak(pd_ctx *ctx, int32_t kind, double *rate_out /*host*/, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

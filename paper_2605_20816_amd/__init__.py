@@ -87,6 +87,8 @@ _SIGS = {
     "pd_profile_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "pd_probe_peak": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
@@ -314,6 +316,16 @@ class Context:
         self._check(lib().pd_profile_eval(self._h, arr, n, _ptrs(thetas), PREC[prec], int(reps),
                                           ms, _stream(stream)))
         return dict(zip(STAGES, list(ms)))
+
+    PEAK_KINDS = ("fp32_fma", "exp2", "fp32_fma4_exp2", "fp64_fma", "mfma_bf16")
+
+    def probe_peak(self, kind, stream=None):
+        """Measured rate of one unit (pd_probe_peak): flop/s for the FMA and
+        matrix-core kinds, exponentials/s for "exp2" and "fp32_fma4_exp2"."""
+        rate = ctypes.c_double(0.0)
+        self._check(lib().pd_probe_peak(self._h, self.PEAK_KINDS.index(kind), ctypes.byref(rate),
+                                        _stream(stream)))
+        return float(rate.value)
 
     def autotune(self, probs, thetas, prec="fp64", stream=None):
         """Time the candidate work decompositions on this batch; returns the chosen

@@ -181,6 +181,8 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   const auto Cvec = pd_glb((const T *)M.C + (size_t)r * M.Npad * DP);
   const int N = M.N;
   T mrun = (T)-INFINITY, S = (T)0;
+  // grains N .. Npad-1 (read when N is not a multiple of 8) have row
+  // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
   for (int i0 = 0; i0 < N; i0 += 8) {
     T s[8];
 #pragma unroll
@@ -189,7 +191,7 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       T v = cp[0];
 #pragma unroll
       for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
-      s[j] = (i0 + j < N) ? v : (T)-INFINITY;
+      s[j] = v;
     }
     T cm = s[0];
 #pragma unroll
