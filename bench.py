@@ -197,8 +197,10 @@ def roofline_at_scale(pdl, ctx, torch, synth, peaks, n_maps=16):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
+    # 2000 steps: the paper's iteration budget, and long enough (~0.1 s) that the
+    # per-call set-up of pd_fit and the GPU's clock state do not move the rate
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--t99-maps", type=int, default=16,
