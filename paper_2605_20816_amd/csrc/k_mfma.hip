@@ -64,30 +64,48 @@ __device__ inline void pix_rc(int r0, int c0, int o, int W, int &r, int &c) {
   }
 }
 
-// All 16 * NKB features of one pixel (zero beyond K or outside the map), then
-// the 8 of block kb for lane half h: v[e] = psi_{16 kb + 8 h + e}.
+// P_a(x1) and P_b(x2) of one pixel for a, b <= the largest exponent that the
+// 16 * NKB features need (zero beyond the degree or outside the map).
 template <int NKB>
-__device__ inline void pixel_feats(const MapDev &M, int r, int c, bool valid, int half,
-                                   float (&v)[NKB][8]) {
-  constexpr int AM = feat_deg(16 * NKB - 1);  // largest exponent needed
-  const float *tx = (const float *)M.txT, *ty = (const float *)M.tyT;
+struct PixTables {
+  static constexpr int AM = feat_deg(16 * NKB - 1);
   float px[AM + 1], py[AM + 1];
+};
+template <int NKB>
+__device__ inline void pixel_tables(const MapDev &M, int r, int c, bool valid, PixTables<NKB> &t) {
+  // global (not flat) loads: they must not hold up the LDS waits of the
+  // products that run while they are in flight
+  const auto tx = pd_glb((const float *)M.txT), ty = pd_glb((const float *)M.tyT);
 #pragma unroll
-  for (int a = 0; a <= AM; ++a) {
-    px[a] = (valid && a <= M.d) ? tx[c * M.DP + a] : 0.f;
-    py[a] = (valid && a <= M.d) ? ty[r * M.DP + a] : 0.f;
+  for (int a = 0; a <= PixTables<NKB>::AM; ++a) {
+    t.px[a] = (valid && a <= M.d) ? tx[c * M.DP + a] : 0.f;
+    t.py[a] = (valid && a <= M.d) ? ty[r * M.DP + a] : 0.f;
   }
+}
+// The 8 features of block kb for lane half h: v[kb][e] = psi_{16 kb + 8 h + e}
+// (zero beyond K).
+template <int NKB>
+__device__ inline void feats_from_tables(const MapDev &M, const PixTables<NKB> &t, int half,
+                                         float (&v)[NKB][8]) {
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k0 = 16 * kb + e, k1 = 16 * kb + 8 + e;
-      const float f0 = px[feat_a(k0)] * py[feat_b(k0)];
-      const float f1 = px[feat_a(k1)] * py[feat_b(k1)];
+      const float f0 = t.px[feat_a(k0)] * t.py[feat_b(k0)];
+      const float f1 = t.px[feat_a(k1)] * t.py[feat_b(k1)];
       const float f = half ? f1 : f0;
       const int k = half ? k1 : k0;
       v[kb][e] = k < M.K ? f : 0.f;
     }
+}
+// All 16 * NKB features of one pixel, the 8 of block kb for lane half h.
+template <int NKB>
+__device__ inline void pixel_feats(const MapDev &M, int r, int c, bool valid, int half,
+                                   float (&v)[NKB][8]) {
+  PixTables<NKB> t;
+  pixel_tables<NKB>(M, r, c, valid, t);
+  feats_from_tables<NKB>(M, t, half, v);
 }
 
 // Three-piece split of 8 FP32 values.
@@ -275,7 +293,8 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ m
 
 // ---------------------------------------------------------------------------
 // k16_grad: block = 4 waves on one pixel chunk, wave w on grain group 4 q + w.
-// Per 32-pixel tile the four waves build the shared operands once in LDS:
+// Per 32-pixel tile the four waves build the shared operands once in LDS (two
+// buffers: tile t + 1 is built while tile t's products run):
 //   sA  [3][NKB][64] x 16 B : psi rows (pixel = row) for the logit product
 //   sQ  [2][2][64]   x 16 B : psi^T (feature = column) in FP16 hi/lo for the
 //                             gradient product, inner index h*8+e of block kb2
@@ -294,7 +313,7 @@ struct GradLds {
 };
 
 template <int NKB>
-__device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh) {
+__device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh)[2]) {
   constexpr int GT = PD_MF_GROUP_TILES;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
@@ -332,59 +351,13 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh)
   const int fa = c_fa[fcol], fb = c_fb[fcol];
   const bool fvalid = col < M.K;
   const float *txf = (const float *)M.txT, *tyf = (const float *)M.tyT;
-  for (int pt = pt0; pt < pt1; ++pt) {
-    const int pbase = pt * 32;
-    const int r0 = pbase / M.W, c0 = pbase - r0 * M.W;
-    __syncthreads();
-    if (wave == 0) {
-      int r, c;
-      pix_rc(r0, c0, col, M.W, r, c);
-      float v[NKB][8];
-      pixel_feats<NKB>(M, r, c, pbase + col < n, half, v);
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) split3(v[kb], sh.A[0][kb][lane], sh.A[1][kb][lane], sh.A[2][kb][lane]);
-    } else if (wave <= 2) {
-      const int kb2 = wave - 1;
-      f16x8 qh, ql;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int o = 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
-        int r, c;
-        pix_rc(r0, c0, o, M.W, r, c);
-        const float v = (fvalid && pbase + o < n) ? txf[c * M.DP + fa] * tyf[r * M.DP + fb] : 0.f;
-        const _Float16 h = (_Float16)v;
-        qh[e] = h;
-        ql[e] = (_Float16)(v - (float)h);
-      }
-      sh.Q[kb2][0][lane] = qh;
-      sh.Q[kb2][1][lane] = ql;
-    } else {
-      int g = -1, lo = 0x7fffffff, hi = -1;
-      if (lane < 32) {
-        const int p = pbase + lane;
-        sh.L[lane] = pd_glb(M.lse32)[p];
-        g = p < n ? pd_glb(M.labels)[p] : -1;
-        sh.G[lane] = g;
-        if (g >= 0) lo = hi = g;
-      }
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, PD_WAVE));
-        hi = max(hi, __shfl_xor(hi, o, PD_WAVE));
-      }
-      if (lane == 0) {
-        sh.lo = lo;
-        sh.hi = hi;
-      }
-    }
-    __syncthreads();
-    if (!active) continue;
+  auto compute_tile = [&](const GradLds &S) {
     bf16x8 ph[NKB], pm[NKB], pl[NKB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
-      ph[kb] = sh.A[0][kb][lane];
-      pm[kb] = sh.A[1][kb][lane];
-      pl[kb] = sh.A[2][kb][lane];
+      ph[kb] = S.A[0][kb][lane];
+      pm[kb] = S.A[1][kb][lane];
+      pl[kb] = S.A[2][kb][lane];
     }
     float lrow[16];
     int grow[16];
@@ -392,8 +365,8 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh)
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        lrow[4 * b + r] = sh.L[8 * b + 4 * half + r];
-        grow[4 * b + r] = sh.G[8 * b + 4 * half + r];
+        lrow[4 * b + r] = S.L[8 * b + 4 * half + r];
+        grow[4 * b + r] = S.G[8 * b + 4 * half + r];
       }
     f32x16 acc[GT];
 #pragma unroll
@@ -419,7 +392,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh)
     for (int t = 0; t < GT; ++t)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]);
-    if (sh.hi >= g0 && sh.lo < g0 + GT * 32) {
+    if (S.hi >= g0 && S.lo < g0 + GT * 32) {
 #pragma unroll
       for (int t = 0; t < GT; ++t) {
         const int grain = g0 + t * 32 + col;
@@ -429,17 +402,108 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds &sh)
     }
 #pragma unroll
     for (int kb2 = 0; kb2 < 2; ++kb2) {
-      const f16x8 qh = sh.Q[kb2][0][lane], ql = sh.Q[kb2][1][lane];
+      const f16x8 qh = S.Q[kb2][0][lane], ql = S.Q[kb2][1][lane];
       f16x8 x[GT];
 #pragma unroll
       for (int t = 0; t < GT; ++t)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[t][e] = (_Float16)acc[t][8 * kb2 + e];
+        for (int e = 0; e < 8; ++e) {
+          // p - delta rounded to FP32, then to FP16 (as above, no fused form)
+          float q = acc[t][8 * kb2 + e];
+          asm volatile("" : "+v"(q));
+          x[t][e] = (_Float16)q;
+        }
 #pragma unroll
       for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], ql, accg[t], 0, 0, 0);
 #pragma unroll
       for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], qh, accg[t], 0, 0, 0);
     }
+  };
+  // Per tile the waves' roles: wave 0 the psi rows, waves 1-2 the psi^T pieces,
+  // wave 3 lse and labels.  The global data of tile pt + 1 is loaded before tile
+  // pt's products and written to the other LDS buffer after them, so one
+  // barrier per tile separates building from use.
+  PixTables<NKB> tab;     // wave 0
+  float qx[8], qy[8];     // waves 1-2
+  float lse_l = 0.f;      // wave 3 (lanes < 32)
+  int lab_l = -1;
+  auto load_tile = [&](int pt) {
+    const int pbase = pt * 32;
+    const int r0 = pbase / M.W, c0 = pbase - r0 * M.W;
+    if (wave == 0) {
+      int r, c;
+      pix_rc(r0, c0, col, M.W, r, c);
+      pixel_tables<NKB>(M, r, c, pbase + col < n, tab);
+    } else if (wave <= 2) {
+      const int kb2 = wave - 1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int o = 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
+        int r, c;
+        pix_rc(r0, c0, o, M.W, r, c);
+        const bool ok = fvalid && pbase + o < n;
+        qx[e] = ok ? pd_glb(txf)[c * M.DP + fa] : 0.f;
+        qy[e] = ok ? pd_glb(tyf)[r * M.DP + fb] : 0.f;
+      }
+    } else if (lane < 32) {
+      const int p = pbase + lane;
+      lse_l = pd_glb(M.lse32)[p];
+      lab_l = p < n ? pd_glb(M.labels)[p] : -1;
+    }
+  };
+  auto build_tile = [&](GradLds &S) {
+    if (wave == 0) {
+      float v[NKB][8];
+      feats_from_tables<NKB>(M, tab, half, v);
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) split3(v[kb], S.A[0][kb][lane], S.A[1][kb][lane], S.A[2][kb][lane]);
+    } else if (wave <= 2) {
+      const int kb2 = wave - 1;
+      f16x8 qh, ql;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        // psi in FP32 first, then its two FP16 pieces (the empty asm keeps the
+        // product from being folded into a mixed-precision FMA that would round
+        // it to FP16 once, without the FP32 step)
+        float v = qx[e] * qy[e];
+        asm volatile("" : "+v"(v));
+        const _Float16 h = (_Float16)v;
+        qh[e] = h;
+        ql[e] = (_Float16)(v - (float)h);
+      }
+      S.Q[kb2][0][lane] = qh;
+      S.Q[kb2][1][lane] = ql;
+    } else {
+      int g = -1, lo = 0x7fffffff, hi = -1;
+      if (lane < 32) {
+        S.L[lane] = lse_l;
+        g = lab_l;
+        S.G[lane] = g;
+        if (g >= 0) lo = hi = g;
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, PD_WAVE));
+        hi = max(hi, __shfl_xor(hi, o, PD_WAVE));
+      }
+      if (lane == 0) {
+        S.lo = lo;
+        S.hi = hi;
+      }
+    }
+  };
+  if (pt0 < pt1) {
+    load_tile(pt0);
+    build_tile(sh[0]);
+  }
+  for (int pt = pt0; pt < pt1; ++pt) {
+    GradLds &cur = sh[(pt - pt0) & 1];
+    if (pt + 1 < pt1) load_tile(pt + 1);
+    __syncthreads();  // cur is built; the other buffer's readers (tile pt - 1) are done
+    if (active) {
+      compute_tile(cur);
+    }
+    if (pt + 1 < pt1) build_tile(sh[(pt - pt0 + 1) & 1]);
   }
   if (!active) return;
   // accg[t]: rows = grains g0 + 32 t + (8 b + 4 h + r), column = feature col
@@ -460,7 +524,7 @@ template <int NKB>
 __global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
                                                      int total) {
-  __shared__ GradLds sh;
+  __shared__ GradLds sh[2];
   if ((int)blockIdx.x >= total) return;
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
