@@ -122,6 +122,32 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs /*host*/, int32
                             double *const *grad_out /*host*/, pd_precision prec,
                             void *stream);
 
+/* Flags of pd_objective_grad_rows. */
+/* The form pd_fit evaluates: the indicator moments m_i = sum_{x in G_i} psi(x) of
+ * eq. grad are computed once per call (FP64, fixed order) and subtracted from the
+ * sums of p_i psi by the FP64 reduction, instead of subtracting psi inside the
+ * gradient kernel.  FP64 / FP32 only (the BF16 kernels always apply the one-hot
+ * term in place; the flag is accepted and has no effect there). */
+#define PD_EVAL_ONEHOT_PRECOMPUTED 1
+
+/* Phi and grad Phi restricted to a band of pixel rows (eq. log-res and eq. grad
+ * with the sum over x limited to the rows [rows[2p], rows[2p+1]) of map p):
+ *   phi_out[p]  = (1/n) sum_{x in rows} log p_{G(x)}(x),
+ *   grad_out[p] = (1/(eps n)) sum_{x in rows} (p(x) - delta_{G(x)}) psi(x),
+ * with n = height * width of the whole map, so the bands of a partition of the
+ * rows sum to Phi and grad Phi (up to rounding).  This is the share of one device
+ * when a map is split by pixel rows (Phi and its gradient are sums over pixels).
+ * rows (host, 2 * n_probs int32): 0 <= begin <= end <= height, else
+ * PD_ERR_INVALID_ARG; an empty band gives 0 and a zero gradient.  Coordinates
+ * and Legendre tables are those of the whole map.  flags: 0 or
+ * PD_EVAL_ONEHOT_PRECOMPUTED.  Other arguments, layout and errors as in
+ * pd_objective_grad (rows = (0, height) for every map, flags 0, is exactly
+ * pd_objective_grad).  Stream-ordered. */
+pd_status pd_objective_grad_rows(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                                 const int32_t *rows /*host*/, const double *const *theta /*host*/,
+                                 double *phi_out, double *const *grad_out /*host*/,
+                                 pd_precision prec, int32_t flags, void *stream);
+
 /* Diagonal of the Hessian of -Phi (eq. hess of Proposition 4.4):
  * diag_out[p][i*K + k] = (1 / (eps^2 n)) sum_x p_i(x) (1 - p_i(x)) psi_k(x)^2 >= 0,
  * the preconditioner of pd_fit.  theta: host array of DEVICE N_p x K_p FP64;
@@ -272,6 +298,11 @@ typedef struct {
   double phi, acc;        /* final Phi and accuracy                               */
   double seconds_total;   /* wall time of this pd_fit call                        */
   double seconds_to_target; /* wall time until Acc >= target_acc (-1 if never)    */
+  double seconds_iterating; /* device time from the first evaluation's decision to
+                               the last accepted iterate: the `iters` iterations,
+                               with their evals_iterating evaluations, accuracy
+                               checks and L-BFGS updates, without set-up          */
+  int32_t evals_iterating;  /* evaluations in that window                          */
 } pd_fit_report;
 
 /* theta_inout: host array of DEVICE N_p x K_p FP64 pointers (start if

@@ -63,8 +63,9 @@ def _load():
     L.orc_objective_grad.argtypes = [c_int, c_int, c_int, c_int, c_dbl, _f64p, _i32p,
                                      ctypes.c_void_p]
     L.orc_objective_grad.restype = c_dbl
-    L.orc_pixel_terms.argtypes = [c_int, c_int, c_int, c_int, c_dbl, _f64p, _i32p, _i64p,
-                                  c_i64, _f64p, _f64p]
+    L.orc_assign_rows.argtypes = [c_int, c_int, c_int, c_int, _f64p, ctypes.c_void_p,
+                                  c_int, c_int, _i32p, ctypes.POINTER(c_i64)]
+    L.orc_assign_rows.restype = c_i64
     L.orc_objective_grad_rows.argtypes = [c_int, c_int, c_int, c_int, c_dbl, _f64p, _i32p,
                                           c_int, c_int, ctypes.c_void_p]
     L.orc_objective_grad_rows.restype = c_dbl
@@ -136,6 +137,22 @@ def assign(theta, H: int, W: int, d: int, labels=None):
     return out, int(nc.value), int(nn)
 
 
+def assign_rows(theta, H: int, W: int, d: int, r0: int, r1: int, labels=None):
+    """Section 2.1 over the pixel rows [r0, r1) only: returns (F of those rows as
+    int32[(r1 - r0) * W], n_correct over them, n_nan)."""
+    th = _theta(theta, d)
+    N = th.shape[0]
+    out = np.full(H * W, -2, np.int32)
+    nc = ctypes.c_int64(0)
+    lab = None
+    if labels is not None:
+        lab = np.ascontiguousarray(labels, dtype=np.int32).reshape(-1)
+    nn = _load().orc_assign_rows(int(H), int(W), int(N), int(d), th.reshape(-1),
+                                 lab.ctypes.data if lab is not None else None, int(r0), int(r1),
+                                 out, ctypes.byref(nc))
+    return out[r0 * W:r1 * W].copy(), int(nc.value), int(nn)
+
+
 def objective_grad(theta, labels, H: int, W: int, d: int, eps: float, grad: bool = True):
     """eq:Phi and eq:grad: returns (Phi, grad N x K or None); L = n * Phi."""
     th = _theta(theta, d)
@@ -153,7 +170,9 @@ def objective_grad(theta, labels, H: int, W: int, d: int, eps: float, grad: bool
 
 
 def objective_rows(theta, labels, H, W, d, eps, r0, r1, grad=True):
-    """Sum over rows [r0, r1) of log p_G(x) and of (delta - p) eta (no scaling)."""
+    """eq:Phi and eq:grad summed over the pixel rows [r0, r1) only, unscaled:
+    (sum of log p_G(x), sum of (delta_G - p) psi as N x K).  Over a partition of
+    the rows these sum to n Phi and -(eps n) grad Phi."""
     th = _theta(theta, d)
     lab = np.ascontiguousarray(labels, dtype=np.int32).reshape(-1)
     g = np.zeros_like(th) if grad else None
@@ -161,18 +180,6 @@ def objective_rows(theta, labels, H, W, d, eps, r0, r1, grad=True):
                                         th.reshape(-1), lab, int(r0), int(r1),
                                         g.ctypes.data if g is not None else None)
     return float(v), g
-
-
-def pixel_terms(theta, labels, H, W, d, eps, pixels):
-    """lse(x) and log p_G(x) at the given flat pixel indices."""
-    th = _theta(theta, d)
-    lab = np.ascontiguousarray(labels, dtype=np.int32).reshape(-1)
-    pix = np.ascontiguousarray(pixels, dtype=np.int64)
-    lse = np.zeros(pix.size, np.float64)
-    ell = np.zeros(pix.size, np.float64)
-    _load().orc_pixel_terms(int(H), int(W), int(th.shape[0]), int(d), float(eps), th.reshape(-1),
-                            lab, pix, int(pix.size), lse, ell)
-    return lse, ell
 
 
 def softmax_probs(theta, H, W, d, eps):

@@ -125,18 +125,21 @@ static inline void cs_add(csum *a, double v) {
 static inline double cs_val(const csum *a) { return a->s + a->c; }
 
 /* Section 2.1 induced map F_theta with the smallest-index tie-break of the
-   minimisation-diagram cells, and the accuracy Acc^G of Section 2.2.
+   minimisation-diagram cells, and the accuracy Acc^G of Section 2.2, over the
+   pixel rows [r0, r1) of the H x W map (coordinates of the whole map).
    theta: N x K row-major.  labels may be NULL (then n_correct is 0).
-   out[j] = F_theta(x_j), or -1 if any score of x_j is NaN.
-   Returns the number of pixels with a NaN score. */
-int64_t orc_assign(int H, int W, int N, int d, const double *theta,
-                   const int32_t *labels, int32_t *out, int64_t *n_correct) {
+   out[j] = F_theta(x_j) for the pixels j of those rows (indices of the whole
+   map), or -1 if any score of x_j is NaN.  Returns the number of pixels with a
+   NaN score. */
+int64_t orc_assign_rows(int H, int W, int N, int d, const double *theta,
+                        const int32_t *labels, int r0, int r1, int32_t *out,
+                        int64_t *n_correct) {
   int K = orc_num_features(d);
   int A[64], B[64];
   orc_multi_index(d, A, B);
   int64_t correct = 0, nan_count = 0;
 #pragma omp parallel for schedule(static) reduction(+ : correct, nan_count)
-  for (int r = 0; r < H; ++r) {
+  for (int r = r0; r < r1; ++r) {
     double psi[64];
     for (int c = 0; c < W; ++c) {
       pixel_features(r, c, H, W, d, A, B, psi);
@@ -160,6 +163,12 @@ int64_t orc_assign(int H, int W, int N, int d, const double *theta,
   }
   if (n_correct) *n_correct = correct;
   return nan_count;
+}
+
+/* F_theta and Acc^G over the whole map. */
+int64_t orc_assign(int H, int W, int N, int d, const double *theta,
+                   const int32_t *labels, int32_t *out, int64_t *n_correct) {
+  return orc_assign_rows(H, W, N, d, theta, labels, 0, H, out, n_correct);
 }
 
 /* Per-pixel terms of Section 2.3 / Section 4 (eq:Phi):
@@ -250,35 +259,12 @@ double orc_objective_grad(int H, int W, int N, int d, double eps,
   return cs_val(&tot) / n;
 }
 
-/* Per-pixel lse(x) and ell(x) = log p_G(x) at the listed pixel indices, for
-   checking sampled outputs of large maps one by one. */
-void orc_pixel_terms(int H, int W, int N, int d, double eps,
-                     const double *theta, const int32_t *labels,
-                     const int64_t *pix, int64_t npix, double *lse_out,
-                     double *ell_out) {
-  int K = orc_num_features(d);
-  int A[64], B[64];
-  orc_multi_index(d, A, B);
-#pragma omp parallel
-  {
-    double *s = (double *)malloc(sizeof(double) * (size_t)N);
-    double psi[64];
-#pragma omp for schedule(static)
-    for (int64_t q = 0; q < npix; ++q) {
-      int64_t j = pix[q];
-      int r = (int)(j / W), c = (int)(j % W);
-      pixel_features(r, c, H, W, d, A, B, psi);
-      double lse;
-      double ell = pixel_terms(theta, psi, N, K, eps, labels[j], s, &lse);
-      if (lse_out) lse_out[q] = lse;
-      if (ell_out) ell_out[q] = ell;
-    }
-    free(s);
-  }
-}
-
-/* Objective over a subset of rows [r0, r1) only (Phi's partial sum, not
-   divided by n): used to time the oracle on a bounded sample of a large map. */
+/* eq:Phi and eq:grad with the sum over x restricted to the pixel rows [r0, r1)
+   (coordinates of the whole map), unscaled: returns sum_x log p_G(x) and writes
+   grad_partial[i*K + k] = sum_x (delta_{i,G(x)} - p_i(x)) psi_k(x) (NULL skips it).
+   Summed over a partition of the rows these are n Phi and -(eps n) grad Phi.
+   Used for checking row bands of large maps and for timing the oracle on a
+   bounded sample. */
 double orc_objective_grad_rows(int H, int W, int N, int d, double eps,
                                const double *theta, const int32_t *labels,
                                int r0, int r1, double *grad_partial) {

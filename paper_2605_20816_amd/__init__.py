@@ -59,7 +59,8 @@ class _Mlp(ctypes.Structure):
 class _FitReport(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
                 ("phi", ctypes.c_double), ("acc", ctypes.c_double),
-                ("seconds_total", ctypes.c_double), ("seconds_to_target", ctypes.c_double)]
+                ("seconds_total", ctypes.c_double), ("seconds_to_target", ctypes.c_double),
+                ("seconds_iterating", ctypes.c_double), ("evals_iterating", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,6 +79,11 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                          ctypes.c_void_p]),
+    "pd_objective_grad_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem),
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                              ctypes.c_int32, ctypes.c_void_p]),
     "pd_assign": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                  ctypes.c_void_p, ctypes.c_void_p]),
@@ -281,6 +287,26 @@ class Context:
                                             _stream(stream)))
         return phi, grads
 
+    def objective_grad_rows(self, probs, thetas, rows, prec="fp64", onehot_precomputed=False,
+                            grad=True, stream=None):
+        """Phi and grad Phi summed over the row band [r0, r1) of each map (rows: one
+        (r0, r1) pair per map), both scaled by 1/n of the whole map.  With
+        onehot_precomputed, the evaluation takes the form pd_fit uses."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        dev = thetas[0].device
+        _check_thetas(probs, thetas)
+        if len(rows) != n:
+            raise ValueError("one (r0, r1) pair per map")
+        rr = (ctypes.c_int32 * (2 * n))(*[int(v) for pair in rows for v in pair])
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        grads = [torch.empty_like(t) for t in thetas] if grad else None
+        self._check(lib().pd_objective_grad_rows(
+            self._h, arr, n, rr, _ptrs(thetas), ctypes.c_void_p(phi.data_ptr()),
+            _ptrs(grads) if grad else None, PREC[prec],
+            1 if onehot_precomputed else 0, _stream(stream)))
+        return phi, grads
+
     def hessian_diag(self, probs, thetas, prec="fp64", stream=None):
         """Diagonal of the Hessian of -Phi (N x K float64 per map)."""
         n = len(probs)
@@ -354,7 +380,9 @@ class Context:
                                  _stream(stream)))
         return [dict(status=FIT_STATUS.get(r.status, r.status), iters=r.iters, evals=r.evals,
                      phi=r.phi, acc=r.acc, seconds_total=r.seconds_total,
-                     seconds_to_target=r.seconds_to_target) for r in reps]
+                     seconds_to_target=r.seconds_to_target,
+                     seconds_iterating=r.seconds_iterating,
+                     evals_iterating=r.evals_iterating) for r in reps]
 
     # ------------------------------------------------------------ warm start
     def descriptors(self, probs, frames=False, stream=None):

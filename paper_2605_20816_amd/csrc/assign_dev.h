@@ -23,9 +23,10 @@ __device__ inline void assign_block(const MapDev &M, int base, double *sth) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
   const int local = base + wave;
-  const bool wave_valid = local < M.H * M.segs;
-  const int r = wave_valid ? local / M.segs : 0;
-  const int c = wave_valid ? (local - r * M.segs) * PD_WAVE + lane : M.W;
+  const bool wave_valid = local < M.rows * M.segs;
+  const int lr = wave_valid ? local / M.segs : 0;
+  const int r = M.row0 + lr;
+  const int c = wave_valid ? (local - lr * M.segs) * PD_WAVE + lane : M.W;
   const bool valid = c < M.W;
   const int cc = valid ? c : M.W - 1;
   const auto px = pd_glb(M.tx64 + (size_t)cc * DP);

@@ -80,12 +80,13 @@ static void choose_tiles(int H, int W, int Npad, int target_waves, int &tr, int 
   if (px < 64) px = 64;
   tc = (int)std::min<long long>(std::min(W, 256), px);
   long long rows = px / tc;
-  if (rows < 1) rows = 1;
   if (rows > H) rows = H;
+  if (rows < 1) rows = 1;  // also for an empty row range (no tiles then)
   tr = (int)rows;
 }
 
-void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec) {
+void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec,
+                    const int32_t *rows) {
   P.n = n;
   P.prec = prec;
   P.maps.assign(n, MapDev{});
@@ -101,6 +102,12 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
   P.max_hw = 0;
   P.max_k = 0;
   int max_d = 1;
+  for (int p = 0; p < n; ++p) max_d = std::max(max_d, probs[p].degree);
+  // BF16 path: the matrix-core kernels run 16-feature blocks up to the batch's
+  // largest degree (one block to degree 4, two above), so every map's thc pieces
+  // are padded to that width: a map of lower degree reads zeros, not the next
+  // grain's row, in the blocks beyond its own features
+  const int kp_batch = pd_dmax_bucket(max_d) <= 4 ? 16 : 32;
   const size_t tsz = prec == 0 ? 8 : 4;  // FP32 tables for the FP32 and BF16 paths
   for (int p = 0; p < n; ++p) {
     const pd_problem &q = probs[p];
@@ -114,15 +121,17 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.DP = q.degree + 1;
     M.Npad = (q.n_grains + PD_WAVE - 1) / PD_WAVE * PD_WAVE;
     M.segs = (q.width + PD_WAVE - 1) / PD_WAVE;
+    M.row0 = rows ? rows[2 * p] : 0;
+    M.rows = rows ? rows[2 * p + 1] - rows[2 * p] : q.height;
     M.eps = q.eps;
     M.grad_scale = 1.0 / (q.eps * (double)q.height * (double)q.width);
     M.grad_sign = 1.0;
     M.labels = q.labels;
-    choose_tiles(M.H, M.W, M.Npad, P.target_waves, M.tile_rows, M.tile_cols);
-    M.tiles_r = (M.H + M.tile_rows - 1) / M.tile_rows;
+    choose_tiles(M.rows, M.W, M.Npad, P.target_waves, M.tile_rows, M.tile_cols);
+    M.tiles_r = (M.rows + M.tile_rows - 1) / M.tile_rows;
     M.tiles_c = (M.W + M.tile_cols - 1) / M.tile_cols;
     // row-segment items, padded to whole blocks so a block never spans two maps
-    M.a_items = (M.H * M.segs + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
+    M.a_items = (M.rows * M.segs + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
     // gradient work list: super-tiles of 4 tiles (block-summed partials) for
     // degree <= 4, else one tile per partial (a property of the map alone, so a
     // map's result does not depend on its batch)
@@ -131,11 +140,11 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.b_items = (M.stiles * M.st_size * (M.Npad / PD_WAVE) + PD_WAVES_PER_BLOCK - 1) /
                 PD_WAVES_PER_BLOCK * PD_WAVES_PER_BLOCK;
     M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
-    const long long n_px = (long long)M.H * M.W;
+    const long long n_px = (long long)M.rows * M.W;  // evaluated pixels
     const bool mf = prec == 2;
     // BF16 matrix-core path: 32-pixel tiles; k16_lse blocks of 16 tiles;
     // k16_grad waves = pixel chunks x 128-grain groups (about 4096 waves)
-    M.Kp = (M.K + 15) / 16 * 16;
+    M.Kp = kp_batch;
     M.n32 = (int)((n_px + 31) / 32 * 32);
     M.tiles32 = M.n32 / 32;
     M.a16_items = (M.tiles32 + 15) / 16;
@@ -143,9 +152,10 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     {
       // about target_waves / 2 waves of k16_grad (4 grain groups per block)
       long long ct = (long long)M.tiles32 * ((M.ggroups + 3) / 4 * 4) / std::max(1, P.target_waves / 2);
+      if (ct > M.tiles32) ct = M.tiles32;
       if (ct < 1) ct = 1;
-      M.chunk_tiles = (int)std::min<long long>(ct, M.tiles32);
-      M.chunks = (M.tiles32 + M.chunk_tiles - 1) / M.chunk_tiles;
+      M.chunk_tiles = (int)ct;
+      M.chunks = (M.tiles32 + M.chunk_tiles - 1) / M.chunk_tiles;  // 0 for no pixels
     }
     M.b16_items = M.chunks * ((M.ggroups + 3) / 4);  // k16_grad blocks
     R.tx64 = L.take(sizeof(double) * M.W * M.DP);
@@ -153,7 +163,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.txT = L.take(tsz * M.W * M.DP);
     R.tyT = L.take(tsz * M.H * M.DP);
     R.thc = L.take(sizeof(double) * M.N * M.K);
-    R.C = L.take(mf ? 0 : tsz * (size_t)M.H * M.Npad * M.DP);
+    R.C = L.take(mf ? 0 : tsz * (size_t)M.rows * M.Npad * M.DP);
     R.lse = L.take(mf ? 0 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
@@ -165,7 +175,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
     P.offA[p + 1] = P.offA[p] + M.a_items;
     P.offB[p + 1] = P.offB[p] + M.b_items;
-    P.offP[p + 1] = P.offP[p] + (int)(((long long)M.H * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
+    P.offP[p + 1] = P.offP[p] + (int)(((long long)M.rows * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
     P.offR[p + 1] = P.offR[p] + M.r_items;
     P.off16P[p + 1] = P.off16P[p] + (int)(((long long)M.Npad * M.Kp + PD_BLOCK - 1) / PD_BLOCK);
     P.off16A[p + 1] = P.off16A[p] + M.a16_items;
@@ -176,7 +186,6 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.r_off = P.offR[p];
     P.max_hw = std::max(P.max_hw, std::max(M.H, M.W));
     P.max_k = std::max(P.max_k, M.K);
-    max_d = std::max(max_d, M.d);
   }
   P.dmax = pd_dmax_bucket(max_d);
   P.o_maps = L.take(sizeof(MapDev) * n);
@@ -429,9 +438,11 @@ pd_status pd_validate(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs, voi
   return PD_OK;
 }
 
-pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
-                            const double *const *theta, double *phi_out,
-                            double *const *grad_out, pd_precision prec, void *stream) {
+// Shared by pd_objective_grad and pd_objective_grad_rows (rows: null or checked).
+static pd_status objective_grad_impl(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                                     const int32_t *rows, const double *const *theta,
+                                     double *phi_out, double *const *grad_out, pd_precision prec,
+                                     int32_t flags, void *stream) {
   if (!ctx) return PD_ERR_INVALID_ARG;
   ctx->err.clear();
   int code = 0;
@@ -439,26 +450,48 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_prob
   if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
   if (!theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta is NULL");
   if (!phi_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "phi_out is NULL");
+  if (flags & ~PD_EVAL_ONEHOT_PRECOMPUTED) return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown flags");
   for (int p = 0; p < n_probs; ++p) {
     pd_status st = pd_check_problem(ctx, probs[p], p);
     if (st != PD_OK) return st;
     if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta[" + std::to_string(p) + "] is NULL");
+    if (rows && !(0 <= rows[2 * p] && rows[2 * p] <= rows[2 * p + 1] && rows[2 * p + 1] <= probs[p].height))
+      return pd_fail(ctx, PD_ERR_INVALID_ARG,
+                     "map " + std::to_string(p) + ": rows must satisfy 0 <= begin <= end <= height");
   }
   PD_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  if (code == 2) return pd_bf16_objective_grad(ctx, probs, n_probs, theta, phi_out, grad_out, s);
+  if (code == 2) return pd_bf16_objective_grad(ctx, probs, n_probs, rows, theta, phi_out, grad_out, s);
   EvalPlan P;
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
-  pd_plan_layout(P, L, probs, n_probs, code);
+  P.onehot_pre = (flags & PD_EVAL_ONEHOT_PRECOMPUTED) != 0;
+  pd_plan_layout(P, L, probs, n_probs, code, rows);
   pd_status st = pd_reserve(ctx, L.off);
   if (st != PD_OK) return st;
   pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
   PD_HIP(ctx, pd_plan_upload(ctx, P, s));
   pd_plan_tables(P, s);
+  if (P.any_grad) pd_plan_onehot(P, s);
   pd_plan_eval(P, P.any_grad, s, true);
   PD_HIP(ctx, hipGetLastError());
   return PD_OK;
+}
+
+pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                            const double *const *theta, double *phi_out,
+                            double *const *grad_out, pd_precision prec, void *stream) {
+  return objective_grad_impl(ctx, probs, n_probs, nullptr, theta, phi_out, grad_out, prec, 0,
+                             stream);
+}
+
+pd_status pd_objective_grad_rows(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                                 const int32_t *rows, const double *const *theta,
+                                 double *phi_out, double *const *grad_out, pd_precision prec,
+                                 int32_t flags, void *stream) {
+  if (ctx && !rows) return pd_fail(ctx, PD_ERR_INVALID_ARG, "rows is NULL");
+  return objective_grad_impl(ctx, probs, n_probs, rows, theta, phi_out, grad_out, prec, flags,
+                             stream);
 }
 
 pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,

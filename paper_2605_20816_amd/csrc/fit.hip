@@ -73,6 +73,10 @@ struct FitDev {
   double f, t, f0, dphi0, gamma, acc, gg, gmax;
   double prev_t, prev_f, prev_d, lo_t, lo_f, lo_d, hi_t, hi_f, hi_d;
   uint64_t clk_start, clk_target;
+  // device clock at the decision on the first evaluation and at the last accepted
+  // iterate, and the evaluation count at that iterate (the report's step timing)
+  uint64_t clk_first, clk_last;
+  int32_t evals_last;
   uint64_t *trace;  // optional stage stamps of the decision kernel (PD_FIT_TRACE builds)
   // multi-block passes of an accepted step (maps with N K >= FIT_SPLIT_MIN_NK):
   // phase 1 = the memory's dot products are pending (k_fit_dots, k_fit_rec),
@@ -941,6 +945,8 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     F.reset_tried = 0;
     F.f = ft;
     F.iters++;
+    F.clk_last = wall_clock64();
+    F.evals_last = F.evals;
   }
   __syncthreads();
   if (F.iters >= F.max_iter) {
@@ -1162,6 +1168,8 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
     if (threadIdx.x == 0 && F.precond) *F.want_diag = (1 % F.precond) == 0 ? 1 : 0;
     if (threadIdx.x == 0) {
       F.f = ft;
+      F.clk_first = F.clk_last = wall_clock64();
+      F.evals_last = F.evals;
       if (!isfinite(ft)) {
         fit_stop(F, ST_NONFINITE);
       } else {
@@ -1378,6 +1386,8 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     F.gamma = 1.0;
     F.acc = -1.0;
     F.clk_target = 0;
+    F.clk_first = F.clk_last = 0;
+    F.evals_last = 0;
     *F.active = 1;
     *F.assign_pending = 0;
     if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
@@ -1719,6 +1729,10 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     r.phi = -f.f;
     r.acc = (double)h_nc[p] / (double)f.n_pix;
     r.seconds_total = std::chrono::duration<double>(t_end - t_call).count();
+    r.seconds_iterating = rate_khz > 0 && f.clk_last >= f.clk_first
+                              ? (double)(f.clk_last - f.clk_first) / ((double)rate_khz * 1e3)
+                              : 0.0;
+    r.evals_iterating = f.evals_last > 0 ? f.evals_last - 1 : 0;
     r.seconds_to_target = -1.0;
     // host set-up before the first device work, plus device time to the target
     if (f.status == ST_TARGET && rate_khz > 0 && f.clk_target >= f.clk_start)

@@ -130,7 +130,7 @@ template <typename T, int D>
 __device__ inline void prep_one(const MapDev &M, int r, int i) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  T *out = (T *)M.C + ((size_t)r * M.Npad + i) * DP;
+  T *out = (T *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP;
   if (i >= M.N) {
     out[0] = (T)-INFINITY;
 #pragma unroll
@@ -155,9 +155,9 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
-  if (flat >= (long long)M.H * M.Npad) return;
-  const int r = (int)(flat / M.Npad), i = (int)(flat - (long long)r * M.Npad);
-  PD_DISPATCH_D(M.d, (prep_one<T, D>(M, r, i)));
+  if (flat >= (long long)M.rows * M.Npad) return;
+  const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
+  PD_DISPATCH_D(M.d, (prep_one<T, D>(M, M.row0 + lr, i)));
 }
 
 // ---------------------------------------------------------------------------
@@ -165,20 +165,21 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
 template <typename T, int D>
 __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
-  if (local >= M.H * M.segs) {  // padding item (item counts are multiples of 4)
+  if (local >= M.rows * M.segs) {  // padding item (item counts are multiples of 4)
     if (lane == 0) pd_glb(M.part_l)[local] = 0.0;
     return;
   }
-  const int r = local / M.segs;
-  const int c = (local - r * M.segs) * PD_WAVE + lane;
+  const int lr = local / M.segs;  // row within the evaluated rows
+  const int r = M.row0 + lr;
+  const int c = (local - lr * M.segs) * PD_WAVE + lane;
   const bool valid = c < M.W;
   const int cc = valid ? c : M.W - 1;
   const auto tx = pd_glb((const T *)M.txT + (size_t)cc * DP);
   T px[DP];
 #pragma unroll
   for (int a = 0; a < DP; ++a) px[a] = tx[a];
-  const auto Crow = pd_uni((const T *)M.C + (size_t)r * M.Npad * DP);
-  const auto Cvec = pd_glb((const T *)M.C + (size_t)r * M.Npad * DP);
+  const auto Crow = pd_uni((const T *)M.C + (size_t)lr * M.Npad * DP);
+  const auto Cvec = pd_glb((const T *)M.C + (size_t)lr * M.Npad * DP);
   const int N = M.N;
   T mrun = (T)-INFINITY, S = (T)0;
   // grains N .. Npad-1 (read when N is not a multiple of 8) have row
@@ -206,7 +207,7 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   double ell = 0.0;
   if (valid) {
     const size_t j = (size_t)r * M.W + c;
-    pd_glb((T *)M.lse)[j] = lse;
+    pd_glb((T *)M.lse)[(size_t)lr * M.W + c] = lse;
     const int g = pd_glb(M.labels)[j];
     if (g >= 0 && g < N) {
       const auto cg = Cvec + (size_t)g * DP;
@@ -297,8 +298,8 @@ __device__ inline GradItem grad_item_of(const MapDev &M, int local) {
     return g;
   }
   const int tr = tile / M.tiles_c, tcol = tile - tr * M.tiles_c;
-  g.r0 = tr * M.tile_rows;
-  g.r1 = min(g.r0 + M.tile_rows, M.H);
+  g.r0 = M.row0 + tr * M.tile_rows;
+  g.r1 = min(g.r0 + M.tile_rows, M.row0 + M.rows);
   g.c0 = tcol * M.tile_cols;
   g.c1 = min(g.c0 + M.tile_cols, M.W);
   return g;
@@ -415,14 +416,14 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
   for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
   const auto txT = pd_uni((const T *)M.txT);
   for (int r = r0; r < r1; ++r) {
-    const auto cp = pd_glb((const T *)M.C + ((size_t)r * M.Npad + i) * DP);
+    const auto cp = pd_glb((const T *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
     T cf[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) cf[a] = cp[a];
     T racc[DP], dacc[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) racc[a] = dacc[a] = (T)0;
-    const auto lrow = pd_uni((const T *)M.lse + (size_t)r * M.W);
+    const auto lrow = pd_uni((const T *)M.lse + (size_t)(r - M.row0) * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
     int c = c0;
     for (; c + CH <= c1; c += CH)
@@ -721,6 +722,7 @@ void pd_launch_center(const MapDev *maps, int n_maps, int max_k, hipStream_t s) 
 }
 void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps, int blocks,
                     hipStream_t s) {
+  if (blocks <= 0) return;  // no rows to evaluate (empty row bands)
   if (prec == 0) k_prep<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
   else k_prep<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
 }
@@ -735,6 +737,7 @@ void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps
 void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                    int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (blocks <= 0) return;
   if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse, double, dmax, blocks, s, maps, off, n_maps, total); }
   else { PD_LAUNCH_BY_DMAX(k_lse, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
@@ -753,6 +756,7 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
 void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                           int total, const MapDev *amaps, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (blocks <= 0) return;
   if (dmax > 4) {
     // the FP64 scores of degree > 4 would raise the objective half's register
     // count: two launches instead
@@ -771,6 +775,7 @@ void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t 
 void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                     int total, bool diag, bool hot, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (blocks <= 0) return;
   if (prec == 0) PD_LAUNCH_GRAD(k_grad, double, dmax, hot, blocks, s, maps, off, n_maps, total);
   else PD_LAUNCH_GRAD(k_grad, float, dmax, hot, blocks, s, maps, off, n_maps, total);
   if (diag) {
@@ -782,7 +787,8 @@ void pd_launch_grad(int prec, int dmax, const MapDev *maps, const int32_t *off, 
 void pd_launch_onehot(int dmax, const MapDev *maps, const int32_t *off_b, int n_maps, int total,
                       const int32_t *off_r, int blocks_r, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  switch (dmax) {
+  // with no pixels the partials are never read: k_reduce_onehot sums zero tiles
+  if (blocks > 0) switch (dmax) {
     case 2: k_onehot<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
     case 4: k_onehot<4><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;
     case 6: k_onehot<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off_b, n_maps, total); break;

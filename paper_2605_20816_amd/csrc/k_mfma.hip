@@ -177,13 +177,16 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
   const int tile0 = blk * (4 * TPW) + wave * TPW;
   // B operands: psi^T of this wave's tiles (pixel = column), three pieces
   bf16x8 bh[TPW][NKB], bm[TPW][NKB], bl[TPW][NKB];
-  const int n = M.H * M.W;
+  // p: index among the evaluated pixels (rows row0 .. row0 + rows - 1, row-major);
+  // q = pix0 + p: index in the whole map
+  const int npx = M.rows * M.W, pix0 = M.row0 * M.W;
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int p = (tile0 + t) * 32 + col;
-    const int r = p / M.W, c = p - r * M.W;
+    const int q = pix0 + p;
+    const int r = q / M.W, c = q - r * M.W;
     float v[NKB][8];
-    pixel_feats<NKB>(M, r, c, p < n, half, v);
+    pixel_feats<NKB>(M, r, c, p < npx, half, v);
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) split3(v[kb], bh[t][kb], bm[t][kb], bl[t][kb]);
   }
@@ -258,12 +261,13 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
     const float lse = mm + __builtin_amdgcn_logf(ss);
     const int p = (tile0 + t) * 32 + col;
     if (half == 0 && p < M.n32) {
-      pd_glb(M.lse32)[p] = p < n ? lse : INFINITY;
-      if (p < n) {
-        const int g = pd_glb(M.labels)[p];
+      pd_glb(M.lse32)[p] = p < npx ? lse : INFINITY;
+      if (p < npx) {
+        const int q = pix0 + p;
+        const int g = pd_glb(M.labels)[q];
         if (g >= 0 && g < M.N) {
           // exact FP64 logit of the true grain
-          const int r = p / M.W, c = p - r * M.W;
+          const int r = q / M.W, c = q - r * M.W;
           const double *px = M.tx64 + (size_t)c * M.DP, *py = M.ty64 + (size_t)r * M.DP;
           const double *th = M.thc + (size_t)g * M.K;
           double sg = 0.0;
@@ -344,7 +348,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   for (int t = 0; t < GT; ++t)
 #pragma unroll
     for (int j = 0; j < 16; ++j) accg[t][j] = 0.f;
-  const int n = M.H * M.W;
+  const int npx = M.rows * M.W, pix0 = M.row0 * M.W;  // evaluated pixels, first one
   const int pt0 = chunk * M.chunk_tiles;
   const int pt1 = min(pt0 + M.chunk_tiles, M.tiles32);
   const int fcol = col < M.K ? col : 0;
@@ -429,11 +433,11 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   int lab_l = -1;
   auto load_tile = [&](int pt) {
     const int pbase = pt * 32;
-    const int r0 = pbase / M.W, c0 = pbase - r0 * M.W;
+    const int r0 = (pix0 + pbase) / M.W, c0 = pix0 + pbase - r0 * M.W;
     if (wave == 0) {
       int r, c;
       pix_rc(r0, c0, col, M.W, r, c);
-      pixel_tables<NKB>(M, r, c, pbase + col < n, tab);
+      pixel_tables<NKB>(M, r, c, pbase + col < npx, tab);
     } else if (wave <= 2) {
       const int kb2 = wave - 1;
 #pragma unroll
@@ -441,14 +445,14 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
         const int o = 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
         int r, c;
         pix_rc(r0, c0, o, M.W, r, c);
-        const bool ok = fvalid && pbase + o < n;
+        const bool ok = fvalid && pbase + o < npx;
         qx[e] = ok ? pd_glb(txf)[c * M.DP + fa] : 0.f;
         qy[e] = ok ? pd_glb(tyf)[r * M.DP + fb] : 0.f;
       }
     } else if (lane < 32) {
       const int p = pbase + lane;
       lse_l = pd_glb(M.lse32)[p];
-      lab_l = p < n ? pd_glb(M.labels)[p] : -1;
+      lab_l = p < npx ? pd_glb(M.labels)[pix0 + p] : -1;
     }
   };
   auto build_tile = [&](GradLds &S) {
@@ -585,10 +589,12 @@ void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
     k16_prep<<<P.off16P[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16P, P.n);
   } else if (stage == 1) {
     const int total = P.off16A[P.n];
+    if (total <= 0) return;  // no rows to evaluate (empty row bands)
     if (nkb == 1) k16_lse<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
     else k16_lse<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
   } else if (stage == 2) {
     const int total = P.off16B[P.n];  // blocks: chunks x ceil(grain groups / 4)
+    if (total <= 0) return;
     if (nkb == 1) k16_grad<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
     else k16_grad<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
   } else {
@@ -602,15 +608,15 @@ void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) 
 }
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
-                                 const double *const *theta, double *phi_out,
-                                 double *const *grad_out, hipStream_t s) {
+                                 const int32_t *rows, const double *const *theta,
+                                 double *phi_out, double *const *grad_out, hipStream_t s) {
   for (int p = 0; p < n; ++p)
     if (probs[p].degree > 6)
       return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
   EvalPlan P;
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n, 2);
-  pd_plan_layout(P, L, probs, n, 2);
+  pd_plan_layout(P, L, probs, n, 2, rows);
   pd_status st = pd_reserve(ctx, L.off);
   if (st != PD_OK) return st;
   pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);

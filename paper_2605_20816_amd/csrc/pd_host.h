@@ -68,7 +68,10 @@ struct EvalPlan {
 pd_status pd_fail(pd_ctx *c, pd_status s, const std::string &msg);
 pd_status pd_check_problem(pd_ctx *ctx, const pd_problem &p, int idx);
 pd_status pd_reserve(pd_ctx *ctx, size_t bytes);
-void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec);
+// rows (may be null): 2 entries per map, the evaluated rows [rows[2p], rows[2p+1])
+// (already checked); null evaluates every row.
+void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int prec,
+                    const int32_t *rows = nullptr);
 void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
                   double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
@@ -83,8 +86,8 @@ void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center,
 void pd_plan_assign(const EvalPlan &P, hipStream_t s);
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
-                                 const double *const *theta, double *phi_out,
-                                 double *const *grad_out, hipStream_t s);
+                                 const int32_t *rows, const double *const *theta,
+                                 double *phi_out, double *const *grad_out, hipStream_t s);
 void pd_fit_release(pd_ctx *ctx);
 // BF16 path: stage 0 prep (thc pieces), 1 log-sum-exp, 2 gradient, 3 reductions.
 void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s);

@@ -24,6 +24,10 @@ struct MapDev {
   // problem
   int32_t H, W, N, d, K, DP, Npad;  // DP = d + 1; Npad = N rounded up to 64
   int32_t segs;                     // ceil(W / 64): 64-pixel row segments
+  // evaluated rows [row0, row0 + rows): the whole map (0, H), or one slab of it
+  // (the share of one device when a map is split by pixel rows).  Coordinates,
+  // tables and the 1/n of Phi and grad Phi always refer to the whole H x W map.
+  int32_t row0, rows;
   double eps;
   double grad_scale;                // 1 / (eps * n)
   double grad_sign;                 // +1: grad = dPhi/dtheta; -1: its negative (the fit's f = -Phi)
@@ -36,8 +40,8 @@ struct MapDev {
   double *ty64;                     // [H][DP]  P_b(x2) at each row, FP64
   void *txT;                        // [W][DP]  the same in the evaluation type
   double *thc;                      // [N][K]   -log2(e)/eps * (theta_i - mean_j theta_j)
-  void *C;                          // [H][Npad][DP] row coefficients, evaluation type
-  void *lse;                        // [n] base-2 log-sum-exp per pixel, evaluation type
+  void *C;                          // [rows][Npad][DP] row coefficients, evaluation type
+  void *lse;                        // [rows * W] base-2 log-sum-exp per pixel, evaluation type
   double *part_l;                   // [a_items] per-wave partial sums of log2 p_G
   double *part_g;                   // [stiles][Npad][K] partial sums of (p - delta) psi, or of
                                     // p psi when onehot is set
@@ -59,9 +63,11 @@ struct MapDev {
   // FP32 row table and the BF16 matrix-core path
   void *tyT;                        // [H][DP] P_b(x2) in the evaluation type
   void *T3;                         // [3][Npad][Kp] bf16 pieces of thc
-  float *lse32;                     // [n32] base-2 log-sum-exp (+inf on padding pixels)
+  float *lse32;                     // [n32] base-2 log-sum-exp of the evaluated pixels
+                                    // (+inf on padding pixels)
   float *part_g32;                  // [chunks][Npad][32] partial gradient moments
-  int32_t Kp, n32, tiles32;         // K rounded up to 16; pixels rounded up to 32; 32-pixel tiles
+  int32_t Kp, n32, tiles32;         // feature width of the BF16 pieces; evaluated pixels
+                                    // rounded up to 32; 32-pixel tiles
   int32_t a16_items, b16_items;     // blocks of k16_lse; waves of k16_grad
   int32_t chunk_tiles, chunks, ggroups;
   // Hessian diagonal sum_x p_i (1 - p_i) psi_k^2 / (eps^2 n) of -Phi (eq. hess),

@@ -23,6 +23,8 @@ Pixel (r, c) of an H x W map sits at ((2c+1-W)/W, (2r+1-H)/H).
 """
 from __future__ import annotations
 
+import hashlib
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -115,7 +117,8 @@ def anisotropic_power_diagram(H, W, N, rng, wmax=0.02, lmin=0.5, lmax=2.0):
                     aniso=A[keep], keep=keep)
 
 
-def polynomial_diagram(H, W, N, D, rng):
+def _polynomial_parts(H, W, N, D, rng):
+    """Draws of a random polynomial diagram and its per-row score function."""
     h = 2.0 / np.sqrt(N)
     y = rng.uniform(-1.0, 1.0, size=(N, 2))
     w = rng.uniform(0.0, 0.125 * h * h, size=N)
@@ -135,10 +138,45 @@ def polynomial_diagram(H, W, N, D, rng):
         ca = C @ Vy[r]                           # N x (D+1) over a
         return ca @ Vx.T                         # N x W
 
-    lab = _argmin_rows(H, W, row)
-    lab, keep = _compact(lab, N)
+    return C, y, w, sigma, h, row
+
+
+def polynomial_diagram(H, W, N, D, rng, cache=None):
+    """Random polynomial diagram of degree D.  With ``cache`` (a path), the
+    uncompacted arg-min labels are read from that file when it holds this map
+    (same H, W, N, D and the same coefficients), and written to it otherwise."""
+    C, y, w, sigma, h, row = _polynomial_parts(H, W, N, D, rng)
+    raw = _cached_labels(cache, H, W, N, D, C) if cache else None
+    if raw is None:
+        raw = _argmin_rows(H, W, row)
+        if cache:
+            _store_labels(cache, H, W, N, D, C, raw)
+    lab, keep = _compact(raw, N)
     return GrainMap(H, W, lab, keep.size, "poly", D, coef=C[keep], sites=y[keep],
                     weights=w[keep], keep=keep, meta=dict(sigma=sigma, h=h))
+
+
+def _coef_digest(C):
+    return hashlib.sha256(np.ascontiguousarray(C, dtype=np.float64).tobytes()).hexdigest()
+
+
+def _cached_labels(path, H, W, N, D, C):
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        if (tuple(int(v) for v in z["shape"]) != (H, W, N, D)
+                or str(z["coef_sha256"]) != _coef_digest(C)):
+            return None
+        return z["raw"].astype(np.int32).reshape(-1)
+
+
+def _store_labels(path, H, W, N, D, C, raw):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    dt = np.int16 if N <= 32767 else np.int32
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, raw=raw.astype(dt), shape=np.array([H, W, N, D]),
+                        coef_sha256=np.array(_coef_digest(C)))
+    os.replace(tmp, path)
 
 
 def boundary_noise(gm: GrainMap, frac, rng):
@@ -224,12 +262,28 @@ def config_c4_map(j, seed=404):
     return gm
 
 
-def config_c5(seed=505, H=2048, W=2048, N=5000, D=6):
-    """2048x2048 random degree-6 polynomial diagram, N = 5000; d = 6."""
+CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cache")
+
+
+def config_c5(seed=505, H=2048, W=2048, N=5000, D=6, use_cache=True):
+    """2048x2048 random degree-6 polynomial diagram, N = 5000; d = 6.  The arg-min
+    labels (about 90 s of CPU work) are kept in synth/cache/, keyed by the
+    diagram's coefficients; tests regenerate sampled rows to check the file."""
     rng = np.random.default_rng(seed)
-    gm = polynomial_diagram(H, W, N, D, rng)
+    cache = None
+    if use_cache:
+        cache = os.path.join(CACHE_DIR, f"poly_{H}x{W}_N{N}_D{D}_seed{seed}.npz")
+    gm = polynomial_diagram(H, W, N, D, rng, cache=cache)
     gm.meta.update(degree=D, eps=1e-3)
     return gm
+
+
+def config_c5_rows(rows, seed=505, H=2048, W=2048, N=5000, D=6):
+    """Uncompacted arg-min labels of the given rows of the c5 map, computed
+    directly (no cache): a check of the cached file."""
+    rng = np.random.default_rng(seed)
+    _, _, _, _, _, row = _polynomial_parts(H, W, N, D, rng)
+    return np.stack([np.argmin(row(r), axis=0).astype(np.int32) for r in rows])
 
 
 def training_map(k, base=10000, H=256, W=256, D=6):

@@ -219,8 +219,10 @@ def test_power_and_anisotropic_maps_reconstruct(orc):
 
 # ---------------------------------------------------------------- objective ---
 
-def _mp_phi_grad(theta, labels, H, W, d, eps, orc, dps=40):
-    """40-digit Phi and gradient from exact rational scores (eq:Phi, eq:grad)."""
+def _mp_phi_grad(theta, labels, H, W, d, eps, orc, dps=40, rows=None):
+    """40-digit Phi and gradient from exact rational scores (eq:Phi, eq:grad).
+    With rows = (r0, r1): the unscaled sums over those pixel rows only,
+    (sum of log p_G, sum of (delta - p) psi)."""
     mpmath.mp.dps = dps
     N, K = theta.shape
     a, b = orc.multi_index(d)
@@ -238,6 +240,8 @@ def _mp_phi_grad(theta, labels, H, W, d, eps, orc, dps=40):
 
     for j, f in enumerate(sc):
         r, c = divmod(j, W)
+        if rows is not None and not rows[0] <= r < rows[1]:
+            continue
         Px, Py = leg(Fraction(2 * c + 1 - W, W), d), leg(Fraction(2 * r + 1 - H, H), d)
         psi = [Px[a[k]] * Py[b[k]] for k in range(K)]
         s = [-(mpmath.mpf(fi.numerator) / fi.denominator) / e for fi in f]
@@ -250,6 +254,8 @@ def _mp_phi_grad(theta, labels, H, W, d, eps, orc, dps=40):
             wgt = (1 if i == g else 0) - mpmath.exp(s[i] - lse)
             for k in range(K):
                 grad[i][k] += wgt * (mpmath.mpf(psi[k].numerator) / psi[k].denominator)
+    if rows is not None:
+        return float(total), np.array([[float(v) for v in row] for row in grad])
     phi = total / n
     G = np.array([[float(-v / (e * n)) for v in row] for row in grad])
     return float(phi), G
@@ -266,6 +272,55 @@ def test_objective_gradient_40_digit(orc):
         phi_x, g_x = _mp_phi_grad(th, lab, H, W, d, eps, orc)
         assert abs(phi - phi_x) <= 1e-14 * max(1.0, abs(phi_x))
         assert np.max(np.abs(g - g_x)) <= 1e-13 * np.max(np.abs(g_x))
+
+
+def test_row_bands_40_digit_and_partition(orc):
+    """eq:Phi and eq:grad restricted to pixel rows (the share of one device when a
+    map is split by rows): each band against 40-digit arithmetic over the same
+    rows, and the bands of a partition sum to n Phi and -(eps n) grad Phi."""
+    rng = np.random.default_rng(31)
+    H, W, N, d, eps = 7, 5, 4, 2, 0.07
+    a, b = orc.multi_index(d)
+    th = synth.random_theta(N, d, rng, scale=0.5, multi_index=(a, b))
+    lab = synth.random_labels(H, W, N, rng)
+    cuts = [0, 2, 3, 7]
+    tot, gtot = 0.0, np.zeros_like(th)
+    for r0, r1 in zip(cuts[:-1], cuts[1:]):
+        v, g = orc.objective_rows(th, lab, H, W, d, eps, r0, r1)
+        vx, gx = _mp_phi_grad(th, lab, H, W, d, eps, orc, rows=(r0, r1))
+        assert abs(v - vx) <= 1e-14 * max(1.0, abs(vx))
+        assert np.max(np.abs(g - gx)) <= 1e-13 * np.max(np.abs(gx))
+        tot += v
+        gtot += g
+    phi, gf = orc.objective_grad(th, lab, H, W, d, eps)
+    n = H * W
+    assert abs(tot - n * phi) <= 1e-13 * abs(n * phi)
+    assert np.max(np.abs(gtot + eps * n * gf)) <= 1e-13 * np.max(np.abs(gtot))
+    v, g = orc.objective_rows(th, lab, H, W, d, eps, 3, 3)
+    assert v == 0.0 and not g.any()
+
+
+def test_assign_rows_is_the_band_of_the_full_assignment(orc):
+    """Section 2.1 over a band of rows: exactly the full map's labels there, and
+    the band counts of a partition add up to the full count."""
+    rng = np.random.default_rng(32)
+    H, W, N, d = 9, 11, 6, 3
+    th = synth.random_theta(N, d, rng, multi_index=orc.multi_index(d))
+    lab = synth.random_labels(H, W, N, rng)
+    F, nc, _ = orc.assign(th, H, W, d, lab)
+    ex = _exact_scores(th, H, W, d, orc)
+    tot = 0
+    for r0, r1 in ((0, 4), (4, 5), (5, 9)):
+        Fb, ncb, nn = orc.assign_rows(th, H, W, d, r0, r1, lab)
+        assert nn == 0 and np.array_equal(Fb, F[r0 * W:r1 * W])
+        for j in range(r0 * W, r1 * W):
+            sc = ex[j]
+            best = min(range(N), key=lambda i: (sc[i], i))
+            gap = min(float(sc[i] - sc[best]) for i in range(N) if i != best)
+            if gap > 1e-12:
+                assert Fb[j - r0 * W] == best
+        tot += ncb
+    assert tot == nc
 
 
 def test_phi_at_zero_and_gradient_closed_form(orc):
