@@ -289,6 +289,20 @@ typedef struct {
                              the newest pair, every search starting at t = 1.
                              Gauge PD_GAUGE_LAST_ZERO.  With PD_BF16, D comes
                              from an FP32 evaluation at the refresh iterates.      */
+  /* Schedule of eps (annealing; Section 5.2 and the end of Section 5.6.4 leave it
+   * to future work).  anneal_levels S = 0: one fit at each map's eps.  S > 0:
+   * levels eps_k = eps * anneal_factor^(S - k), k = 0 .. S, each an L-BFGS fit
+   * (fresh memory) from the previous level's theta; level k < S has a budget of
+   * min(anneal_iters, max_iter - k anneal_iters) iterations, the last level
+   * max_iter - S anneal_iters.  Since F_theta does not depend on eps (Lemma 4.1),
+   * a map stops at the first accepted iterate of any level whose accuracy
+   * reaches target_acc.  The report sums iterations, evaluations and times over
+   * the levels, gives the status of the map's last level (budget for a map that
+   * ran out inside the schedule), and phi = Phi at the map's own eps.  The init
+   * modes apply to the first level (the warm start's scale search at eps_0).  */
+  int32_t anneal_levels;  /* 0 .. 30                                             */
+  double anneal_factor;   /* > 1 when anneal_levels > 0                          */
+  int32_t anneal_iters;   /* >= 1 when anneal_levels > 0                         */
 } pd_fit_opts;
 
 typedef struct {

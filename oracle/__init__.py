@@ -229,4 +229,4 @@ def gauge_project(v, mode: str):
     return v
 
 
-from .lbfgs import lbfgs_fit, newton_fit  # noqa: E402,F401
+from .lbfgs import annealed_fit, lbfgs_fit, newton_fit  # noqa: E402,F401

@@ -250,3 +250,45 @@ def newton_fit(theta0, objective, hessian, *, gauge_last=True, tol=1e-12, max_it
             t *= 0.5
         x = xn
     return x
+
+
+def annealed_fit(objective_eps, theta0, eps, *, stages, factor, stage_iters, accuracy=None,
+                 target_acc=0.99, max_iter=2000, **fit_kw):
+    """The fit with a decreasing schedule of the regularisation parameter, the
+    annealing that Section 5.2 and the end of Section 5.6.4 leave to future work:
+    eps_k = eps * factor**(stages - k), k = 0 .. stages, each level maximising
+    Phi_{eps_k} with lbfgs_fit from the previous level's final theta (a new
+    L-BFGS memory per level, since the curvature of Phi_eps scales with 1/eps^2).
+    Levels k < stages run at most stage_iters iterations; the last one runs the
+    rest of the max_iter budget.  Stopping is aligned with Err: the hard assignment
+    F_theta does not depend on eps (Lemma 4.1 and the end of Section 5.6.4), so the
+    first accepted iterate of any level with Acc >= target_acc ends the whole fit.
+
+    objective_eps(theta, e) -> (Phi_e(theta), grad).  Returns lbfgs_fit's dict for
+    the whole run (iters and evals summed over the levels; status of the last
+    level; phi = Phi_eps at the final theta, at the target eps whichever level
+    stopped) plus "levels": per level (eps_k, iters, evals, status, acc)."""
+    if stages < 0 or not (factor > 1.0) or stage_iters < 0:
+        raise ValueError("stages >= 0, factor > 1, stage_iters >= 0")
+    x = np.array(theta0, np.float64)
+    levels, records = [], []
+    iters = evals = 0
+    res = None
+    for k in range(stages + 1):
+        e_k = eps * factor ** (stages - k)
+        budget = max_iter - iters if k == stages else min(stage_iters, max_iter - iters)
+        res = lbfgs_fit(lambda th, e=e_k: objective_eps(th, e), x, accuracy=accuracy,
+                        target_acc=target_acc, max_iter=budget, **fit_kw)
+        x = res["theta"]
+        iters += res["iters"]
+        evals += res["evals"]
+        records.extend(res["records"])
+        levels.append(dict(eps=e_k, iters=res["iters"], evals=res["evals"],
+                           status=res["status"], acc=res["acc"]))
+        if res["status"] in ("target", "nonfinite") or iters >= max_iter and k < stages:
+            if res["status"] != "target" and k < stages:
+                res = dict(res, status="budget")
+            break
+    phi = res["phi"] if levels[-1]["eps"] == eps else float(objective_eps(x, eps)[0])
+    return dict(theta=x, phi=phi, acc=res["acc"], iters=iters, evals=evals,
+                status=res["status"], records=records, levels=levels)

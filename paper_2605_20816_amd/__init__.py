@@ -49,7 +49,8 @@ class _FitOpts(ctypes.Structure):
                 ("history", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("target_acc", ctypes.c_double), ("gtol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("precondition", ctypes.c_int32)]
+                ("precondition", ctypes.c_int32), ("anneal_levels", ctypes.c_int32),
+                ("anneal_factor", ctypes.c_double), ("anneal_iters", ctypes.c_int32)]
 
 
 class _Mlp(ctypes.Structure):
@@ -366,15 +367,17 @@ class Context:
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
             max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, precondition=0,
-            stream=None):
+            anneal=None, stream=None):
         """Device L-BFGS fit of every map; thetas are updated in place.
+        anneal: None, or (levels, factor, iters per level) for the schedule of eps.
         Returns a list of report dicts."""
         n = len(probs)
         arr = (_Problem * n)(*[p.c() for p in probs])
         h = None if mlp is None else mlp.handle()
+        al, af, ai = anneal if anneal is not None else (0, 0.0, 0)
         opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
                         check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p),
-                        int(precondition))
+                        int(precondition), int(al), float(af), int(ai))
         reps = (_FitReport * n)()
         self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
                                  _stream(stream)))

@@ -28,6 +28,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <cmath>
 #include <vector>
 
 #define FIT_THREADS 512
@@ -98,6 +99,8 @@ struct FitDev {
 
 struct FitState {
   hipStream_t stream = nullptr;
+  double *phi_buf = nullptr;  // Phi at the maps' own eps after an annealed fit
+  size_t phi_cap = 0;
 };
 
 // ------------------------------------------------------------------ block helpers
@@ -1408,6 +1411,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
 void pd_fit_release(pd_ctx *ctx) {
   if (ctx->fit) {
     if (ctx->fit->stream) (void)hipStreamDestroy(ctx->fit->stream);
+    if (ctx->fit->phi_buf) (void)hipFree(ctx->fit->phi_buf);
     delete ctx->fit;
     ctx->fit = nullptr;
   }
@@ -1428,9 +1432,11 @@ static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *
   }
 }
 
-extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
-                            double *const *theta_inout, const pd_fit_opts *opts,
-                            pd_fit_report *reports, void *stream) {
+// One level of the fit: L-BFGS on Phi at each map's own eps (the body of pd_fit
+// without a schedule of eps).
+static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
+                           double *const *theta_inout, const pd_fit_opts *opts,
+                           pd_fit_report *reports, void *stream) {
   using clk = std::chrono::steady_clock;
   const auto t_call = clk::now();
   if (!ctx) return PD_ERR_INVALID_ARG;
@@ -1745,5 +1751,115 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
       r.seconds_to_target = r.seconds_total;
     }
   }
+  return PD_OK;
+}
+
+// The fit with an optional schedule of eps (annealing): levels
+// eps_k = eps * anneal_factor^(S - k), k = 0 .. S = anneal_levels, each level a
+// fit_level call from the previous level's theta with a fresh L-BFGS memory (the
+// curvature of Phi_eps scales with 1/eps^2).  Level k < S has the budget
+// min(anneal_iters, max_iter - k anneal_iters) iterations, the last level
+// max_iter - S anneal_iters (budgets by the schedule, whatever a level used).
+// F_theta does not depend on eps (Lemma 4.1), so a map that reaches the target
+// accuracy at any level stops there (Err-aligned stopping); the other maps go on
+// to the next level, in one batched call.
+extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
+                            double *const *theta_inout, const pd_fit_opts *opts,
+                            pd_fit_report *reports, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!probs || n < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta_inout || !opts || !reports)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta_inout, opts and reports must be non-NULL");
+  if (opts->anneal_levels < 0 || opts->anneal_levels > 30)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_levels must be in [0, 30]");
+  if (opts->anneal_levels == 0) return fit_level(ctx, probs, n, theta_inout, opts, reports, stream);
+  if (!(opts->anneal_factor > 1.0) || !std::isfinite(opts->anneal_factor))
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_factor must be finite and > 1");
+  if (opts->anneal_iters < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_iters must be >= 1");
+  if (opts->max_iter < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "max_iter must be >= 0");
+  using clk = std::chrono::steady_clock;
+  const auto t_call = clk::now();
+  const int S = opts->anneal_levels;
+  std::vector<int> live(n), last_level(n, 0);
+  for (int p = 0; p < n; ++p) live[p] = p;
+  std::vector<double> before(n, 0.0);  // seconds of the earlier levels, per map
+  for (int p = 0; p < n; ++p) {
+    reports[p] = pd_fit_report{};
+    reports[p].status = ST_BUDGET;
+    reports[p].seconds_to_target = -1.0;
+  }
+  for (int k = 0; k <= S && !live.empty(); ++k) {
+    const long long spent = (long long)k * opts->anneal_iters;
+    const long long left = std::max(0LL, (long long)opts->max_iter - spent);
+    const int budget = (int)(k == S ? left : std::min<long long>(opts->anneal_iters, left));
+    if (budget == 0 && k < S) break;  // the budget ends inside the schedule
+    const double f = std::pow(opts->anneal_factor, (double)(S - k));
+    const int nl = (int)live.size();
+    std::vector<pd_problem> pk(nl);
+    std::vector<double *> tk(nl);
+    for (int q = 0; q < nl; ++q) {
+      pk[q] = probs[live[q]];
+      pk[q].eps = probs[live[q]].eps * f;
+      tk[q] = theta_inout[live[q]];
+    }
+    pd_fit_opts ok = *opts;
+    ok.anneal_levels = 0;
+    ok.max_iter = budget;
+    if (k > 0) ok.init = PD_INIT_GIVEN;  // from the last level's theta
+    std::vector<pd_fit_report> rk(nl);
+    const pd_status st = fit_level(ctx, pk.data(), nl, tk.data(), &ok, rk.data(), stream);
+    if (st != PD_OK) return st;
+    std::vector<int> next;
+    for (int q = 0; q < nl; ++q) {
+      const int p = live[q];
+      pd_fit_report &r = reports[p];
+      const pd_fit_report &x = rk[q];
+      r.status = x.status == ST_TARGET || x.status == ST_NONFINITE || k == S ? x.status : ST_BUDGET;
+      r.iters += x.iters;
+      r.evals += x.evals;
+      r.phi = x.phi;
+      r.acc = x.acc;
+      r.seconds_iterating += x.seconds_iterating;
+      r.evals_iterating += x.evals_iterating;
+      if (x.status == ST_TARGET && x.seconds_to_target >= 0.0)
+        r.seconds_to_target = before[p] + x.seconds_to_target;
+      before[p] += x.seconds_total;
+      last_level[p] = k;
+      if (x.status != ST_TARGET && x.status != ST_NONFINITE) next.push_back(p);
+    }
+    live.swap(next);
+  }
+  // phi at each map's own eps for the maps that stopped above the last level
+  std::vector<int> redo;
+  for (int p = 0; p < n; ++p)
+    if (last_level[p] != S) redo.push_back(p);
+  if (!redo.empty()) {
+    const int nr = (int)redo.size();
+    std::vector<pd_problem> pr(nr);
+    std::vector<const double *> th(nr);
+    for (int q = 0; q < nr; ++q) {
+      pr[q] = probs[redo[q]];
+      th[q] = theta_inout[redo[q]];
+    }
+    if (!ctx->fit) ctx->fit = new FitState();
+    if ((int)ctx->fit->phi_cap < nr) {
+      if (ctx->fit->phi_buf) (void)hipFree(ctx->fit->phi_buf);
+      ctx->fit->phi_buf = nullptr;
+      ctx->fit->phi_cap = 0;
+      FIT_HIP(ctx, hipMalloc((void **)&ctx->fit->phi_buf, sizeof(double) * nr));
+      ctx->fit->phi_cap = nr;
+    }
+    const pd_status st =
+        pd_objective_grad(ctx, pr.data(), nr, th.data(), ctx->fit->phi_buf, nullptr, PD_FP64, stream);
+    if (st != PD_OK) return st;
+    std::vector<double> ph(nr);
+    FIT_HIP(ctx, hipMemcpyAsync(ph.data(), ctx->fit->phi_buf, sizeof(double) * nr,
+                                hipMemcpyDeviceToHost, (hipStream_t)stream));
+    FIT_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    for (int q = 0; q < nr; ++q) reports[redo[q]].phi = ph[q];
+  }
+  const double total = std::chrono::duration<double>(clk::now() - t_call).count();
+  for (int p = 0; p < n; ++p) reports[p].seconds_total = total;
   return PD_OK;
 }

@@ -82,9 +82,13 @@ def test_c2_after_benchmark_steps_and_at_the_fit(pd, orc):
     x = th.cpu().numpy()
     check(ctx, orc, [p], [gm], [x], "fp64", 1e-10, 1e-10)
     check(ctx, orc, [p], [gm], [x], "fp32", 2e-3, 2e-3)
-    # a fitted iterate (>= 99% accuracy), where p - delta cancels most
+    # a fitted iterate (>= 99% accuracy), where p - delta cancels most: the
+    # preconditioned FP32 fit gets there in about 1600 iterations (the plain FP64
+    # fit needs about 2700 on this noisy map)
     th = torch.zeros((gm.N, 6), dtype=torch.float64, device="cuda")
-    rep = ctx.fit([p], [th], "fp64", init="zero", max_iter=2000, target_acc=0.99)[0]
+    rep = ctx.fit([p], [th], "fp32", init="zero", max_iter=4000, target_acc=0.99, history=16,
+                  precondition=40, check_every=8)[0]
+    print(f"c2 fit: {rep['iters']} iterations, acc {rep['acc']:.4f}")
     assert rep["status"] == "target"
     x = th.cpu().numpy()
     for prec in ("fp64", "fp32", "bf16"):

@@ -577,3 +577,71 @@ def test_preconditioned_fit_reaches_target_in_fewer_iterations(orc):
     assert r0["status"] == r1["status"] == "target"
     assert r1["iters"] < r0["iters"]
     assert np.all(r1["theta"][-1] == 0)
+
+
+# ------------------------------------------------ eps annealing (f2) --------
+
+def test_preconditioned_fit_is_eps_covariant(orc):
+    """Lemma 4.1 (Phi_eps(theta) = Phi_1(theta / eps)) carried through the fit: the
+    diagonal-preconditioned L-BFGS (unit first step, D scaling as 1/eps^2) from
+    theta0 at eps takes the iterates eps * u_k of the same fit at eps = 1 from
+    theta0 / eps, so rescaling the start and changing eps are the same thing
+    (the end of Section 5.6.4)."""
+    gm = synth.polynomial_diagram(24, 20, 6, 2, np.random.default_rng(31))
+    d, eps = 2, 1e-2
+    K = orc.num_features(d)
+    th0 = synth.random_theta(gm.N, d, np.random.default_rng(32), scale=0.02,
+                             multi_index=orc.multi_index(d))
+    th0 = th0 - th0[-1]
+    traj = {}
+    for e, start in ((eps, th0), (1.0, th0 / eps)):
+        xs = []
+        obj = lambda th, e=e: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, e)
+        pre = lambda th, e=e: orc.hessian_diag(th, gm.labels, gm.H, gm.W, d, e)
+        orc.lbfgs_fit(obj, start, max_iter=8, precondition=pre, diag_every=3,
+                      callback=lambda it, x, phi, acc: xs.append(x.copy()))
+        traj[e] = xs
+    assert len(traj[eps]) == len(traj[1.0]) == 8
+    for a, b in zip(traj[eps], traj[1.0]):
+        assert np.max(np.abs(a - eps * b)) <= 1e-9 * np.max(np.abs(a))
+    assert K == 6
+
+
+def test_annealed_fit_without_levels_is_the_plain_fit(orc):
+    gm = synth.config_c1()
+    d, eps = 1, 1e-2
+    obj_e = lambda th, e: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, e)
+    acc = lambda th: orc.assign(th, gm.H, gm.W, d, gm.labels)[1] / gm.labels.size
+    z = np.zeros((gm.N, 3))
+    r0 = orc.lbfgs_fit(lambda th: obj_e(th, eps), z, accuracy=acc, max_iter=40)
+    r1 = orc.annealed_fit(obj_e, z, eps, stages=0, factor=4.0, stage_iters=10, accuracy=acc,
+                          max_iter=40)
+    assert r0["iters"] == r1["iters"] and r0["evals"] == r1["evals"]
+    assert np.array_equal(r0["theta"], r1["theta"]) and r0["phi"] == r1["phi"]
+
+
+def test_annealed_fit_levels_and_err_aligned_stop(orc):
+    """eps_k = eps * factor**(S - k); each level starts from the last one's theta,
+    where the accuracy is unchanged (F_theta does not depend on eps); the fit ends
+    at the first iterate, at any level, whose accuracy reaches the target; phi is
+    reported at the target eps."""
+    gm = synth.polynomial_diagram(48, 48, 10, 2, np.random.default_rng(33))
+    d, eps = 2, 1e-3
+    obj_e = lambda th, e: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, e)
+    acc = lambda th: orc.assign(th, gm.H, gm.W, d, gm.labels)[1] / gm.labels.size
+    seen = []
+    r = orc.annealed_fit(obj_e, np.zeros((gm.N, 6)), eps, stages=2, factor=8.0, stage_iters=15,
+                         accuracy=acc, target_acc=0.99, max_iter=2000,
+                         callback=lambda it, x, phi, a: seen.append((x.copy(), a)))
+    lv = r["levels"]
+    assert [v["eps"] for v in lv] == [eps * 64.0, eps * 8.0, eps][:len(lv)]
+    assert r["status"] == "target" and r["acc"] >= 0.99
+    assert all(v["status"] != "target" for v in lv[:-1]) and lv[-1]["status"] == "target"
+    assert all(v["iters"] <= 15 for v in lv[:-1])
+    assert r["iters"] == sum(v["iters"] for v in lv)
+    # the first iterate to reach the target is the last one
+    accs = [a for _, a in seen]
+    assert accs[-1] >= 0.99 and all(a < 0.99 for a in accs[:-1])
+    # phi at the target eps
+    assert r["phi"] == orc.objective_grad(r["theta"], gm.labels, gm.H, gm.W, d, eps,
+                                          grad=False)[0]
