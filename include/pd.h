@@ -122,6 +122,27 @@ pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs /*host*/, int32
                             double *const *grad_out /*host*/, pd_precision prec,
                             void *stream);
 
+/* Allocation-free variant of pd_objective_grad, for callers that cannot
+ * allocate device memory during the call (code under stream capture into a
+ * graph, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, operation, layouts and results as pd_objective_grad (the same
+ * kernels run), but every scratch buffer of the evaluation lives in one fixed
+ * device array of PD_NOALLOC_SCRATCH_BYTES bytes per device, set up by
+ * pd_create, and nothing is allocated: no hipMalloc, hipFree or pinned host
+ * memory, and the plan records are written by a kernel.
+ * Limits: at most PD_NOALLOC_MAX_MAPS maps per call (else PD_ERR_INVALID_ARG);
+ * an evaluation whose scratch exceeds the array returns PD_ERR_UNSUPPORTED
+ * before any launch (roughly: FP32 up to a 1024 x 1024 map with 1000 grains at
+ * degree 4; FP64 about half of that).  Every call on one device shares that
+ * device's array and leaves its contents there: calls that overlap on one device
+ * (other streams, other contexts or host threads) race.  Stream-ordered. */
+#define PD_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define PD_NOALLOC_MAX_MAPS 4
+pd_status pd_objective_grad_noalloc(pd_ctx *ctx, const pd_problem *probs /*host*/,
+                                    int32_t n_probs, const double *const *theta /*host*/,
+                                    double *phi_out, double *const *grad_out /*host*/,
+                                    pd_precision prec, void *stream);
+
 /* Flags of pd_objective_grad_rows. */
 /* The form pd_fit evaluates: the indicator moments m_i = sum_{x in G_i} psi(x) of
  * eq. grad are computed once per call (FP64, fixed order) and subtracted from the

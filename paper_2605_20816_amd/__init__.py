@@ -30,6 +30,9 @@ MAX_DEGREE = 8
 DESC_DIM = 32
 FRAME_DIM = 8
 MLP_WIDTH = 256
+# pd_objective_grad_noalloc: fixed scratch per device and maps per call
+NOALLOC_SCRATCH_BYTES = 64 << 20
+NOALLOC_MAX_MAPS = 4
 
 
 class PdError(RuntimeError):
@@ -80,6 +83,10 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                          ctypes.c_void_p]),
+    "pd_objective_grad_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem),
+                                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.c_int, ctypes.c_void_p]),
     "pd_objective_grad_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem),
                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
@@ -287,6 +294,20 @@ class Context:
                                             ctypes.c_void_p(phi.data_ptr()), gp, PREC[prec],
                                             _stream(stream)))
         return phi, grads
+
+    def objective_grad_noalloc(self, probs, thetas, phi_out, grad_out, prec="fp64",
+                               stream=None):
+        """pd_objective_grad_noalloc: the caller passes every output (phi_out (n,)
+        float64, grad_out a list of N x K float64 tensors or None); the library
+        allocates nothing."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        gp = _ptrs(grad_out) if grad_out is not None else None
+        self._check(lib().pd_objective_grad_noalloc(
+            self._h, arr, n, _ptrs(thetas), ctypes.c_void_p(phi_out.data_ptr()), gp, PREC[prec],
+            _stream(stream)))
+        return phi_out, grad_out
 
     def objective_grad_rows(self, probs, thetas, rows, prec="fp64", onehot_precomputed=False,
                             grad=True, stream=None):

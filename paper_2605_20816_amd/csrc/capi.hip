@@ -344,6 +344,63 @@ static pd_status precision_code(pd_ctx *ctx, pd_precision prec, int &code) {
   return PD_OK;
 }
 
+pd_status pd_plan_place(pd_ctx *ctx, EvalPlan &P, const Arena &L, const PlanMemory &mem,
+                        const double *const *theta, double *phi_out, double *const *grad_out,
+                        hipStream_t s) {
+  char *base = mem.base;
+  if (base == nullptr) {
+    pd_status st = pd_reserve(ctx, L.off);
+    if (st != PD_OK) return st;
+    base = ctx->ws;
+  } else if (L.off > mem.cap) {
+    return pd_fail(ctx, PD_ERR_UNSUPPORTED,
+                   "this evaluation needs " + std::to_string(L.off) +
+                       " bytes of scratch; the fixed buffer holds " + std::to_string(mem.cap));
+  }
+  pd_plan_bind(P, base, theta, phi_out, grad_out, nullptr, nullptr);
+  const hipError_t e = mem.base ? pd_plan_upload_by_kernel(P, s) : pd_plan_upload(ctx, P, s);
+  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  return PD_OK;
+}
+
+pd_status pd_objective_grad_impl(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                                 const int32_t *rows, const double *const *theta,
+                                 double *phi_out, double *const *grad_out, pd_precision prec,
+                                 int32_t flags, void *stream, const PlanMemory &mem) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta is NULL");
+  if (!phi_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "phi_out is NULL");
+  if (flags & ~PD_EVAL_ONEHOT_PRECOMPUTED) return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown flags");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta[" + std::to_string(p) + "] is NULL");
+    if (rows && !(0 <= rows[2 * p] && rows[2 * p] <= rows[2 * p + 1] && rows[2 * p + 1] <= probs[p].height))
+      return pd_fail(ctx, PD_ERR_INVALID_ARG,
+                     "map " + std::to_string(p) + ": rows must satisfy 0 <= begin <= end <= height");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (code == 2)
+    return pd_bf16_objective_grad(ctx, probs, n_probs, rows, theta, phi_out, grad_out, s, mem);
+  EvalPlan P;
+  Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
+  P.onehot_pre = (flags & PD_EVAL_ONEHOT_PRECOMPUTED) != 0;
+  pd_plan_layout(P, L, probs, n_probs, code, rows);
+  pd_status st = pd_plan_place(ctx, P, L, mem, theta, phi_out, grad_out, s);
+  if (st != PD_OK) return st;
+  pd_plan_tables(P, s);
+  if (P.any_grad) pd_plan_onehot(P, s);
+  pd_plan_eval(P, P.any_grad, s, true);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
 extern "C" {
 
 pd_status pd_create(int device, pd_ctx **out) {
@@ -358,6 +415,11 @@ pd_status pd_create(int device, pd_ctx **out) {
   if (hipSetDevice(device) != hipSuccess) return PD_ERR_HIP;
   pd_ctx *c = new pd_ctx();
   c->device = device;
+  const pd_status st = pd_noalloc_setup(c);
+  if (st != PD_OK) {
+    delete c;
+    return st;
+  }
   *out = c;
   return PD_OK;
 }
@@ -438,51 +500,11 @@ pd_status pd_validate(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs, voi
   return PD_OK;
 }
 
-// Shared by pd_objective_grad and pd_objective_grad_rows (rows: null or checked).
-static pd_status objective_grad_impl(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
-                                     const int32_t *rows, const double *const *theta,
-                                     double *phi_out, double *const *grad_out, pd_precision prec,
-                                     int32_t flags, void *stream) {
-  if (!ctx) return PD_ERR_INVALID_ARG;
-  ctx->err.clear();
-  int code = 0;
-  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
-  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
-  if (!theta) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta is NULL");
-  if (!phi_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "phi_out is NULL");
-  if (flags & ~PD_EVAL_ONEHOT_PRECOMPUTED) return pd_fail(ctx, PD_ERR_INVALID_ARG, "unknown flags");
-  for (int p = 0; p < n_probs; ++p) {
-    pd_status st = pd_check_problem(ctx, probs[p], p);
-    if (st != PD_OK) return st;
-    if (!theta[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta[" + std::to_string(p) + "] is NULL");
-    if (rows && !(0 <= rows[2 * p] && rows[2 * p] <= rows[2 * p + 1] && rows[2 * p + 1] <= probs[p].height))
-      return pd_fail(ctx, PD_ERR_INVALID_ARG,
-                     "map " + std::to_string(p) + ": rows must satisfy 0 <= begin <= end <= height");
-  }
-  PD_HIP(ctx, hipSetDevice(ctx->device));
-  hipStream_t s = (hipStream_t)stream;
-  if (code == 2) return pd_bf16_objective_grad(ctx, probs, n_probs, rows, theta, phi_out, grad_out, s);
-  EvalPlan P;
-  Arena L;
-  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
-  P.onehot_pre = (flags & PD_EVAL_ONEHOT_PRECOMPUTED) != 0;
-  pd_plan_layout(P, L, probs, n_probs, code, rows);
-  pd_status st = pd_reserve(ctx, L.off);
-  if (st != PD_OK) return st;
-  pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
-  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
-  pd_plan_tables(P, s);
-  if (P.any_grad) pd_plan_onehot(P, s);
-  pd_plan_eval(P, P.any_grad, s, true);
-  PD_HIP(ctx, hipGetLastError());
-  return PD_OK;
-}
-
 pd_status pd_objective_grad(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
                             const double *const *theta, double *phi_out,
                             double *const *grad_out, pd_precision prec, void *stream) {
-  return objective_grad_impl(ctx, probs, n_probs, nullptr, theta, phi_out, grad_out, prec, 0,
-                             stream);
+  return pd_objective_grad_impl(ctx, probs, n_probs, nullptr, theta, phi_out, grad_out, prec, 0,
+                                stream, PlanMemory{});
 }
 
 pd_status pd_objective_grad_rows(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
@@ -490,8 +512,8 @@ pd_status pd_objective_grad_rows(pd_ctx *ctx, const pd_problem *probs, int32_t n
                                  double *phi_out, double *const *grad_out, pd_precision prec,
                                  int32_t flags, void *stream) {
   if (ctx && !rows) return pd_fail(ctx, PD_ERR_INVALID_ARG, "rows is NULL");
-  return objective_grad_impl(ctx, probs, n_probs, rows, theta, phi_out, grad_out, prec, flags,
-                             stream);
+  return pd_objective_grad_impl(ctx, probs, n_probs, rows, theta, phi_out, grad_out, prec, flags,
+                                stream, PlanMemory{});
 }
 
 pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,

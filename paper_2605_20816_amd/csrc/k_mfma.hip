@@ -609,7 +609,8 @@ void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) 
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
                                  const int32_t *rows, const double *const *theta,
-                                 double *phi_out, double *const *grad_out, hipStream_t s) {
+                                 double *phi_out, double *const *grad_out, hipStream_t s,
+                                 const PlanMemory &mem) {
   for (int p = 0; p < n; ++p)
     if (probs[p].degree > 6)
       return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
@@ -617,14 +618,11 @@ pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n, 2);
   pd_plan_layout(P, L, probs, n, 2, rows);
-  pd_status st = pd_reserve(ctx, L.off);
+  pd_status st = pd_plan_place(ctx, P, L, mem, theta, phi_out, grad_out, s);
   if (st != PD_OK) return st;
-  pd_plan_bind(P, ctx->ws, theta, phi_out, grad_out, nullptr, nullptr);
-  hipError_t e = pd_plan_upload(ctx, P, s);
-  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, hipGetErrorString(e));
   pd_plan_tables(P, s);
   pd_bf16_plan_eval(ctx, P, s, true);
-  e = hipGetLastError();
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, hipGetErrorString(e));
   return PD_OK;
 }

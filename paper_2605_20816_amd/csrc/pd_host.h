@@ -65,6 +65,15 @@ struct EvalPlan {
   int32_t *d_off16P = nullptr, *d_off16A = nullptr, *d_off16B = nullptr, *d_off16R = nullptr;
 };
 
+// Device memory of an evaluation plan.  base == nullptr: the context's
+// workspace, grown on demand, with the plan records staged through pinned host
+// memory.  Otherwise `cap` bytes of fixed device memory, the plan records written
+// by a kernel from its arguments, so that nothing is allocated.
+struct PlanMemory {
+  char *base = nullptr;
+  size_t cap = 0;
+};
+
 pd_status pd_fail(pd_ctx *c, pd_status s, const std::string &msg);
 pd_status pd_check_problem(pd_ctx *ctx, const pd_problem &p, int idx);
 pd_status pd_reserve(pd_ctx *ctx, size_t bytes);
@@ -75,6 +84,24 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
 void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
                   double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
+// Memory for a laid-out plan (reserved in the workspace, or checked against the
+// fixed buffer: PD_ERR_UNSUPPORTED if it does not fit), then bind and upload.
+pd_status pd_plan_place(pd_ctx *ctx, EvalPlan &P, const Arena &L, const PlanMemory &mem,
+                        const double *const *theta, double *phi_out, double *const *grad_out,
+                        hipStream_t s);
+// noalloc.hip: the plan records (maps and work-list offsets, at most
+// PD_NOALLOC_MAX_MAPS maps) written into the plan's memory by a one-block kernel
+// whose arguments carry them.
+hipError_t pd_plan_upload_by_kernel(const EvalPlan &P, hipStream_t s);
+// Set-up of the fixed scratch buffer of the allocation-free entry point on the
+// current device (its device address, kept per device).  Called by pd_create.
+pd_status pd_noalloc_setup(pd_ctx *ctx);
+// Shared body of pd_objective_grad, pd_objective_grad_rows and
+// pd_objective_grad_noalloc (rows: null or a checked row band per map).
+pd_status pd_objective_grad_impl(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                                 const int32_t *rows, const double *const *theta,
+                                 double *phi_out, double *const *grad_out, pd_precision prec,
+                                 int32_t flags, void *stream, const PlanMemory &mem);
 void pd_plan_tables(const EvalPlan &P, hipStream_t s);
 // Indicator moments of every map when P.onehot_pre (after pd_plan_tables).
 void pd_plan_onehot(const EvalPlan &P, hipStream_t s);
@@ -87,7 +114,8 @@ void pd_plan_assign(const EvalPlan &P, hipStream_t s);
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,
                                  const int32_t *rows, const double *const *theta,
-                                 double *phi_out, double *const *grad_out, hipStream_t s);
+                                 double *phi_out, double *const *grad_out, hipStream_t s,
+                                 const PlanMemory &mem);
 void pd_fit_release(pd_ctx *ctx);
 // BF16 path: stage 0 prep (thc pieces), 1 log-sum-exp, 2 gradient, 3 reductions.
 void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s);
