@@ -351,6 +351,24 @@ pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);
 
+/* Physical parameters of a fitted degree-1 (power) or degree-2 (anisotropic
+ * power) diagram, Section 5.6.3 with eq. pd-lr-to-phys / apd-lr-to-phys of
+ * Section 2.3.1.  The Legendre coefficients (P_2(t) = (3t^2 - 1)/2) are rewritten
+ * as h_i(x) = x.A_i x + c_i.x + c_i0, and y_i = -(1/2) A_i^{-1} c_i,
+ * w_i = y_i.A_i y_i - c_i0.  The gauge freedom of Lemma 4.2 (adding
+ * lambda (x1^2 + x2^2) to every grain changes no cell) is used to make every
+ * anisotropy positive definite: lambda = max(0, margin - min_i lambda_min(A_i))
+ * and A_i + lambda I is returned.  Degree 1: A_i = I (the common |x|^2 is the
+ * gauge term the coefficients already drop), lambda = 0.
+ *   theta:      DEVICE n_grains x K FP64 (K = 3 or 6; any gauge);
+ *   params_out: DEVICE n_grains x PD_PHYS_DIM FP64, per grain
+ *               y1, y2, w, A11, A12, A22;
+ *   lambda_out: DEVICE double[1], the shift applied.
+ * margin > 0 finite.  Degree outside {1, 2}: PD_ERR_UNSUPPORTED.  Stream-ordered. */
+#define PD_PHYS_DIM 6
+pd_status pd_recover_params(pd_ctx *ctx, int32_t n_grains, int32_t degree, const double *theta,
+                            double margin, double *params_out, double *lambda_out, void *stream);
+
 /* Per-stage timing of one evaluation (the library's tracing hook; not part of
  * the paper).  Runs the evaluation of pd_objective_grad stage by stage, each
  * stage `reps` times back to back between HIP events on `stream`, and writes the

@@ -92,6 +92,9 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                               ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                               ctypes.c_int32, ctypes.c_void_p]),
+    "pd_recover_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "pd_assign": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                  ctypes.c_void_p, ctypes.c_void_p]),
@@ -338,6 +341,19 @@ class Context:
         self._check(lib().pd_hessian_diag(self._h, arr, n, _ptrs(thetas), _ptrs(out), PREC[prec],
                                           _stream(stream)))
         return out
+
+    def recover_params(self, theta, degree, margin=1e-3, stream=None):
+        """Physical parameters of a degree-1/2 fit: (params N x 6 float64 with
+        columns y1, y2, w, A11, A12, A22; the shift lambda as a 1-element tensor)."""
+        if not (theta.dtype == torch.float64 and theta.is_cuda and theta.is_contiguous()):
+            raise ValueError("theta must be a contiguous float64 CUDA tensor")
+        N = theta.shape[0]
+        out = torch.empty((N, 6), dtype=torch.float64, device=theta.device)
+        lam = torch.empty(1, dtype=torch.float64, device=theta.device)
+        self._check(lib().pd_recover_params(self._h, N, degree, ctypes.c_void_p(theta.data_ptr()),
+                                            float(margin), ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(lam.data_ptr()), _stream(stream)))
+        return out, lam
 
     def assign(self, probs, thetas, labels_out=True, stream=None):
         """F_theta per map and #correct.  Returns ([labels int32 (n,)] or None, counts int64)."""

@@ -16,21 +16,25 @@
 // by all lanes at one address (broadcast); grains are scanned in ascending order.
 #define AS_CHUNK 64
 
-template <int D>
-__device__ inline void assign_block(const MapDev &M, int base, double *sth) {
-  constexpr int DP = D + 1;
+// Canonical arg-min over every grain for the pixel (r, c) of each thread, with
+// theta staged through sth by the whole block (every thread of the block must
+// call it; the pixel may differ per thread and need not be valid).  Returns the
+// smallest index among the minimal scores; *bad is set if a score is NaN.
+template <int D, bool UNI_ROW>
+__device__ inline int canonical_argmin(const MapDev &M, int r, int c, double *sth, bool *bad_out) {
   constexpr int K = (D + 1) * (D + 2) / 2;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
-  const int lane = threadIdx.x % PD_WAVE;
-  const int local = base + wave;
-  const bool wave_valid = local < M.rows * M.segs;
-  const int lr = wave_valid ? local / M.segs : 0;
-  const int r = M.row0 + lr;
-  const int c = wave_valid ? (local - lr * M.segs) * PD_WAVE + lane : M.W;
-  const bool valid = c < M.W;
-  const int cc = valid ? c : M.W - 1;
-  const auto px = pd_glb(M.tx64 + (size_t)cc * DP);
-  const auto py = pd_uni(M.ty64 + (size_t)r * DP);
+  constexpr int DP = D + 1;
+  const auto px = pd_glb(M.tx64 + (size_t)c * DP);
+  double py[DP];
+  if (UNI_ROW) {
+    const auto pu = pd_uni(M.ty64 + (size_t)r * DP);
+#pragma unroll
+    for (int b = 0; b < DP; ++b) py[b] = pu[b];
+  } else {
+    const auto pv = pd_glb(M.ty64 + (size_t)r * DP);
+#pragma unroll
+    for (int b = 0; b < DP; ++b) py[b] = pv[b];
+  }
   double psi[K];
 #pragma unroll
   for (int deg = 0; deg <= D; ++deg)
@@ -76,6 +80,23 @@ __device__ inline void assign_block(const MapDev &M, int base, double *sth) {
       }
     }
   }
+  *bad_out = bad;
+  return best;
+}
+
+template <int D>
+__device__ inline void assign_block(const MapDev &M, int base, double *sth) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int local = base + wave;
+  const bool wave_valid = local < M.rows * M.segs;
+  const int lr = wave_valid ? local / M.segs : 0;
+  const int r = M.row0 + lr;
+  const int c = wave_valid ? (local - lr * M.segs) * PD_WAVE + lane : M.W;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  bool bad = false;
+  const int best = canonical_argmin<D, true>(M, r, cc, sth, &bad);
   long long correct = 0;
   if (valid) {
     const int lab = bad ? -1 : best;

@@ -163,12 +163,17 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.txT = L.take(tsz * M.W * M.DP);
     R.tyT = L.take(tsz * M.H * M.DP);
     R.thc = L.take(sizeof(double) * M.N * M.K);
-    R.C = L.take(mf ? 0 : tsz * (size_t)M.rows * M.Npad * M.DP);
-    R.lse = L.take(mf ? 0 : tsz * n_px);
+    // FP64 row coefficients and log-sum-exp in both VALU modes
+    R.C = L.take(mf ? 0 : sizeof(double) * (size_t)M.rows * M.Npad * M.DP);
+    R.lse = L.take(mf ? 0 : sizeof(double) * n_px);
+    R.rpix = L.take(mf ? 0 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
     R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
-    R.part_c = L.take(sizeof(int64_t) * (M.a_items / PD_WAVES_PER_BLOCK));
+    R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    const bool cert = P.cert && !mf;
+    R.cert = L.take(cert ? 32 : 0);  // bound (8), uncertain count (4), canonical count (8)
+    R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
@@ -208,9 +213,21 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
     M.thc = (double *)(base + R.thc);
     M.C = base + R.C;
     M.lse = base + R.lse;
+    M.rpix = base + R.rpix;
     M.part_l = (double *)(base + R.part_l);
     M.part_g = (double *)(base + R.part_g);
     M.part_c = (int64_t *)(base + R.part_c);
+    if (P.cert && P.prec != 2) {
+      M.cert = (double *)(base + R.cert);
+      M.unc_count = (int32_t *)(base + R.cert + 8);
+      M.fb_count = (int64_t *)(base + R.cert + 16);
+      M.unc_list = (int32_t *)(base + R.unc_list);
+    } else {
+      M.cert = nullptr;
+      M.unc_count = nullptr;
+      M.fb_count = nullptr;
+      M.unc_list = nullptr;
+    }
     M.onehot = P.onehot_pre && P.prec != 2 ? (double *)(base + R.onehot) : nullptr;
     M.part_d = P.with_diag ? (double *)(base + R.part_d) : nullptr;
     M.diag = nullptr;
@@ -285,10 +302,14 @@ void pd_plan_eval(const EvalPlan &P, bool with_grad, hipStream_t s, bool center,
                   const MapDev *assign_maps) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-  if (assign_maps)
+  if (P.cert && P.prec != 2) {
+    pd_launch_lse_cert(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+    pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
+  } else if (assign_maps) {
     pd_launch_lse_assign(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], assign_maps, s);
-  else
+  } else {
     pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  }
   if (with_grad)
     pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], P.with_diag, !P.onehot_pre, s);
   pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], with_grad, with_grad && P.with_diag, s);

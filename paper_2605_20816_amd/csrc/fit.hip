@@ -59,6 +59,17 @@ struct FitDev {
   const double *phi_t;
   const int64_t *part_c;  // per-block correct counts of the last assignment
   int32_t c_items;        // their number
+  // certified accuracy (FP64/FP32 evaluations): the objective launch at xt also
+  // counts the pixels that F_xt labels correctly (per-wave counts in part_c plus
+  // the canonical pass's fb_count), so the accuracy of an accepted iterate is
+  // known when it is accepted; the decision kernel clears the slots for the next
+  // evaluation.  Otherwise (BF16) the accepted iterate is assigned in the next
+  // step (assign_pending).
+  int32_t cert;
+  int64_t cnt_t;          // correct pixels of the evaluation at xt
+  double *cert_slot;
+  int32_t *unc_count;
+  int64_t *fb_count;
   double *thc;       // evaluation input: cscale * (xt - grain mean of xt)
   double cscale;     // -log2(e) / eps
   int32_t *active, *assign_pending;
@@ -952,6 +963,20 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     F.evals_last = F.evals;
   }
   __syncthreads();
+  if (F.cert) {
+    // xt, now the iterate, was assigned in its own evaluation
+    if (threadIdx.x == 0) {
+      F.acc = (double)F.cnt_t / (double)F.n_pix;
+      if ((F.iters % F.check_every) == 0 && F.acc >= F.target_acc) {
+        F.clk_target = wall_clock64();
+        fit_stop(F, ST_TARGET);
+      } else if (F.iters >= F.max_iter) {
+        fit_stop(F, ST_BUDGET);
+      }
+    }
+    __syncthreads();
+    if (F.status != ST_RUNNING) return;
+  }
   if (F.iters >= F.max_iter) {
     if (threadIdx.x == 0) {
       F.phase = PH_STOP;
@@ -960,7 +985,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     __syncthreads();
     return;
   }
-  if (threadIdx.x == 0 && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
+  if (threadIdx.x == 0 && !F.cert && (F.iters % F.check_every) == 0) *F.assign_pending = 1;
   const bool refresh = F.precond > 0 && (F.iters % F.precond) == 0;
   if (refresh) refresh_dinv(F, red);
   if (F.split) {
@@ -1126,7 +1151,25 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_decide(FitDev *Fs, const in
   // the last accepted iterate (assigned in this step's objective launch), its
   // per-block counts, summed in a fixed order
   const double ft = -*sF.phi_t;
-  if (pending != 0) {
+  if (sF.cert) {
+    // the certified correct count of this evaluation's point xt, then clear the
+    // slots that the next evaluation accumulates into
+    long long c = 0;
+    for (int t = threadIdx.x; t < sF.c_items; t += blockDim.x) c += sF.part_c[t];
+    c = pd_wave_sum_i64(c);
+    long long *cw = (long long *)red;
+    if ((threadIdx.x & 63) == 0) cw[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += cw[w];
+      sF.cnt_t = tot + *sF.fb_count;
+      *sF.cert_slot = 0.0;
+      *sF.unc_count = 0;
+      *sF.fb_count = 0;
+    }
+    __syncthreads();
+  } else if (pending != 0) {
     long long c = 0;
     for (int t = threadIdx.x; t < sF.c_items; t += blockDim.x) c += sF.part_c[t];
     c = pd_wave_sum_i64(c);
@@ -1175,6 +1218,15 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
       F.evals_last = F.evals;
       if (!isfinite(ft)) {
         fit_stop(F, ST_NONFINITE);
+      } else if (F.cert) {
+        // the start's accuracy came with its evaluation
+        F.acc = (double)F.cnt_t / (double)F.n_pix;
+        if (F.acc >= F.target_acc) {
+          F.clk_target = wall_clock64();
+          fit_stop(F, ST_TARGET);
+        } else if (F.max_iter == 0) {
+          fit_stop(F, ST_BUDGET);
+        }
       } else {
         *F.assign_pending = 1;
         if (F.max_iter == 0) F.phase = PH_STOP;
@@ -1394,6 +1446,11 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
     *F.active = 1;
     *F.assign_pending = 0;
     if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
+    if (F.cert) {
+      *F.cert_slot = 0.0;
+      *F.unc_count = 0;
+      *F.fb_count = 0;
+    }
   }
   // the first evaluation is at the start itself
   form_trial(F, 0.0, red, false);
@@ -1428,7 +1485,8 @@ static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *
     // whose refresh flag is set (its gate), at the same trial point
     if (Pdiag) pd_plan_eval(*Pdiag, true, s, false);
   } else {
-    pd_plan_eval(P, true, s, false, amaps);
+    // certified assignment of xt inside the objective launch (P.cert)
+    pd_plan_eval(P, true, s, false);
   }
 }
 
@@ -1491,6 +1549,7 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
   P.with_diag = opts->precondition > 0;
   P.onehot_pre = true;  // indicator moments once per fit
+  P.cert = eval_prec != 2;  // the accuracy of every evaluated point, certified
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);
@@ -1575,7 +1634,8 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.diag_floor = 1e-6;
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
-    f.c_items = M.a_items / PD_WAVES_PER_BLOCK;
+    f.cert = P.cert ? 1 : 0;
+    f.c_items = P.cert ? M.a_items : M.a_items / PD_WAVES_PER_BLOCK;
     f.nchunk = coff[p + 1] - coff[p];
     f.split = f.nchunk > 0 ? 1 : 0;
     if (f.split) {
@@ -1591,6 +1651,9 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   for (int p = 0; p < n; ++p) {
     F[p].thc = P.maps[p].thc;
     F[p].part_c = P.maps[p].part_c;
+    F[p].cert_slot = P.maps[p].cert;
+    F[p].unc_count = P.maps[p].unc_count;
+    F[p].fb_count = P.maps[p].fb_count;
   }
   for (int p = 0; p < n; ++p) {
     P.maps[p].gate = flags + p;

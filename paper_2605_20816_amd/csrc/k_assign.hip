@@ -47,6 +47,46 @@ __global__ __launch_bounds__(PD_BLOCK) void k_validate(const MapDev *__restrict_
   if (b) bad[blockIdx.y] = 1;
 }
 
+// The canonical arg-min of the pixels that the certified objective launch could
+// not decide (unc_list), counted into fb_count.  grid: (blocks, n_maps); the
+// blocks stride over the list 256 pixels at a time.
+template <int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_assign_list(const MapDev *__restrict__ maps) {
+  constexpr int KM = (DMAX + 1) * (DMAX + 2) / 2;
+  __shared__ double sth[AS_CHUNK * KM];
+  __shared__ int bsum;
+  const MapDev &M = maps[blockIdx.y];
+  if (M.cert == nullptr || PD_GATED(M)) return;
+  const int cap = M.rows * M.W;
+  const int count = min(*pd_uni(M.unc_count), cap);
+  for (int base = blockIdx.x * PD_BLOCK; base < count; base += gridDim.x * PD_BLOCK) {
+    const int q = base + (int)threadIdx.x;
+    const bool valid = q < count;
+    const int pix = valid ? pd_glb(M.unc_list)[q] : M.row0 * M.W;
+    const int r = pix / M.W, c = pix - r * M.W;
+    bool bad = false;
+    int best = 0;
+    PD_DISPATCH_UPTO(DMAX, M.d, (best = canonical_argmin<D, false>(M, r, c, sth, &bad)));
+    const int ok = (valid && !bad && best == pd_glb(M.labels)[pix]) ? 1 : 0;
+    if (threadIdx.x == 0) bsum = 0;
+    __syncthreads();
+    const long long ws = pd_wave_sum_i64(ok);
+    if ((threadIdx.x % PD_WAVE) == 0 && ws) atomicAdd(&bsum, (int)ws);
+    __syncthreads();
+    if (threadIdx.x == 0 && bsum) atomicAdd((unsigned long long *)M.fb_count, (unsigned long long)bsum);
+  }
+}
+
+void pd_launch_assign_list(int dmax, const MapDev *maps, int n_maps, hipStream_t s) {
+  const dim3 grid(256, n_maps);
+  switch (dmax) {
+    case 2: k_assign_list<2><<<grid, PD_BLOCK, 0, s>>>(maps); break;
+    case 4: k_assign_list<4><<<grid, PD_BLOCK, 0, s>>>(maps); break;
+    case 6: k_assign_list<6><<<grid, PD_BLOCK, 0, s>>>(maps); break;
+    default: k_assign_list<8><<<grid, PD_BLOCK, 0, s>>>(maps); break;
+  }
+}
+
 void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       bool count, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;

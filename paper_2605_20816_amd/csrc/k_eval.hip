@@ -8,8 +8,15 @@
 //   C_{r,i,a} = -(log2 e / eps) sum_b thc_{i,(a,b)} P_b(x2_r),
 // costing d FMAs per (pixel, grain) instead of K.  Logits are kept in base 2
 // (exp2 is the hardware instruction), thc is theta minus its grain mean (a
-// common shift, which changes neither p nor Phi by Lemma 4.2, and keeps FP32
-// logits small).
+// common shift, which changes neither p nor Phi by Lemma 4.2).
+//
+// Precision: the row coefficients, logits, running maxima and log-sum-exp are
+// FP64 in both modes (an FP64 FMA issues at the rate of a non-packed FP32 one on
+// this GPU).  The evaluation type T (FP64 or FP32) is that of the exponentials
+// and of the per-row partial sums.  At eps = 1e-3 a fitted theta gives logits of
+// 1e3..1e4 whose FP32 rounding (1e-4..1e-3 absolute) would be the dominant error
+// of p near a fitted iterate, where the gradient is a small difference of large
+// sums; an FP32 exponent argument s - lse is rounded only after the subtraction.
 //
 // Kernel A (k_lse): one wave per 64-pixel row segment, lanes = pixels, loop over
 //   grains in chunks of 8 with an online max / sum of exp2 (one exp2 per pair
@@ -126,15 +133,15 @@ __global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ 
 // Row coefficients C[r][i][a] = sum_b thc[i][(a,b)] P_b(x2_r).  Padded grains
 // i in [N, Npad) get C = (-inf, 0, ..., 0): exp2 of their logit is 0.
 // grid: blocks over the flattened (map, r, i), offsets in off (n_maps + 1).
-template <typename T, int D>
+template <int D>
 __device__ inline void prep_one(const MapDev &M, int r, int i) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  T *out = (T *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP;
+  double *out = (double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP;
   if (i >= M.N) {
-    out[0] = (T)-INFINITY;
+    out[0] = -INFINITY;
 #pragma unroll
-    for (int a = 1; a < DP; ++a) out[a] = (T)0;
+    for (int a = 1; a < DP; ++a) out[a] = 0.0;
     return;
   }
   const double *th = M.thc + (size_t)i * K;
@@ -144,29 +151,82 @@ __device__ inline void prep_one(const MapDev &M, int r, int i) {
     double v = th[pd_alpha_index(a, 0)];
 #pragma unroll
     for (int b = 1; a + b <= D; ++b) v = __builtin_fma(th[pd_alpha_index(a, b)], ty[b], v);
-    out[a] = (T)v;
+    out[a] = v;
   }
 }
 
-template <typename T>
+// Rounding bound of grain i's logit against the canonical FP64 score (see
+// lse_item's certified arg-max): with u = 2^-53 and c = log2(e)/eps, the logit
+// s_i = thc_i . psi formed by the two FMA chains of the row factorisation is
+// within (2d + 7) u ||thc_i||_1 of c (theta_i - mean) . psi evaluated exactly on
+// the FP64 tables (thc itself carries 2 rounding errors per entry), and the
+// canonical score within (K + 2) u ||theta_i||_1 of theta_i . psi; |psi| <= 1.
+// Returned with a factor 2 of margin.
+template <int D>
+__device__ inline double cert_bound(const MapDev &M, int i) {
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  const double *th = M.thc + (size_t)i * K;
+  const double *x = M.theta + (size_t)i * K;
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    a += fabs(th[k]);
+    b += fabs(x[k]);
+  }
+  constexpr double u = 0x1p-53;
+  return 2.0 * ((2 * D + 8) * u * a + (PD_LOG2E / M.eps) * (K + 4) * u * b);
+}
+
 __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ maps,
                                                    const int32_t *__restrict__ off, int n_maps) {
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
+  if (M.cert != nullptr && (long long)(blockIdx.x - off[m]) * PD_BLOCK < M.Npad) {
+    // the blocks of the first evaluated row also take the largest logit
+    // rounding bound over the grains (block maximum, one atomic per block; the
+    // fit clears the slot after each evaluation)
+    __shared__ double bred[PD_BLOCK];
+    double bnd = 0.0;
+    if (flat < M.Npad && flat < M.N) PD_DISPATCH_D(M.d, (bnd = cert_bound<D>(M, (int)flat)));
+    bred[threadIdx.x] = bnd;
+    __syncthreads();
+    for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const double o = bred[threadIdx.x + w];
+        // NaN wins (it makes every pixel uncertain, and the canonical pass flags it)
+        if (!(o <= bred[threadIdx.x])) bred[threadIdx.x] = o;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      atomicMax((unsigned long long *)M.cert, (unsigned long long)__double_as_longlong(bred[0]));
+  }
   if (flat >= (long long)M.rows * M.Npad) return;
   const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
-  PD_DISPATCH_D(M.d, (prep_one<T, D>(M, M.row0 + lr, i)));
+  PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i)));
 }
 
 // ---------------------------------------------------------------------------
 // Kernel A: per-pixel base-2 log-sum-exp over grains and partial sums of log2 p_G.
-template <typename T, int D>
+// With CERT, also the hard assignment of every pixel at this theta, certified
+// against the canonical FP64 arg-min (Section 2.1): the loop keeps the largest
+// chunk maximum (and its chunk) and the second largest; at the end the 8 logits
+// of the best chunk are formed again (the same operations, so the same values),
+// giving the best grain b and the runner-up value.  If the gap to the runner-up
+// exceeds twice the logit rounding bound of cert_bound (taken over all grains),
+// the canonical scores have the same strict minimum at b; otherwise the pixel is
+// listed for k_assign_list.  Per-wave counts of certified correct pixels go to
+// part_c[local].
+template <typename T, int D, bool CERT = false>
 __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   if (local >= M.rows * M.segs) {  // padding item (item counts are multiples of 4)
-    if (lane == 0) pd_glb(M.part_l)[local] = 0.0;
+    if (lane == 0) {
+      pd_glb(M.part_l)[local] = 0.0;
+      if (CERT) pd_glb(M.part_c)[local] = 0;
+    }
     return;
   }
   const int lr = local / M.segs;  // row within the evaluated rows
@@ -174,50 +234,106 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   const int c = (local - lr * M.segs) * PD_WAVE + lane;
   const bool valid = c < M.W;
   const int cc = valid ? c : M.W - 1;
-  const auto tx = pd_glb((const T *)M.txT + (size_t)cc * DP);
-  T px[DP];
+  const auto tx = pd_glb(M.tx64 + (size_t)cc * DP);
+  double px[DP];
 #pragma unroll
   for (int a = 0; a < DP; ++a) px[a] = tx[a];
-  const auto Crow = pd_uni((const T *)M.C + (size_t)lr * M.Npad * DP);
-  const auto Cvec = pd_glb((const T *)M.C + (size_t)lr * M.Npad * DP);
+  const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
+  const auto Cvec = pd_glb((const double *)M.C + (size_t)lr * M.Npad * DP);
   const int N = M.N;
-  T mrun = (T)-INFINITY, S = (T)0;
+  const int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  // S sums exp2(s_i - mrun) over the grains other than the pixel's label g, so
+  // that r = 1 - p_g (the labelled grain's p - 1 in eq. grad, up to sign) comes
+  // out as a sum of small terms instead of a difference of two numbers near 1
+  double mrun = -INFINITY;
+  T S = (T)0;
+  double bv = -INFINITY, sv = -INFINITY;  // CERT: best / second chunk maximum
+  int bi = 0;                             // CERT: first grain of the best chunk
   // grains N .. Npad-1 (read when N is not a multiple of 8) have row
   // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
   for (int i0 = 0; i0 < N; i0 += 8) {
-    T s[8];
+    double s[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const auto cp = Crow + (size_t)(i0 + j) * DP;
-      T v = cp[0];
+      double v = cp[0];
 #pragma unroll
       for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
       s[j] = v;
     }
-    T cm = s[0];
+    double cm = s[0];
 #pragma unroll
     for (int j = 1; j < 8; ++j) cm = pd_max(cm, s[j]);
-    const T mnew = pd_max(mrun, cm);
-    S *= pd_exp2<T>(mrun - mnew);
+    const double mnew = pd_max(mrun, cm);
+    if (CERT) {
+      const bool gt = cm > bv;
+      sv = gt ? bv : pd_max(sv, cm);
+      bi = gt ? i0 : bi;
+      bv = gt ? cm : bv;
+    }
+    S *= pd_exp2<T>((T)(mrun - mnew));
+    T e[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) S += pd_exp2<T>(s[j] - mnew);
+    for (int j = 0; j < 8; ++j) e[j] = pd_exp2<T>((T)(s[j] - mnew));
+    if (__ballot((unsigned)(g - i0) < 8u) != 0) {
+      // a label of this segment lies in the chunk: leave its term out
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = (i0 + j == g) ? (T)0 : e[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) S += e[j];
     mrun = mnew;
   }
-  const T lse = mrun + pd_log2<T>(S);
   double ell = 0.0;
-  if (valid) {
-    const size_t j = (size_t)r * M.W + c;
-    pd_glb((T *)M.lse)[(size_t)lr * M.W + c] = lse;
-    const int g = pd_glb(M.labels)[j];
-    if (g >= 0 && g < N) {
-      const auto cg = Cvec + (size_t)g * DP;
-      T v = cg[0];
+  double lse;
+  if (g >= 0 && g < N) {
+    // the label's logit, with the same operations as in the loop (bit-identical)
+    const auto cg = Cvec + (size_t)g * DP;
+    double v = cg[0];
 #pragma unroll
-      for (int a = 1; a < DP; ++a) v = pd_fma(cg[a], px[a], v);
-      ell = (double)v - (double)lse;
-    } else {
-      ell = NAN;
+    for (int a = 1; a < DP; ++a) v = pd_fma(cg[a], px[a], v);
+    const T tot = S + pd_exp2<T>((T)(v - mrun));
+    lse = mrun + (double)pd_log2<T>(tot);
+    ell = v - lse;
+    if (valid) pd_glb((T *)M.rpix)[(size_t)lr * M.W + c] = S / tot;
+  } else {
+    lse = mrun + (double)pd_log2<T>(S);
+    ell = NAN;
+    if (valid) pd_glb((T *)M.rpix)[(size_t)lr * M.W + c] = (T)0;
+  }
+  if (valid) pd_glb((double *)M.lse)[(size_t)lr * M.W + c] = lse;
+  else ell = 0.0;
+  if constexpr (CERT) {
+    const auto cb = Cvec + (size_t)bi * DP;
+    double v1 = -INFINITY, v2 = -INFINITY;
+    int j1 = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double v = cb[j * DP];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) v = pd_fma(cb[j * DP + a], px[a], v);
+      if (v > v1) {
+        v2 = v1;
+        v1 = v;
+        j1 = j;
+      } else {
+        v2 = pd_max(v2, v);
+      }
     }
+    const double bound = __longlong_as_double((long long)*pd_uni((const unsigned long long *)M.cert));
+    const bool sure = (v1 - pd_max(v2, sv)) > 2.0 * bound;  // false for NaN
+    const long long ok = (valid && sure && bi + j1 == g) ? 1 : 0;
+    const bool unsure = valid && !sure;
+    const unsigned long long um = __ballot(unsure);
+    if (um != 0) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(M.unc_count, __popcll(um));
+      base = __shfl(base, 0, PD_WAVE);
+      const int pos = base + __popcll(um & ((1ull << lane) - 1ull));
+      if (unsure && pos < M.rows * M.W) pd_glb(M.unc_list)[pos] = r * M.W + c;
+    }
+    const long long wc = pd_wave_sum_i64(ok);
+    if (lane == 0) pd_glb(M.part_c)[local] = wc;
   }
   const double tot = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
@@ -235,6 +351,20 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   PD_DISPATCH_UPTO(DMAX, M.d, (lse_item<T, D>(M, item - off[m], lane)));
+}
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_lse_cert(const MapDev *__restrict__ maps,
+                                                       const int32_t *__restrict__ off, int n_maps,
+                                                       int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (lse_item<T, D, true>(M, item - off[m], lane)));
 }
 
 // The fit's objective launch: blocks [0, lse_blocks) are k_lse's; the next
@@ -350,18 +480,29 @@ __device__ inline void grad_block_sum(const MapDev &M, int local, double *part, 
 // moments computed once per plan (k_onehot) -- the form a fit uses, since the
 // label test costs about a fifth of the kernel.
 // With DIAG, also w = p (1 - p) times P_a(x1)^2 per lane (Hessian diagonal).
+// With HOT, the labelled grain's weight p - 1 is taken as -r, r = 1 - p_G the sum
+// of the other grains' probabilities (stored per pixel by the objective kernel),
+// so that near a fitted iterate, where p_G -> 1, it keeps its relative accuracy.
+// Logits in FP64 from the FP64 column data pxd; the weights accumulate against
+// the column data pxp of the evaluation type (the same array in FP64).
 template <typename T, int D, int CH, bool DIAG, bool HOT>
-__device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *lp,
-                                 const PD_AS_CONST int32_t *gp, const T (&cf)[D + 1],
+__device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONST T *pxp,
+                                 const PD_AS_CONST double *lp, const PD_AS_CONST int32_t *gp,
+                                 const PD_AS_CONST T *rp, const double (&cf)[D + 1],
                                  T (&racc)[D + 1], T (&dacc)[D + 1], int gbase, int lane) {
   constexpr int DP = D + 1;
+  constexpr bool F64 = sizeof(T) == sizeof(double);
+  double pd[CH][DP];
   T px[CH][DP];
-  T l[CH];
+  double l[CH];
   int g[CH];
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
 #pragma unroll
-    for (int a = 1; a < DP; ++a) px[j][a] = pxp[j * DP + a];
+    for (int a = 1; a < DP; ++a) {
+      pd[j][a] = pxd[j * DP + a];
+      px[j][a] = F64 ? (T)pd[j][a] : pxp[j * DP + a];
+    }
     l[j] = lp[j];
     if (HOT) g[j] = gp[j];
   }
@@ -370,32 +511,32 @@ __device__ inline void grad_cols(const PD_AS_CONST T *pxp, const PD_AS_CONST T *
 #pragma unroll
     for (int j = 0; j < CH; ++j) hit |= ((unsigned)(g[j] - gbase) < (unsigned)PD_WAVE) ? (1u << j) : 0u;
   }
-#pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    T s = cf[0];
-#pragma unroll
-    for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], px[j][a], s);
-    const T p = pd_exp2<T>(s - l[j]);
-    racc[0] += p;
-#pragma unroll
-    for (int a = 1; a < DP; ++a) racc[a] = pd_fma(p, px[j][a], racc[a]);
-    if (DIAG) {
-      const T w = pd_fma(-p, p, p);
-      dacc[0] += w;
-#pragma unroll
-      for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(w, px[j][a] * px[j][a], dacc[a]);
-    }
-  }
+  T rr[CH];
   if (HOT && hit) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      if ((hit >> j) & 1u) {
-        if (lane == g[j] - gbase) {
-          racc[0] -= (T)1;
+    for (int j = 0; j < CH; ++j) rr[j] = rp[j];
+  }
 #pragma unroll
-          for (int a = 1; a < DP; ++a) racc[a] -= px[j][a];
-        }
-      }
+  for (int j = 0; j < CH; ++j) {
+    double s = cf[0];
+#pragma unroll
+    for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], pd[j][a], s);
+    const T p = pd_exp2<T>((T)(s - l[j]));
+    T w = p;
+    T q = (T)1 - p;  // 1 - p (for the Hessian diagonal)
+    if (HOT && ((hit >> j) & 1u)) {
+      const bool own = lane == g[j] - gbase;
+      w = own ? -rr[j] : p;
+      q = own ? rr[j] : q;
+    }
+    racc[0] += w;
+#pragma unroll
+    for (int a = 1; a < DP; ++a) racc[a] = pd_fma(w, px[j][a], racc[a]);
+    if (DIAG) {
+      const T v = p * q;
+      dacc[0] += v;
+#pragma unroll
+      for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(v, px[j][a] * px[j][a], dacc[a]);
     }
   }
 }
@@ -415,21 +556,25 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
 #pragma unroll
   for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
   const auto txT = pd_uni((const T *)M.txT);
+  const auto txd = pd_uni((const double *)M.tx64);
   for (int r = r0; r < r1; ++r) {
-    const auto cp = pd_glb((const T *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
-    T cf[DP];
+    const auto cp = pd_glb((const double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
+    double cf[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) cf[a] = cp[a];
     T racc[DP], dacc[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) racc[a] = dacc[a] = (T)0;
-    const auto lrow = pd_uni((const T *)M.lse + (size_t)(r - M.row0) * M.W);
+    const auto lrow = pd_uni((const double *)M.lse + (size_t)(r - M.row0) * M.W);
+    const auto rrow = pd_uni((const T *)M.rpix + (size_t)(r - M.row0) * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
     int c = c0;
     for (; c + CH <= c1; c += CH)
-      grad_cols<T, D, CH, DIAG, HOT>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, CH, DIAG, HOT>(txd + (size_t)c * DP, txT + (size_t)c * DP, lrow + c, grow + c,
+                                     rrow + c, cf, racc, dacc, gbase, lane);
     for (; c < c1; ++c)
-      grad_cols<T, D, 1, DIAG, HOT>(txT + (size_t)c * DP, lrow + c, grow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, 1, DIAG, HOT>(txd + (size_t)c * DP, txT + (size_t)c * DP, lrow + c, grow + c,
+                                    rrow + c, cf, racc, dacc, gbase, lane);
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -722,9 +867,9 @@ void pd_launch_center(const MapDev *maps, int n_maps, int max_k, hipStream_t s) 
 }
 void pd_launch_prep(int prec, const MapDev *maps, const int32_t *off, int n_maps, int blocks,
                     hipStream_t s) {
+  (void)prec;  // FP64 row coefficients in both modes
   if (blocks <= 0) return;  // no rows to evaluate (empty row bands)
-  if (prec == 0) k_prep<double><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
-  else k_prep<float><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
+  k_prep<<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps);
 }
 #define PD_LAUNCH_BY_DMAX(KERNEL, T, dmax, blocks, s, ...)                    \
   switch (dmax) {                                                            \
@@ -753,6 +898,13 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
     case 6: KERNEL<T, 6, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
     default: KERNEL<T, 8, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;         \
   }
+void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                        int total, hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (blocks <= 0) return;
+  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse_cert, double, dmax, blocks, s, maps, off, n_maps, total); }
+  else { PD_LAUNCH_BY_DMAX(k_lse_cert, float, dmax, blocks, s, maps, off, n_maps, total); }
+}
 void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                           int total, const MapDev *amaps, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;

@@ -42,7 +42,8 @@ struct Arena {
 };
 
 struct MapRegions {
-  size_t tx64, ty64, txT, tyT, thc, C, lse, part_l, part_g, part_c, T3, lse32, part_g32, part_d, onehot;
+  size_t tx64, ty64, txT, tyT, thc, C, lse, rpix, part_l, part_g, part_c, T3, lse32, part_g32, part_d,
+      onehot, cert, unc_list;
 };
 
 // Everything one batched evaluation / assignment needs, laid out in an arena.
@@ -53,6 +54,10 @@ struct EvalPlan {
   // FP64/FP32: the indicator moments are computed once (pd_plan_onehot, after
   // the tables) and the gradient kernel skips the one-hot term (set before bind)
   bool onehot_pre = false;
+  // FP64/FP32: the objective launch also assigns every pixel with a certified
+  // arg-max (per-wave counts in part_c, the canonical pass for the rest); the
+  // caller clears the cert slots between evaluations (set before layout)
+  bool cert = false;
   int target_waves = 8192;
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;

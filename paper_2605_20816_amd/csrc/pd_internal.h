@@ -42,6 +42,8 @@ struct MapDev {
   double *thc;                      // [N][K]   -log2(e)/eps * (theta_i - mean_j theta_j)
   void *C;                          // [rows][Npad][DP] row coefficients, evaluation type
   void *lse;                        // [rows * W] base-2 log-sum-exp per pixel, evaluation type
+  void *rpix;                       // [rows * W] 1 - p_G(x) per pixel (the sum of the other
+                                    // grains' probabilities), evaluation type
   double *part_l;                   // [a_items] per-wave partial sums of log2 p_G
   double *part_g;                   // [stiles][Npad][K] partial sums of (p - delta) psi, or of
                                     // p psi when onehot is set
@@ -57,7 +59,16 @@ struct MapDev {
   // assignment
   int32_t *labels_out;              // n or null
   int64_t *n_correct;               // -> n_correct_out[map] or null
-  int64_t *part_c;                  // [a_items / 4] per-block correct counts
+  int64_t *part_c;                  // [a_items] per-block (k_assign) or per-wave (certified
+                                    // objective launch) correct counts
+  // certified accuracy inside the objective launch (the fit; null elsewhere):
+  // cert = the largest rounding bound of a logit against the canonical scores
+  // (u64 atomic maximum of non-negative doubles, k_prep); pixels whose top two
+  // logits are closer than twice that go to unc_list for the canonical arg-min
+  // (k_assign_list), whose correct ones are counted in fb_count
+  double *cert;
+  int32_t *unc_list, *unc_count;    // [rows * W] pixel indices; their number
+  int64_t *fb_count;
   // optional gate: when non-null and zero, every kernel skips this map
   const int32_t *gate;
   // FP32 row table and the BF16 matrix-core path
@@ -203,4 +214,9 @@ void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n
 // fit's decision kernel sums them itself.
 void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_maps, int total,
                       bool count, hipStream_t s);
+// k_lse with the certified arg-max of every pixel (per-wave correct counts in
+// part_c, uncertain pixels to unc_list), then k_assign_list on those pixels.
+void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                        int total, hipStream_t s);
+void pd_launch_assign_list(int dmax, const MapDev *maps, int n_maps, hipStream_t s);
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);

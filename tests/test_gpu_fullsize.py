@@ -134,13 +134,14 @@ def test_c3_full_map(pd, orc):
 
 
 def test_c3_at_the_fit(pd, orc):
-    """A fitted c3 iterate (FP32 fit with the diagonal preconditioner to 99%)."""
+    """A fitted c3 iterate (FP32 fit with the diagonal preconditioner to 99%:
+    about 2200 iterations with memory 32 and the diagonal refreshed every 10)."""
     pdl, ctx = pd
     gm = synth.config_c3()
     p = pdl.Problem(dev(gm.labels, torch.int32), gm.H, gm.W, gm.N, 4, 1e-3)
     th = torch.zeros((gm.N, 15), dtype=torch.float64, device="cuda")
-    rep = ctx.fit([p], [th], "fp32", init="zero", max_iter=2000, target_acc=0.99,
-                  history=16, precondition=40, check_every=8)[0]
+    rep = ctx.fit([p], [th], "fp32", init="zero", max_iter=5000, target_acc=0.99,
+                  history=32, precondition=10)[0]
     print(f"c3 fit: {rep['iters']} iterations, acc {rep['acc']:.4f}")
     assert rep["status"] == "target"
     bands = [(0, 8), (508, 516), (1016, 1024)]

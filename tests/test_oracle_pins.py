@@ -645,3 +645,65 @@ def test_annealed_fit_levels_and_err_aligned_stop(orc):
     # phi at the target eps
     assert r["phi"] == orc.objective_grad(r["theta"], gm.labels, gm.H, gm.W, d, eps,
                                           grad=False)[0]
+
+
+# ------------------------------------------ physical parameters (f1) --------
+
+def _forward_pd(y, w):
+    """Section 2.3.1: theta = (|y|^2 - w, -2 y1, -2 y2) in the order (1, x, y)."""
+    return np.stack([(y ** 2).sum(1) - w, -2 * y[:, 0], -2 * y[:, 1]], 1)
+
+
+def _forward_apd_legendre(y, w, A):
+    """eq. h-APD in monomials, then x^2 = (2 P_2(x) + 1) / 3 (Section 3.3)."""
+    Ay = np.einsum("nij,nj->ni", A, y)
+    return np.stack([(y * Ay).sum(1) - w + (A[:, 0, 0] + A[:, 1, 1]) / 3, -2 * Ay[:, 0],
+                     -2 * Ay[:, 1], 2 * A[:, 0, 0] / 3, 2 * A[:, 0, 1], 2 * A[:, 1, 1] / 3], 1)
+
+
+def test_recover_power_diagram_round_trip(orc):
+    rng = np.random.default_rng(60)
+    y = rng.uniform(-1, 1, (20, 2))
+    w = rng.uniform(0, 0.05, 20)
+    y2, w2, A2, lam = orc.recover_params(_forward_pd(y, w), 1)
+    assert lam == 0.0 and np.allclose(A2, np.eye(2))
+    assert np.max(np.abs(y2 - y)) <= 1e-15 and np.max(np.abs(w2 - w)) <= 1e-14
+
+
+def test_recover_anisotropic_round_trip(orc):
+    """The generator's own (y, w, A) come back from its Legendre coefficients
+    (every A_i has lambda_min >= 0.5 > margin, so no shift)."""
+    gm = synth.anisotropic_power_diagram(32, 32, 25, np.random.default_rng(61))
+    th = _forward_apd_legendre(gm.sites, gm.weights, gm.aniso)
+    y2, w2, A2, lam = orc.recover_params(th, 2, margin=0.1)
+    assert lam == 0.0
+    assert np.max(np.abs(A2 - gm.aniso)) <= 1e-14
+    assert np.max(np.abs(y2 - gm.sites)) <= 1e-12
+    assert np.max(np.abs(w2 - gm.weights)) <= 1e-12
+
+
+def test_recover_gauge_shift_keeps_the_diagram(orc):
+    """Section 5.6.3: in the fit's gauge theta_N = 0 the last anisotropy is 0 (not
+    positive definite); the common shift A_i + lambda I makes every smallest
+    eigenvalue >= margin, the smallest exactly margin, and the recovered
+    parameters generate scores that differ from the given ones by one common
+    function (Lemma 4.2), so the diagram is the same."""
+    gm = synth.anisotropic_power_diagram(40, 36, 18, np.random.default_rng(62))
+    th = _forward_apd_legendre(gm.sites, gm.weights, gm.aniso)
+    th = th - th[-1]  # the gauge theta_N = 0
+    margin = 0.05
+    y2, w2, A2, lam = orc.recover_params(th, 2, margin=margin)
+    lmin = np.linalg.eigvalsh(A2)[:, 0]
+    assert lam > 0 and np.all(lmin >= margin - 1e-12) and abs(lmin.min() - margin) <= 1e-12
+    back = _forward_apd_legendre(y2, w2, A2)
+    diff = back - th
+    assert np.max(np.abs(diff - diff[0])) <= 1e-11 * np.max(np.abs(th))
+    F0 = orc.assign(th, gm.H, gm.W, 2)[0]
+    F1 = orc.assign(back, gm.H, gm.W, 2)[0]
+    assert np.mean(F0 == F1) >= 1 - 2 / F0.size
+    assert np.array_equal(F0, gm.labels) or np.mean(F0 == gm.labels) >= 0.995
+
+
+def test_recover_rejects_higher_degree(orc):
+    with pytest.raises(ValueError):
+        orc.recover_params(np.zeros((3, 10)), 3)
