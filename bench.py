@@ -201,7 +201,58 @@ def band_errors(ctx, orc_rows, prob, th, prec, band, torch):
             "grad_max_rel": float(np.max(np.abs(gd - gr)) / np.max(np.abs(gr)))}
 
 
+def summarize_trace(path: str, top: int = 30) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace CSV: per kernel, the number
+    of launches and their average duration, and the same over the working
+    launches only.  A fit captures several steps per graph, and a map that has
+    stopped leaves its later steps as gated launches that return at once; those
+    (under 2% of the kernel's longest launch) are counted apart, so the working
+    average is the one to compare with a live per-launch timing."""
+    import csv
+    durs = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+            durs.setdefault(row["Kernel_Name"], []).append(d)
+    lines = ["| kernel | launches | avg us (all) | working launches | avg us (working) | total ms |",
+             "|---|---|---|---|---|---|"]
+    for name, ds in sorted(durs.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        mx = max(ds)
+        work = [d for d in ds if d >= 0.02 * mx]
+        lines.append(f"| `{name}` | {len(ds)} | {sum(ds) / len(ds) / 1e3:.2f} | {len(work)} | "
+                     f"{sum(work) / len(work) / 1e3:.2f} | {sum(ds) / 1e6:.2f} |")
+    return "\n".join(lines)
+
+
+def summarize_counters(path: str) -> str:
+    """Markdown summary of a rocprofv3 --pmc counter CSV: per kernel and counter,
+    the dispatches and the average counter value per dispatch over the working
+    dispatches (those whose counter sum is at least 2% of the kernel's largest:
+    gated launches of a stopped map read almost nothing)."""
+    import csv
+    vals = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            key = (row["Kernel_Name"], row["Counter_Name"])
+            vals.setdefault(key, {}).setdefault(row["Dispatch_Id"], 0.0)
+            vals[key][row["Dispatch_Id"]] += float(row["Counter_Value"])
+    lines = ["| kernel | counter | dispatches | working | avg per working dispatch |",
+             "|---|---|---|---|---|"]
+    for (name, ctr), per in sorted(vals.items(), key=lambda kv: -sum(kv[1].values()))[:40]:
+        v = list(per.values())
+        mx = max(v) if v else 0.0
+        work = [x for x in v if x >= 0.02 * mx] or v
+        lines.append(f"| `{name}` | {ctr} | {len(v)} | {len(work)} | {sum(work) / len(work):.6g} |")
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-trace":
+        print(summarize_trace(sys.argv[2]))
+        return
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-counters":
+        print(summarize_counters(sys.argv[2]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed L-BFGS iterations")

@@ -164,14 +164,15 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.tyT = L.take(tsz * M.H * M.DP);
     R.thc = L.take(sizeof(double) * M.N * M.K);
     // FP64 row coefficients and log-sum-exp in both VALU modes
-    R.C = L.take(mf ? 0 : sizeof(double) * (size_t)M.rows * M.Npad * M.DP);
+    // (the BF16 path needs them only for the certified arg-max of a fit)
+    R.C = L.take(mf && !P.cert ? 0 : sizeof(double) * (size_t)M.rows * M.Npad * M.DP);
     R.lse = L.take(mf ? 0 : sizeof(double) * n_px);
-    R.rpix = L.take(mf ? 0 : tsz * n_px);
+    R.rpix = L.take(mf ? sizeof(float) * (size_t)M.n32 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
     R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
     R.part_c = L.take(sizeof(int64_t) * M.a_items);
-    const bool cert = P.cert && !mf;
+    const bool cert = P.cert;
     R.cert = L.take(cert ? 32 : 0);  // bound (8), uncertain count (4), canonical count (8)
     R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
@@ -217,7 +218,7 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
     M.part_l = (double *)(base + R.part_l);
     M.part_g = (double *)(base + R.part_g);
     M.part_c = (int64_t *)(base + R.part_c);
-    if (P.cert && P.prec != 2) {
+    if (P.cert) {
       M.cert = (double *)(base + R.cert);
       M.unc_count = (int32_t *)(base + R.cert + 8);
       M.fb_count = (int64_t *)(base + R.cert + 16);

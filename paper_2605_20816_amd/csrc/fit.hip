@@ -1478,8 +1478,9 @@ void pd_fit_release(pd_ctx *ctx) {
 // pending accuracy check of its accepted iterate (amaps).
 static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *amaps,
                         const EvalPlan *Pdiag, hipStream_t s) {
+  (void)amaps;
   if (prec == 2) {
-    pd_launch_assign(P.dmax, amaps, P.d_offA, P.n, P.offA[P.n], false, s);
+    // matrix-core objective and gradient, then the certified assignment of xt
     pd_bf16_plan_eval(ctx, P, s, false);
     // the preconditioner's Hessian diagonal: an FP32 evaluation of the maps
     // whose refresh flag is set (its gate), at the same trial point
@@ -1549,7 +1550,7 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
   P.with_diag = opts->precondition > 0;
   P.onehot_pre = true;  // indicator moments once per fit
-  P.cert = eval_prec != 2;  // the accuracy of every evaluated point, certified
+  P.cert = true;  // the accuracy of every evaluated point, certified
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;
   std::vector<size_t> o_vec(n);

@@ -208,17 +208,116 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
   PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i)));
 }
 
+// The certified arg-max of one pixel per lane (see lse_item): the 8 logits of
+// the best chunk bi are formed again (FP64), and the gap from its best grain to
+// the runner-up (in the chunk, or sv, an upper bound of the other chunks'
+// maxima) is compared with twice the rounding bound of cert_bound.
+template <int D>
+__device__ inline void cert_finish(const MapDev &M, int local, int lane, int r, int c, bool valid,
+                                   int g, const double (&px)[D + 1],
+                                   const PD_AS_GLOBAL double *Cvec, int bi, double sv) {
+  constexpr int DP = D + 1;
+  const auto cb = Cvec + (size_t)bi * DP;
+  double v1 = -INFINITY, v2 = -INFINITY;
+  int j1 = 0;
+#pragma unroll 1
+  for (int j = 0; j < 8; ++j) {
+    double v = cb[j * DP];
+#pragma unroll
+    for (int a = 1; a < DP; ++a) v = pd_fma(cb[j * DP + a], px[a], v);
+    if (v > v1) {
+      v2 = v1;
+      v1 = v;
+      j1 = j;
+    } else {
+      v2 = pd_max(v2, v);
+    }
+  }
+  const double bound = __longlong_as_double((long long)*pd_uni((const unsigned long long *)M.cert));
+  const bool sure = (v1 - pd_max(v2, sv)) > 2.0 * bound;  // false for NaN
+  const long long ok = (valid && sure && bi + j1 == g) ? 1 : 0;
+  const bool unsure = valid && !sure;
+  const unsigned long long um = __ballot(unsure);
+  if (um != 0) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(M.unc_count, __popcll(um));
+    base = __shfl(base, 0, PD_WAVE);
+    const int pos = base + __popcll(um & ((1ull << lane) - 1ull));
+    if (unsure && pos < M.rows * M.W) pd_glb(M.unc_list)[pos] = r * M.W + c;
+  }
+  const long long wc = pd_wave_sum_i64(ok);
+  if (lane == 0) pd_glb(M.part_c)[local] = wc;
+}
+
+// The certified arg-max alone (the FP64 evaluation runs it after k_lse: fused
+// into the FP64 objective loop it doubled that loop's registers): FP64 logits,
+// the chunk maxima, the best chunk and an upper bound of the others.
+template <int D>
+__device__ inline void argmax_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  if (local >= M.rows * M.segs) {
+    if (lane == 0) pd_glb(M.part_c)[local] = 0;
+    return;
+  }
+  const int lr = local / M.segs;
+  const int r = M.row0 + lr;
+  const int c = (local - lr * M.segs) * PD_WAVE + lane;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  const auto tx = pd_glb(M.tx64 + (size_t)cc * DP);
+  double px[DP];
+#pragma unroll
+  for (int a = 0; a < DP; ++a) px[a] = tx[a];
+  const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
+  const auto Cvec = pd_glb((const double *)M.C + (size_t)lr * M.Npad * DP);
+  const int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  double bv = -INFINITY, sv = -INFINITY;
+  int bi = 0;
+  for (int i0 = 0; i0 < M.N; i0 += 8) {
+    double cm = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const auto cp = Crow + (size_t)(i0 + j) * DP;
+      double v = cp[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
+      cm = pd_max(cm, v);
+    }
+    const bool gt = cm > bv;
+    sv = gt ? bv : pd_max(sv, cm);
+    bi = gt ? i0 : bi;
+    bv = gt ? cm : bv;
+  }
+  cert_finish<D>(M, local, lane, r, c, valid, g, px, Cvec, bi, sv);
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_cert_argmax(const MapDev *__restrict__ maps,
+                                                          const int32_t *__restrict__ off,
+                                                          int n_maps, int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (argmax_item<D>(M, item - off[m], lane)));
+}
+
 // ---------------------------------------------------------------------------
 // Kernel A: per-pixel base-2 log-sum-exp over grains and partial sums of log2 p_G.
-// With CERT, also the hard assignment of every pixel at this theta, certified
+// With CERT (FP32 exponentials; the FP64 evaluation runs k_cert_argmax after
+// k_lse), also the hard assignment of every pixel at this theta, certified
 // against the canonical FP64 arg-min (Section 2.1): the loop keeps the largest
-// chunk maximum (and its chunk) and the second largest; at the end the 8 logits
-// of the best chunk are formed again (the same operations, so the same values),
-// giving the best grain b and the runner-up value.  If the gap to the runner-up
-// exceeds twice the logit rounding bound of cert_bound (taken over all grains),
-// the canonical scores have the same strict minimum at b; otherwise the pixel is
-// listed for k_assign_list.  Per-wave counts of certified correct pixels go to
-// part_c[local].
+// chunk maximum (and its chunk) and an upper bound of the other chunks' maxima;
+// at the end the 8 logits of the best chunk are formed again, giving the best
+// grain b and the runner-up value.  If the gap to the runner-up exceeds twice the
+// logit rounding bound of cert_bound (taken over all grains; it also covers the
+// few units in the last place between the loop's reference-relative logits and
+// the recomputed ones), the canonical scores have the same strict minimum at b;
+// otherwise the pixel is listed for k_assign_list.  Per-wave counts of certified
+// correct pixels go to part_c[local].
 template <typename T, int D, bool CERT = false>
 __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
@@ -245,49 +344,133 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   // S sums exp2(s_i - mrun) over the grains other than the pixel's label g, so
   // that r = 1 - p_g (the labelled grain's p - 1 in eq. grad, up to sign) comes
   // out as a sum of small terms instead of a difference of two numbers near 1
+  // Online maximum: after the first chunk a chunk's logits are formed relative
+  // to the running reference, u = (C0 - mrun) + sum_a C_a P_a(x1) (FP64), and
+  // converted once to the exponent type; the reference moves (an FP64 path) only
+  // when some lane of the wave meets a larger logit.
+  constexpr bool F32 = sizeof(T) == sizeof(float);
   double mrun = -INFINITY;
   T S = (T)0;
-  double bv = -INFINITY, sv = -INFINITY;  // CERT: best / second chunk maximum
+  double bv = -INFINITY, sv = -INFINITY;  // CERT: best chunk maximum, an upper bound of the others
   int bi = 0;                             // CERT: first grain of the best chunk
-  // grains N .. Npad-1 (read when N is not a multiple of 8) have row
-  // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
-  for (int i0 = 0; i0 < N; i0 += 8) {
-    double s[8];
+  if constexpr (F32) {
+    // chunk 0 (grains 0..7; N >= 2, padded grains have logit -inf)
+    double s0[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const auto cp = Crow + (size_t)(i0 + j) * DP;
+      const auto cp = Crow + (size_t)j * DP;
       double v = cp[0];
 #pragma unroll
       for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
-      s[j] = v;
+      s0[j] = v;
     }
-    double cm = s[0];
+    double cm = s0[0];
 #pragma unroll
-    for (int j = 1; j < 8; ++j) cm = pd_max(cm, s[j]);
-    const double mnew = pd_max(mrun, cm);
-    if (CERT) {
-      const bool gt = cm > bv;
-      sv = gt ? bv : pd_max(sv, cm);
+    for (int j = 1; j < 8; ++j) cm = pd_max(cm, s0[j]);
+    mrun = cm;
+    bv = cm;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const T e = pd_exp2<T>((T)(s0[j] - mrun));
+      S += (j == g) ? (T)0 : e;
+    }
+  }
+  // grains N .. Npad-1 (read when N is not a multiple of 8) have row
+  // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
+  for (int i0 = F32 ? 8 : 0; i0 < N; i0 += 8) {
+    T t[8];
+    double cup;  // CERT: an upper bound of the chunk's largest logit, relative to mrun
+    if constexpr (F32) {
+      // FP32 exponentials: logits relative to the running reference, one
+      // conversion each; the reference moves only when a lane meets a larger logit
+      double u[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const auto cp = Crow + (size_t)(i0 + j) * DP;
+        double v = cp[0] - mrun;
+#pragma unroll
+        for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
+        u[j] = v;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = (T)u[j];
+      T cmu = t[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) cmu = pd_max(cmu, t[j]);
+      // the FP32 rounding of u widened by one unit in the last place
+      cup = (double)cmu;
+      cup += fabs(cup) * 0x1p-23;
+      if (__ballot(cmu > (T)0) != 0) {
+        double um = u[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) um = pd_max(um, u[j]);
+        const double sh = um > 0.0 ? um : 0.0;
+        cup = um;
+        S *= pd_exp2<T>((T)(-sh));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = (T)(u[j] - sh);
+        if (CERT) {
+          const double ca = mrun + cup;
+          const bool gt = ca > bv;
+          sv = gt ? bv : pd_max(sv, ca);
+          bi = gt ? i0 : bi;
+          bv = gt ? ca : bv;
+        }
+        mrun += sh;
+        cup = -INFINITY;  // recorded
+      }
+    } else {
+      // FP64 exponentials: absolute logits and the usual online maximum
+      double sj[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const auto cp = Crow + (size_t)(i0 + j) * DP;
+        double v = cp[0];
+#pragma unroll
+        for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
+        sj[j] = v;
+      }
+      double cm = sj[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) cm = pd_max(cm, sj[j]);
+      const double mnew = pd_max(mrun, cm);
+      S *= pd_exp2<T>(mrun - mnew);
+      T e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = pd_exp2<T>(sj[j] - mnew);
+      if (__ballot((unsigned)(g - i0) < 8u) != 0) {
+        // a label of this segment lies in the chunk: leave its term out
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = (i0 + j == g) ? (T)0 : e[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) S += e[j];
+      mrun = mnew;
+      continue;
+    }
+    if (CERT && cup != -INFINITY) {
+      const double ca = mrun + cup;
+      const bool gt = ca > bv;
+      sv = gt ? bv : pd_max(sv, ca);
       bi = gt ? i0 : bi;
-      bv = gt ? cm : bv;
+      bv = gt ? ca : bv;
     }
-    S *= pd_exp2<T>((T)(mrun - mnew));
-    T e[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) e[j] = pd_exp2<T>((T)(s[j] - mnew));
     if (__ballot((unsigned)(g - i0) < 8u) != 0) {
       // a label of this segment lies in the chunk: leave its term out
 #pragma unroll
-      for (int j = 0; j < 8; ++j) e[j] = (i0 + j == g) ? (T)0 : e[j];
-    }
+      for (int j = 0; j < 8; ++j) {
+        const T e = pd_exp2<T>(t[j]);
+        S += (i0 + j == g) ? (T)0 : e;
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) S += e[j];
-    mrun = mnew;
+      for (int j = 0; j < 8; ++j) S += pd_exp2<T>(t[j]);
+    }
   }
   double ell = 0.0;
   double lse;
   if (g >= 0 && g < N) {
-    // the label's logit, with the same operations as in the loop (bit-identical)
+    // the label's logit (its term was left out of S)
     const auto cg = Cvec + (size_t)g * DP;
     double v = cg[0];
 #pragma unroll
@@ -303,38 +486,8 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   }
   if (valid) pd_glb((double *)M.lse)[(size_t)lr * M.W + c] = lse;
   else ell = 0.0;
-  if constexpr (CERT) {
-    const auto cb = Cvec + (size_t)bi * DP;
-    double v1 = -INFINITY, v2 = -INFINITY;
-    int j1 = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      double v = cb[j * DP];
-#pragma unroll
-      for (int a = 1; a < DP; ++a) v = pd_fma(cb[j * DP + a], px[a], v);
-      if (v > v1) {
-        v2 = v1;
-        v1 = v;
-        j1 = j;
-      } else {
-        v2 = pd_max(v2, v);
-      }
-    }
-    const double bound = __longlong_as_double((long long)*pd_uni((const unsigned long long *)M.cert));
-    const bool sure = (v1 - pd_max(v2, sv)) > 2.0 * bound;  // false for NaN
-    const long long ok = (valid && sure && bi + j1 == g) ? 1 : 0;
-    const bool unsure = valid && !sure;
-    const unsigned long long um = __ballot(unsure);
-    if (um != 0) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(M.unc_count, __popcll(um));
-      base = __shfl(base, 0, PD_WAVE);
-      const int pos = base + __popcll(um & ((1ull << lane) - 1ull));
-      if (unsure && pos < M.rows * M.W) pd_glb(M.unc_list)[pos] = r * M.W + c;
-    }
-    const long long wc = pd_wave_sum_i64(ok);
-    if (lane == 0) pd_glb(M.part_c)[local] = wc;
-  }
+  if constexpr (CERT) cert_finish<D>(M, local, lane, r, c, valid, g, px, Cvec, bi, sv);
+
   const double tot = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
 }
@@ -898,12 +1051,28 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
     case 6: KERNEL<T, 6, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
     default: KERNEL<T, 8, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;         \
   }
+void pd_launch_cert_argmax(int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                           int total, hipStream_t s) {
+  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (blocks <= 0) return;
+  switch (dmax) {
+    case 2: k_cert_argmax<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    case 4: k_cert_argmax<4><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    case 6: k_cert_argmax<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+    default: k_cert_argmax<8><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
+  }
+}
 void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                         int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
   if (blocks <= 0) return;
-  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse_cert, double, dmax, blocks, s, maps, off, n_maps, total); }
-  else { PD_LAUNCH_BY_DMAX(k_lse_cert, float, dmax, blocks, s, maps, off, n_maps, total); }
+  if (prec == 0) {
+    // FP64: the objective kernel as is, then the certified arg-max pass
+    PD_LAUNCH_BY_DMAX(k_lse, double, dmax, blocks, s, maps, off, n_maps, total);
+    pd_launch_cert_argmax(dmax, maps, off, n_maps, total, s);
+  } else {
+    PD_LAUNCH_BY_DMAX(k_lse_cert, float, dmax, blocks, s, maps, off, n_maps, total);
+  }
 }
 void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                           int total, const MapDev *amaps, hipStream_t s) {

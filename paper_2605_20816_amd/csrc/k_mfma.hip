@@ -190,11 +190,15 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) split3(v[kb], bh[t][kb], bm[t][kb], bl[t][kb]);
   }
+  // S sums over the grains other than the pixel's label (r = 1 - p_G, below)
   float mrun[TPW], S[TPW];
+  int lab[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     mrun[t] = -INFINITY;
     S[t] = 0.f;
+    const int p = (tile0 + t) * 32 + col;
+    lab[t] = p < npx ? pd_glb(M.labels)[pix0 + p] : -1;
   }
   const long long tot = (long long)M.Npad * Kp;
   const __bf16 *T = (const __bf16 *)M.T3;
@@ -243,8 +247,17 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
         if (cm == -INFINITY) continue;
         const float mn = fmaxf(mrun[t], cm);
         float s = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mn);
+        if (__ballot((unsigned)(lab[t] - gbase) < 32u) != 0) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) s += __builtin_amdgcn_exp2f(acc[j] - mn);
+          for (int j = 0; j < 16; ++j) {
+            const int g = gbase + (j / 4) * 8 + half * 4 + (j % 4);
+            const float e = __builtin_amdgcn_exp2f(acc[j] - mn);
+            s += g == lab[t] ? 0.f : e;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) s += __builtin_amdgcn_exp2f(acc[j] - mn);
+        }
         S[t] = s;
         mrun[t] = mn;
       }
@@ -257,14 +270,14 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
     const float mo = __shfl_xor(mrun[t], 32, PD_WAVE);
     const float so = __shfl_xor(S[t], 32, PD_WAVE);
     const float mm = fmaxf(mrun[t], mo);
-    const float ss = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mm) + so * __builtin_amdgcn_exp2f(mo - mm);
-    const float lse = mm + __builtin_amdgcn_logf(ss);
+    // the other grains' sum (both halves), then the label's own term
+    const float sx = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mm) + so * __builtin_amdgcn_exp2f(mo - mm);
     const int p = (tile0 + t) * 32 + col;
     if (half == 0 && p < M.n32) {
-      pd_glb(M.lse32)[p] = p < npx ? lse : INFINITY;
+      float lse = INFINITY, rr = 0.f;
       if (p < npx) {
         const int q = pix0 + p;
-        const int g = pd_glb(M.labels)[q];
+        const int g = lab[t];
         if (g >= 0 && g < M.N) {
           // exact FP64 logit of the true grain
           const int r = q / M.W, c = q - r * M.W;
@@ -272,11 +285,17 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
           const double *th = M.thc + (size_t)g * M.K;
           double sg = 0.0;
           for (int k = 0; k < M.K; ++k) sg = __builtin_fma(th[k], px[c_fa[k]] * py[c_fb[k]], sg);
+          const float tot = sx + __builtin_amdgcn_exp2f((float)(sg - (double)mm));
+          lse = mm + __builtin_amdgcn_logf(tot);
+          rr = sx / tot;
           ell += sg - (double)lse;
         } else {
+          lse = mm + __builtin_amdgcn_logf(sx);
           ell = NAN;
         }
       }
+      pd_glb(M.lse32)[p] = lse;
+      pd_glb((float *)M.rpix)[p] = rr;
     }
   }
   const double tot_l = pd_wave_sum(ell);
@@ -303,15 +322,20 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ m
 //   sQ  [2][2][64]   x 16 B : psi^T (feature = column) in FP16 hi/lo for the
 //                             gradient product, inner index h*8+e of block kb2
 //                             = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4
-//   sL, sG [32]             : lse and label of the tile's pixels
-// The gradient product takes p - delta in [-1, 1] as one FP16 value (11-bit
-// mantissa, 2^-12 relative) against the two FP16 pieces of psi.
+//   sL, sR, sG [32]         : lse, r = 1 - p_G and label of the tile's pixels
+// The gradient product takes the weight p (other grains) or -r (the pixel's
+// own grain: p - 1 without the cancellation near p = 1) as one FP16 value
+// (11-bit mantissa, 2^-12 relative), scaled by 2^PD_MF_WSHIFT so that small
+// weights stay normal, against the two FP16 pieces of psi; the scale is taken
+// out of the FP32 partial sums.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
+#define PD_MF_WSHIFT 12
 struct GradLds {
   bf16x8 A[3][2][64];
   f16x8 Q[2][2][64];
   float L[32];
+  float R[32];
   int G[32];
   int lo, hi;
 };
@@ -372,6 +396,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
         lrow[4 * b + r] = S.L[8 * b + 4 * half + r];
         grow[4 * b + r] = S.G[8 * b + 4 * half + r];
       }
+    constexpr float wscale = (float)(1 << PD_MF_WSHIFT);
     f32x16 acc[GT];
 #pragma unroll
     for (int t = 0; t < GT; ++t)
@@ -395,13 +420,18 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
 #pragma unroll
     for (int t = 0; t < GT; ++t)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]);
+      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]) * wscale;
     if (S.hi >= g0 && S.lo < g0 + GT * 32) {
+      float rrow[16];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rrow[4 * b + r] = S.R[8 * b + 4 * half + r];
 #pragma unroll
       for (int t = 0; t < GT; ++t) {
         const int grain = g0 + t * 32 + col;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[t][j] -= (grow[j] == grain) ? 1.f : 0.f;
+        for (int j = 0; j < 16; ++j) acc[t][j] = (grow[j] == grain) ? -rrow[j] * wscale : acc[t][j];
       }
     }
 #pragma unroll
@@ -430,6 +460,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   PixTables<NKB> tab;     // wave 0
   float qx[8], qy[8];     // waves 1-2
   float lse_l = 0.f;      // wave 3 (lanes < 32)
+  float r_l = 0.f;
   int lab_l = -1;
   auto load_tile = [&](int pt) {
     const int pbase = pt * 32;
@@ -452,6 +483,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     } else if (lane < 32) {
       const int p = pbase + lane;
       lse_l = pd_glb(M.lse32)[p];
+      r_l = pd_glb((const float *)M.rpix)[p];
       lab_l = p < npx ? pd_glb(M.labels)[pix0 + p] : -1;
     }
   };
@@ -481,6 +513,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
       int g = -1, lo = 0x7fffffff, hi = -1;
       if (lane < 32) {
         S.L[lane] = lse_l;
+        S.R[lane] = r_l;
         g = lab_l;
         S.G[lane] = g;
         if (g >= 0) lo = hi = g;
@@ -519,7 +552,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int g = g0 + t * 32 + (j / 4) * 8 + half * 4 + (j % 4);
-      pd_glb(out)[(size_t)g * FW + col] = accg[t][j];
+      pd_glb(out)[(size_t)g * FW + col] = accg[t][j] * (1.f / (float)(1 << PD_MF_WSHIFT));
     }
   }
 }
@@ -605,6 +638,13 @@ void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
 void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   for (int st = 0; st < 4; ++st) pd_bf16_launch(P, st, s);
+  if (P.cert) {
+    // the certified arg-max of every pixel (FP64 row coefficients), as in the
+    // FP64 evaluation of a fit
+    pd_launch_prep(0, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
+    pd_launch_cert_argmax(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+    pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
+  }
 }
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,

@@ -219,4 +219,7 @@ void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_ma
 void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                         int total, hipStream_t s);
 void pd_launch_assign_list(int dmax, const MapDev *maps, int n_maps, hipStream_t s);
+// The certified arg-max pass alone (FP64 row coefficients from k_prep).
+void pd_launch_cert_argmax(int dmax, const MapDev *maps, const int32_t *off, int n_maps,
+                           int total, hipStream_t s);
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);
