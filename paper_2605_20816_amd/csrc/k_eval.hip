@@ -636,26 +636,23 @@ __device__ inline void grad_block_sum(const MapDev &M, int local, double *part, 
 // With HOT, the labelled grain's weight p - 1 is taken as -r, r = 1 - p_G the sum
 // of the other grains' probabilities (stored per pixel by the objective kernel),
 // so that near a fitted iterate, where p_G -> 1, it keeps its relative accuracy.
-// Logits in FP64 from the FP64 column data pxd; the weights accumulate against
-// the column data pxp of the evaluation type (the same array in FP64).
+// Logits in FP64 from the FP64 column data; p in the evaluation type T (FP32
+// exp2 of the rounded FP64 difference, or the FP64 exp2); the weighted sums per
+// row in FP64 (an FP64 FMA issues at the non-packed FP32 rate, and one FP64
+// copy of the column data keeps the scalar registers of a chunk in budget).
 template <typename T, int D, int CH, bool DIAG, bool HOT>
-__device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONST T *pxp,
-                                 const PD_AS_CONST double *lp, const PD_AS_CONST int32_t *gp,
-                                 const PD_AS_CONST T *rp, const double (&cf)[D + 1],
-                                 T (&racc)[D + 1], T (&dacc)[D + 1], int gbase, int lane) {
+__device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONST double *lp,
+                                 const PD_AS_CONST int32_t *gp, const PD_AS_CONST T *rp,
+                                 const double (&cf)[D + 1], double (&racc)[D + 1],
+                                 double (&dacc)[D + 1], int gbase, int lane) {
   constexpr int DP = D + 1;
-  constexpr bool F64 = sizeof(T) == sizeof(double);
   double pd[CH][DP];
-  T px[CH][DP];
   double l[CH];
   int g[CH];
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
 #pragma unroll
-    for (int a = 1; a < DP; ++a) {
-      pd[j][a] = pxd[j * DP + a];
-      px[j][a] = F64 ? (T)pd[j][a] : pxp[j * DP + a];
-    }
+    for (int a = 1; a < DP; ++a) pd[j][a] = pxd[j * DP + a];
     l[j] = lp[j];
     if (HOT) g[j] = gp[j];
   }
@@ -671,10 +668,10 @@ __device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONS
   }
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
-    double s = cf[0];
+    double s = cf[0] - l[j];
 #pragma unroll
     for (int a = 1; a < DP; ++a) s = pd_fma(cf[a], pd[j][a], s);
-    const T p = pd_exp2<T>((T)(s - l[j]));
+    const T p = pd_exp2<T>((T)s);
     T w = p;
     T q = (T)1 - p;  // 1 - p (for the Hessian diagonal)
     if (HOT && ((hit >> j) & 1u)) {
@@ -682,23 +679,33 @@ __device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONS
       w = own ? -rr[j] : p;
       q = own ? rr[j] : q;
     }
-    racc[0] += w;
+    const double wd = (double)w;
+    racc[0] += wd;
 #pragma unroll
-    for (int a = 1; a < DP; ++a) racc[a] = pd_fma(w, px[j][a], racc[a]);
+    for (int a = 1; a < DP; ++a) racc[a] = pd_fma(wd, pd[j][a], racc[a]);
     if (DIAG) {
-      const T v = p * q;
+      const double v = (double)(p * q);
       dacc[0] += v;
 #pragma unroll
-      for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(v, px[j][a] * px[j][a], dacc[a]);
+      for (int a = 1; a < DP; ++a) dacc[a] = pd_fma(v, pd[j][a] * pd[j][a], dacc[a]);
     }
   }
+}
+
+// Columns per chunk of the gradient loop: the chunk's wave-uniform column data
+// (P_a(x1) for a >= 1 and lse in FP64; the label and r with HOT) in at most
+// 64 scalar registers.
+template <int D, bool HOT>
+constexpr int grad_chunk() {
+  constexpr int dw = 2 * D + 2 + (HOT ? 2 : 0);
+  return 8 * dw <= 64 ? 8 : 4 * dw <= 64 ? 4 : 2;
 }
 
 template <typename T, int D, bool DIAG, bool HOT>
 __device__ inline void grad_item(const MapDev &M, int local, int lane, double *sh) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  constexpr int CH = 8;
+  constexpr int CH = grad_chunk<D, HOT>();
   const GradItem it = grad_item_of(M, local);
   const int r0 = it.r0, r1 = it.r1, c0 = it.c0, c1 = it.c1;
   const int gbase = it.gbase;
@@ -708,31 +715,30 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
   for (int k = 0; k < K; ++k) q[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
-  const auto txT = pd_uni((const T *)M.txT);
   const auto txd = pd_uni((const double *)M.tx64);
   for (int r = r0; r < r1; ++r) {
     const auto cp = pd_glb((const double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
     double cf[DP];
 #pragma unroll
     for (int a = 0; a < DP; ++a) cf[a] = cp[a];
-    T racc[DP], dacc[DP];
+    double racc[DP], dacc[DP];
 #pragma unroll
-    for (int a = 0; a < DP; ++a) racc[a] = dacc[a] = (T)0;
+    for (int a = 0; a < DP; ++a) racc[a] = dacc[a] = 0.0;
     const auto lrow = pd_uni((const double *)M.lse + (size_t)(r - M.row0) * M.W);
     const auto rrow = pd_uni((const T *)M.rpix + (size_t)(r - M.row0) * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
     int c = c0;
     for (; c + CH <= c1; c += CH)
-      grad_cols<T, D, CH, DIAG, HOT>(txd + (size_t)c * DP, txT + (size_t)c * DP, lrow + c, grow + c,
-                                     rrow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, CH, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf, racc,
+                                     dacc, gbase, lane);
     for (; c < c1; ++c)
-      grad_cols<T, D, 1, DIAG, HOT>(txd + (size_t)c * DP, txT + (size_t)c * DP, lrow + c, grow + c,
-                                    rrow + c, cf, racc, dacc, gbase, lane);
+      grad_cols<T, D, 1, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf, racc,
+                                    dacc, gbase, lane);
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
-      const double ra = (double)racc[a];
-      const double da = (double)dacc[a];
+      const double ra = racc[a];
+      const double da = dacc[a];
 #pragma unroll
       for (int b = 0; a + b <= D; ++b) {
         const int k = pd_alpha_index(a, b);
