@@ -178,6 +178,21 @@ pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t
                           const double *const *theta /*host*/, double *const *diag_out /*host*/,
                           pd_precision prec, void *stream);
 
+/* Hessian-vector product of -Phi (eq. hess of Proposition 4.4): for each map,
+ *   hv_out[p][i*K + k] = (1 / (eps^2 n)) sum_x p_i(x) (u_i(x) - ubar(x)) psi_k(x),
+ *   u_i = v_i . psi,  ubar = sum_j p_j u_j,
+ * with p the softmax at theta (so v . Hv = (1 / (eps^2 n)) sum_x Var_p(u) >= 0,
+ * zero along the gauge direction v_i = c for all i).  The product the Newton-CG
+ * solver of pd_fit_newton_cg takes, without forming the NK x NK matrix.
+ * theta, v: host arrays of DEVICE N_p x K_p FP64 (Legendre basis); hv_out: host
+ * array of DEVICE N_p x K_p FP64, overwritten (it may not alias theta or v).
+ * PD_FP64 or PD_FP32 (exponentials and pixel sums in FP32, tile sums in FP64);
+ * PD_BF16: PD_ERR_UNSUPPORTED.  Scratch from the context workspace.
+ * Stream-ordered. */
+pd_status pd_hessian_vec(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                         const double *const *theta /*host*/, const double *const *v /*host*/,
+                         double *const *hv_out /*host*/, pd_precision prec, void *stream);
+
 /* Hard assignment F_theta (Section 2.1, smallest index on ties) in FP64 with the
  * canonical score order f = theta_i0, f = fma(theta_ik, psi_k, f), k = 1..K-1,
  * so labels are bit-reproducible.  labels_out (host array; entries may be NULL)
@@ -350,6 +365,44 @@ typedef struct {
 pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
                  double *const *theta_inout /*host*/, const pd_fit_opts *opts /*host*/,
                  pd_fit_report *reports /*host*/, void *stream);
+
+/* Inexact Newton ascent of Phi (Newton-CG) with Hessian-vector products from
+ * eq. hess of Proposition 4.4, in the gauge theta_N = 0 (on which the Hessian
+ * of -Phi is positive definite, Proposition 4.11).  Per iteration: g = grad(-Phi)
+ * with the last grain's row zeroed; conjugate gradients on H d = -g from d = 0
+ * (H v by the kernels of pd_hessian_vec, last row zeroed), stopped after cg_max
+ * steps, when ||r|| <= min(0.5, sqrt(||g||)) ||g|| (forcing term of Eisenstat
+ * and Walker), or at non-positive curvature (d = -g if at the first step); then
+ * step halving from t = 1 until -Phi(x + t d) <= -Phi(x) + 1e-4 t g.d.  A map
+ * stops at the first iterate (the start included) whose FP64 accuracy (from the
+ * certified arg-max of each evaluation) reaches target_acc, when ||g||_inf <=
+ * gtol, at max_iter iterations, or when max_halvings halvings fail.  Maps of a
+ * batch iterate independently (a stopped map's kernels are gated off).
+ * theta_inout: host array of DEVICE N_p x K_p FP64, the start (moved into the
+ * gauge) and the result.  Allocates its state (7 N K doubles per map) per call;
+ * synchronous (returns after the last phase on `stream`). */
+typedef struct {
+  pd_precision prec;      /* PD_FP64 or PD_FP32: objective and products        */
+  int32_t max_iter;       /* Newton iterations (>= 0)                           */
+  int32_t cg_max;         /* CG steps per iteration, 1 .. 10000                 */
+  int32_t max_halvings;   /* evaluations per line search, 1 .. 60               */
+  double target_acc;      /* stop at Acc >= target_acc; > 1 disables            */
+  double gtol;            /* stop at ||grad||_inf <= gtol (0: only at 0)        */
+} pd_newton_opts;
+
+typedef struct {
+  int32_t status;         /* 0 target, 1 budget, 2 gtol, 3 line search failed,
+                             4 non-finite                                       */
+  int32_t iters, evals, hvps; /* accepted iterations, objective evaluations,
+                             Hessian-vector products                           */
+  double phi, acc;        /* Phi and accuracy at the result                     */
+  double seconds_total;   /* wall time of the call                              */
+  double seconds_to_target; /* wall time until Acc >= target_acc (-1 if never)  */
+} pd_newton_report;
+
+pd_status pd_fit_newton_cg(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_probs,
+                           double *const *theta_inout /*host*/, const pd_newton_opts *opts,
+                           pd_newton_report *reports /*host*/, void *stream);
 
 /* Physical parameters of a fitted degree-1 (power) or degree-2 (anisotropic
  * power) diagram, Section 5.6.3 with eq. pd-lr-to-phys / apd-lr-to-phys of

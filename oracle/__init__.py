@@ -229,5 +229,5 @@ def gauge_project(v, mode: str):
     return v
 
 
-from .lbfgs import annealed_fit, lbfgs_fit, newton_fit  # noqa: E402,F401
+from .lbfgs import annealed_fit, lbfgs_fit, newton_cg_fit, newton_fit  # noqa: E402,F401
 from .recover import recover_params, to_monomial  # noqa: E402,F401

@@ -292,3 +292,90 @@ def annealed_fit(objective_eps, theta0, eps, *, stages, factor, stage_iters, acc
     phi = res["phi"] if levels[-1]["eps"] == eps else float(objective_eps(x, eps)[0])
     return dict(theta=x, phi=phi, acc=res["acc"], iters=iters, evals=evals,
                 status=res["status"], records=records, levels=levels)
+
+
+def newton_cg_fit(objective, hvp, theta0, *, accuracy=None, target_acc=0.99, max_iter=100,
+                  cg_max=20, gtol=0.0, c1=1e-4, max_halvings=30):
+    """Inexact Newton ascent of Phi with Hessian-vector products (eq. hess of
+    Proposition 4.4), in the gauge theta_N = 0 (on that subspace the Hessian of
+    -Phi is positive definite, Proposition 4.11).  Per iteration: g = grad(-Phi)
+    with its last row zeroed; conjugate gradients on H d = -g from d = 0, H the
+    Hessian of -Phi (hvp(theta, v) -> H v, last row zeroed), stopped after cg_max
+    steps, when ||r|| <= eta ||g|| with eta = min(0.5, sqrt(||g||)) (the forcing
+    term of Eisenstat and Walker), or at non-positive curvature (d = -g if that
+    happens at the first step); then step halving from t = 1 until
+    -Phi(x + t d) <= -Phi(x) + c1 t g.d.  Stops at the first iterate (the start
+    included) whose accuracy reaches target_acc, at max_iter iterations, when
+    ||g||_inf <= gtol, or when the halving fails.
+    Returns dict(theta, phi, acc, iters, evals, hvps, status, records)."""
+    x = np.array(theta0, np.float64)
+    x = x - x[-1]
+    evals = hvps = 0
+    records = []
+
+    def f_g(xx):
+        nonlocal evals
+        evals += 1
+        phi, g = objective(xx)
+        g = -np.asarray(g, np.float64).copy()
+        g[-1] = 0.0
+        return -phi, g
+
+    def H(v):
+        nonlocal hvps
+        hvps += 1
+        w = np.asarray(hvp(x, v), np.float64).copy()
+        w[-1] = 0.0
+        return w
+
+    f, g = f_g(x)
+    acc = accuracy(x) if accuracy is not None else None
+    status = "budget"
+    it = 0
+    while True:
+        if acc is not None and acc >= target_acc:
+            status = "target"
+            break
+        gn = math.sqrt(float(np.sum(g * g)))
+        if gn == 0.0 or float(np.max(np.abs(g))) <= gtol:
+            status = "gtol"
+            break
+        if it >= max_iter:
+            break
+        eta = min(0.5, math.sqrt(gn))
+        d = np.zeros_like(g)
+        r = -g
+        p = r.copy()
+        rr = float(np.sum(r * r))
+        for k in range(cg_max):
+            Hp = H(p)
+            pHp = float(np.sum(p * Hp))
+            if not (pHp > 0.0):
+                if k == 0:
+                    d = -g
+                break
+            alpha = rr / pHp
+            d = d + alpha * p
+            r = r - alpha * Hp
+            rr_new = float(np.sum(r * r))
+            if math.sqrt(rr_new) <= eta * gn:
+                break
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+        gd = float(np.sum(g * d))
+        t = 1.0
+        for _ in range(max_halvings):
+            fx, gx = f_g(x + t * d)
+            if fx <= f + c1 * t * gd:
+                break
+            t *= 0.5
+        else:
+            status = "linesearch"
+            break
+        x = x + t * d
+        f, g = fx, gx
+        it += 1
+        acc = accuracy(x) if accuracy is not None else None
+        records.append(dict(phi=-f, acc=acc, t=t, cg=k + 1))
+    return dict(theta=x, phi=-f, acc=acc, iters=it, evals=evals, hvps=hvps, status=status,
+                records=records)

@@ -67,6 +67,18 @@ class _FitReport(ctypes.Structure):
                 ("seconds_iterating", ctypes.c_double), ("evals_iterating", ctypes.c_int32)]
 
 
+class _NewtonOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("max_iter", ctypes.c_int32), ("cg_max", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("target_acc", ctypes.c_double),
+                ("gtol", ctypes.c_double)]
+
+
+class _NewtonReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("hvps", ctypes.c_int32), ("phi", ctypes.c_double), ("acc", ctypes.c_double),
+                ("seconds_total", ctypes.c_double), ("seconds_to_target", ctypes.c_double)]
+
+
 _lib = None
 
 # Every symbol the C ABI declares, with its ctypes signature.
@@ -113,6 +125,15 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                        ctypes.c_void_p]),
+    "pd_hessian_vec": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                      ctypes.c_void_p]),
+    "pd_fit_newton_cg": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(_NewtonOpts),
+                                        ctypes.POINTER(_NewtonReport), ctypes.c_void_p]),
     "pd_mlp_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "pd_descriptors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_void_p),
@@ -341,6 +362,32 @@ class Context:
         self._check(lib().pd_hessian_diag(self._h, arr, n, _ptrs(thetas), _ptrs(out), PREC[prec],
                                           _stream(stream)))
         return out
+
+    def hessian_vec(self, probs, thetas, vs, prec="fp64", stream=None):
+        """H v for the Hessian H of -Phi at each theta (N x K float64 per map)."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        _check_thetas(probs, vs)
+        out = [torch.empty_like(t) for t in thetas]
+        self._check(lib().pd_hessian_vec(self._h, arr, n, _ptrs(thetas), _ptrs(vs), _ptrs(out),
+                                         PREC[prec], _stream(stream)))
+        return out
+
+    def fit_newton_cg(self, probs, thetas, prec="fp64", max_iter=100, cg_max=20, max_halvings=30,
+                      target_acc=0.99, gtol=0.0, stream=None):
+        """Newton-CG ascent of Phi for every map; thetas are updated in place (and
+        moved into the gauge theta_N = 0).  Returns a list of report dicts."""
+        n = len(probs)
+        arr = (_Problem * n)(*[p.c() for p in probs])
+        _check_thetas(probs, thetas)
+        opts = _NewtonOpts(PREC[prec], max_iter, cg_max, max_halvings, target_acc, gtol)
+        reps = (_NewtonReport * n)()
+        self._check(lib().pd_fit_newton_cg(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
+                                           _stream(stream)))
+        return [dict(status=FIT_STATUS.get(r.status, r.status), iters=r.iters, evals=r.evals,
+                     hvps=r.hvps, phi=r.phi, acc=r.acc, seconds_total=r.seconds_total,
+                     seconds_to_target=r.seconds_to_target) for r in reps]
 
     def recover_params(self, theta, degree, margin=1e-3, stream=None):
         """Physical parameters of a degree-1/2 fit: (params N x 6 float64 with

@@ -583,6 +583,60 @@ pd_status pd_hessian_diag(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   return PD_OK;
 }
 
+pd_status pd_hessian_vec(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
+                         const double *const *theta, const double *const *v,
+                         double *const *hv_out, pd_precision prec, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  int code = 0;
+  if (precision_code(ctx, prec, code) != PD_OK) return PD_ERR_INVALID_ARG;
+  if (code == 2) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "pd_hessian_vec: PD_FP64 or PD_FP32");
+  if (!probs || n_probs < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n_probs >= 1 maps");
+  if (!theta || !v || !hv_out) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta, v and hv_out must be non-NULL");
+  for (int p = 0; p < n_probs; ++p) {
+    pd_status st = pd_check_problem(ctx, probs[p], p);
+    if (st != PD_OK) return st;
+    if (!theta[p] || !v[p] || !hv_out[p])
+      return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta / v / hv_out entry " + std::to_string(p) + " is NULL");
+  }
+  PD_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  EvalPlan P;
+  Arena L;
+  P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
+  pd_plan_layout(P, L, probs, n_probs, code);
+  std::vector<size_t> o_cv(n_probs), o_ub(n_probs);
+  for (int p = 0; p < n_probs; ++p) {
+    const MapDev &M = P.maps[p];
+    o_cv[p] = L.take(sizeof(double) * (size_t)M.rows * M.Npad * M.DP);
+    o_ub[p] = L.take(sizeof(double) * (size_t)M.rows * M.W);
+  }
+  const size_t o_phi = L.take(sizeof(double) * n_probs);
+  pd_status st = pd_reserve(ctx, L.off);
+  if (st != PD_OK) return st;
+  pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), hv_out, nullptr, nullptr);
+  for (int p = 0; p < n_probs; ++p) {
+    MapDev &M = P.maps[p];
+    M.hv_in = v[p];
+    M.Cv = ctx->ws + o_cv[p];
+    M.ubar = (double *)(ctx->ws + o_ub[p]);
+    M.onehot = nullptr;
+    // the reduction writes scale * sum_x p_i (u_i - ubar) psi: 1 / (eps^2 n)
+    M.grad_scale = 1.0 / (M.eps * M.eps * (double)M.H * (double)M.W);
+    M.grad_sign = 1.0;
+  }
+  PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  pd_plan_tables(P, s);
+  pd_launch_center(P.d_maps, P.n, P.max_k, s);
+  pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
+  pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+  pd_launch_hvp(P.prec, P.dmax, P.d_maps, P.d_offP, P.d_offA, P.d_offB, P.n, P.offP[P.n],
+                P.offA[P.n], P.offB[P.n], s);
+  pd_launch_reduce(P.d_maps, P.d_offR, P.n, P.offR[P.n], true, false, s);
+  PD_HIP(ctx, hipGetLastError());
+  return PD_OK;
+}
+
 pd_status pd_assign(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
                     const double *const *theta, int32_t *const *labels_out,
                     int64_t *n_correct_out, void *stream) {

@@ -134,17 +134,18 @@ __global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ 
 // i in [N, Npad) get C = (-inf, 0, ..., 0): exp2 of their logit is 0.
 // grid: blocks over the flattened (map, r, i), offsets in off (n_maps + 1).
 template <int D>
-__device__ inline void prep_one(const MapDev &M, int r, int i) {
+__device__ inline void prep_one(const MapDev &M, int r, int i, const double *src = nullptr,
+                                void *dst = nullptr, double pad0 = -INFINITY) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  double *out = (double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP;
+  double *out = (double *)(dst ? dst : M.C) + ((size_t)(r - M.row0) * M.Npad + i) * DP;
   if (i >= M.N) {
-    out[0] = -INFINITY;
+    out[0] = pad0;
 #pragma unroll
     for (int a = 1; a < DP; ++a) out[a] = 0.0;
     return;
   }
-  const double *th = M.thc + (size_t)i * K;
+  const double *th = (src ? src : M.thc) + (size_t)i * K;
   const double *ty = M.ty64 + (size_t)r * DP;
 #pragma unroll
   for (int a = 0; a <= D; ++a) {
@@ -978,6 +979,140 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce_onehot(const MapDev *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Hessian-vector product of -Phi (eq. hess of Proposition 4.4):
+//   (H v)_i = (1 / (eps^2 n)) sum_x p_i(x) (u_i(x) - ubar(x)) psi(x),
+//   u_i = v_i . psi,  ubar = sum_k p_k u_k,
+// with p from the evaluation's logits and lse (k_lse first).  Row coefficients
+// of v as for the logits (Cv[r][i][a] = sum_b v_i,(a,b) P_b(x2_r); zero rows for
+// padded grains, whose p is 0 anyway).
+__global__ __launch_bounds__(PD_BLOCK) void k_prep_v(const MapDev *__restrict__ maps,
+                                                     const int32_t *__restrict__ off, int n_maps) {
+  const int m = pd_find_map(off, n_maps, blockIdx.x);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
+  if (flat >= (long long)M.rows * M.Npad) return;
+  const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
+  PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i, M.hv_in, M.Cv, 0.0)));
+}
+
+// ubar(x) per pixel: lanes = pixels of a row segment, grains in chunks of 8.
+template <typename T, int D>
+__device__ inline void ubar_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  if (local >= M.rows * M.segs) return;
+  const int lr = local / M.segs;
+  const int c = (local - lr * M.segs) * PD_WAVE + lane;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  const auto tx = pd_glb(M.tx64 + (size_t)cc * DP);
+  double px[DP];
+#pragma unroll
+  for (int a = 0; a < DP; ++a) px[a] = tx[a];
+  const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
+  const auto Vrow = pd_uni((const double *)M.Cv + (size_t)lr * M.Npad * DP);
+  const double l = pd_glb((const double *)M.lse)[(size_t)lr * M.W + cc];
+  double acc = 0.0;
+  for (int i0 = 0; i0 < M.N; i0 += 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const auto cp = Crow + (size_t)(i0 + j) * DP;
+      const auto vp = Vrow + (size_t)(i0 + j) * DP;
+      double s = cp[0] - l, u = vp[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) {
+        s = pd_fma(cp[a], px[a], s);
+        u = pd_fma(vp[a], px[a], u);
+      }
+      const double p = (double)pd_exp2<T>((T)s);
+      acc = pd_fma(p, u, acc);
+    }
+  }
+  if (valid) pd_glb(M.ubar)[(size_t)lr * M.W + c] = acc;
+}
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_hvp_pix(const MapDev *__restrict__ maps,
+                                                      const int32_t *__restrict__ off, int n_maps,
+                                                      int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (ubar_item<T, D>(M, item - off[m], lane)));
+}
+
+// Per (pixel tile, 64 grains): sum_x p_i (u_i - ubar) psi, the gradient
+// kernel's work list, partials and super-tile sums.
+template <typename T, int D>
+__device__ inline void hvp_item(const MapDev &M, int local, int lane, double *sh) {
+  constexpr int DP = D + 1;
+  constexpr int K = (D + 1) * (D + 2) / 2;
+  const GradItem it = grad_item_of(M, local);
+  const int i = it.gbase + lane;
+  double q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q[k] = 0.0;
+  const auto txd = pd_uni((const double *)M.tx64);
+  for (int r = it.r0; r < it.r1; ++r) {
+    const size_t ro = ((size_t)(r - M.row0) * M.Npad + i) * DP;
+    const auto cp = pd_glb((const double *)M.C + ro);
+    const auto vp = pd_glb((const double *)M.Cv + ro);
+    double cf[DP], vf[DP], racc[DP];
+#pragma unroll
+    for (int a = 0; a < DP; ++a) {
+      cf[a] = cp[a];
+      vf[a] = vp[a];
+      racc[a] = 0.0;
+    }
+    const auto lrow = pd_uni((const double *)M.lse + (size_t)(r - M.row0) * M.W);
+    const auto urow = pd_uni((const double *)M.ubar + (size_t)(r - M.row0) * M.W);
+    for (int c = it.c0; c < it.c1; ++c) {
+      const auto px = txd + (size_t)c * DP;
+      double s = cf[0] - lrow[c], u = vf[0] - urow[c];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) {
+        s = pd_fma(cf[a], px[a], s);
+        u = pd_fma(vf[a], px[a], u);
+      }
+      const double w = (double)pd_exp2<T>((T)s) * u;
+      racc[0] += w;
+#pragma unroll
+      for (int a = 1; a < DP; ++a) racc[a] = pd_fma(w, px[a], racc[a]);
+    }
+    const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+      for (int b = 0; a + b <= D; ++b) {
+        const int k = pd_alpha_index(a, b);
+        q[k] = __builtin_fma(racc[a], ty[b], q[k]);
+      }
+  }
+  grad_emit<K>(M, it, q, M.part_g, sh, lane);
+}
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k_hvp(const MapDev *__restrict__ maps,
+                                                  const int32_t *__restrict__ off, int n_maps,
+                                                  int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M)) return;
+  __shared__ double sh[4 * PD_WAVE * pd_st_k<DMAX>()];
+  PD_DISPATCH_UPTO(DMAX, M.d, (hvp_item<T, D>(M, item - off[m], lane, sh)));
+  if (M.st_size == 4) grad_block_sum(M, item - off[m], M.part_g, sh, lane);
+}
+
+
+// ---------------------------------------------------------------------------
 // Design-matrix output of pd_features: out[alpha*n + j] in FP64, FP32, or two
 // bf16 planes (hi, then lo = bf16(psi - hi)), from the canonical tables.
 __device__ inline uint16_t pd_bf16_rne(float f) {
@@ -1131,4 +1266,19 @@ void pd_launch_reduce(const MapDev *maps, const int32_t *off_r, int n_maps, int 
 void pd_launch_features_out(const MapDev *maps, int prec, void *out, long long n, hipStream_t s) {
   const long long blocks = (n + PD_BLOCK - 1) / PD_BLOCK;
   k_features_out<<<(unsigned)blocks, PD_BLOCK, 0, s>>>(maps, prec, out);
+}
+void pd_launch_hvp(int prec, int dmax, const MapDev *maps, const int32_t *off_p,
+                   const int32_t *off_a, const int32_t *off_b, int n_maps, int blocks_p,
+                   int total_a, int total_b, hipStream_t s) {
+  if (blocks_p > 0) k_prep_v<<<blocks_p, PD_BLOCK, 0, s>>>(maps, off_p, n_maps);
+  const int ba = (total_a + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  const int bb = (total_b + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+  if (ba > 0) {
+    if (prec == 0) { PD_LAUNCH_BY_DMAX(k_hvp_pix, double, dmax, ba, s, maps, off_a, n_maps, total_a); }
+    else { PD_LAUNCH_BY_DMAX(k_hvp_pix, float, dmax, ba, s, maps, off_a, n_maps, total_a); }
+  }
+  if (bb > 0) {
+    if (prec == 0) { PD_LAUNCH_BY_DMAX(k_hvp, double, dmax, bb, s, maps, off_b, n_maps, total_b); }
+    else { PD_LAUNCH_BY_DMAX(k_hvp, float, dmax, bb, s, maps, off_b, n_maps, total_b); }
+  }
 }

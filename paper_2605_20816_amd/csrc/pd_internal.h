@@ -86,6 +86,11 @@ struct MapDev {
   const int32_t *want_diag;
   double *diag;                     // N x K or null
   double *part_d;                   // [stiles][Npad][K] partial sums (FP64/FP32 paths)
+  // Hessian-vector product (pd_hessian_vec): the direction v (N x K), its row
+  // coefficients Cv (as C), and the per-pixel mean ubar(x) = sum_k p_k(x) v_k . psi(x)
+  const double *hv_in;
+  void *Cv;
+  double *ubar;
 };
 
 
@@ -219,6 +224,12 @@ void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_ma
 void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                         int total, hipStream_t s);
 void pd_launch_assign_list(int dmax, const MapDev *maps, int n_maps, hipStream_t s);
+// Hessian-vector product stages (after the evaluation's tables, thc, C and lse):
+// row coefficients of v, the per-pixel means ubar, the per-tile partials of
+// sum_x p_i (u_i - ubar) psi into part_g (then the gradient reduction).
+void pd_launch_hvp(int prec, int dmax, const MapDev *maps, const int32_t *off_p,
+                   const int32_t *off_a, const int32_t *off_b, int n_maps, int blocks_p,
+                   int total_a, int total_b, hipStream_t s);
 // The certified arg-max pass alone (FP64 row coefficients from k_prep).
 void pd_launch_cert_argmax(int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                            int total, hipStream_t s);

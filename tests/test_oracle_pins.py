@@ -707,3 +707,57 @@ def test_recover_gauge_shift_keeps_the_diagram(orc):
 def test_recover_rejects_higher_degree(orc):
     with pytest.raises(ValueError):
         orc.recover_params(np.zeros((3, 10)), 3)
+
+
+# -------------------------------------------------- Newton-CG (f4) ----------
+
+def _hvp_dense(orc, lab, H, W, d, eps):
+    """H v with H the Hessian of -Phi from the dense eq. hess (itself pinned above
+    by finite differences and the variance form)."""
+    def hv(th, v):
+        N, K = th.shape
+        return (-orc.hessian(th, lab, H, W, d, eps) @ v.reshape(-1)).reshape(N, K)
+    return hv
+
+
+def test_newton_cg_reaches_the_newton_maximiser(orc):
+    """Proposition 4.11: random labels leave no exact reconstruction and a unique
+    gauge-fixed maximiser; the inexact Newton iteration with Hessian-vector
+    products reaches the point the dense damped Newton solve finds."""
+    rng = np.random.default_rng(12)
+    H, W, N, d, eps = 7, 9, 4, 2, 0.3
+    lab = synth.random_labels(H, W, N, rng)
+    K = orc.num_features(d)
+    obj = lambda th: orc.objective_grad(th, lab, H, W, d, eps)
+    ref = orc.newton_fit(np.zeros((N, K)), obj, lambda th: orc.hessian(th, lab, H, W, d, eps))
+    r = orc.newton_cg_fit(obj, _hvp_dense(orc, lab, H, W, d, eps), np.zeros((N, K)),
+                          max_iter=60, cg_max=40, gtol=1e-11)
+    assert r["status"] == "gtol"
+    assert np.max(np.abs(r["theta"] - ref)) <= 1e-8 * np.max(np.abs(ref))
+    phis = [rec["phi"] for rec in r["records"]]
+    assert all(b >= a for a, b in zip(phis, phis[1:]))
+
+
+def test_newton_cg_reaches_target_on_a_power_diagram(orc):
+    gm = synth.config_c1()
+    d, eps = 1, 1e-2
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    acc = lambda th: orc.assign(th, gm.H, gm.W, d, gm.labels)[1] / gm.labels.size
+    # H v for the 64x64 map from the variance form of eq. hess (no dense matrix)
+    X = orc.features(gm.H, gm.W, d)
+
+    def hv(th, v):
+        P = orc.softmax_probs(th, gm.H, gm.W, d, eps)
+        u = v @ X
+        ub = (P * u).sum(0)
+        return ((P * (u - ub)) @ X.T) / (eps * eps * gm.labels.size)
+
+    # the variance-form product equals the dense Hessian on a random direction
+    rng = np.random.default_rng(5)
+    th = rng.normal(size=(gm.N, 3)) * 0.05
+    v = rng.normal(size=(gm.N, 3))
+    dense = _hvp_dense(orc, gm.labels, gm.H, gm.W, d, eps)(th, v)
+    assert np.max(np.abs(hv(th, v) - dense)) <= 1e-10 * np.max(np.abs(dense))
+    r = orc.newton_cg_fit(obj, hv, np.zeros((gm.N, 3)), accuracy=acc, max_iter=200, cg_max=20)
+    assert r["status"] == "target" and r["acc"] >= 0.99
+    assert r["theta"][-1].tolist() == [0.0, 0.0, 0.0]
