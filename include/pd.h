@@ -60,9 +60,12 @@ typedef enum {
 /* Arithmetic of the logit/exp/gradient contractions.  Global reductions of Phi
  * and grad Phi are FP64 in every mode.
  *   PD_FP64: everything FP64 (the paper's precision, Section 5.1).
- *   PD_FP32: FP32 logits, FP32 exp/log-sum-exp, FP64 reductions.
- *   PD_BF16: logit and gradient contractions on BF16 matrix cores (hi/lo split
- *            operands, FP32 accumulation), FP32 log-sum-exp, FP64 reductions. */
+ *   PD_FP32: logits, running maxima and log-sum-exp formed in FP64 from FP64 row
+ *            coefficients; exponentials and per-row partial sums in FP32; FP64
+ *            reductions.
+ *   PD_BF16: logit and gradient contractions on BF16 matrix cores (three-piece
+ *            split logit operands, FP16 gradient weights, FP32 accumulation),
+ *            FP32 log-sum-exp, FP64 reductions. */
 typedef enum { PD_FP64 = 0, PD_FP32 = 1, PD_BF16 = 2 } pd_precision;
 
 /* Gauge of the fit (Lemma 4.2, Remark 4.3).  LAST_ZERO keeps theta_{N-1} = 0
@@ -147,8 +150,14 @@ pd_status pd_objective_grad_noalloc(pd_ctx *ctx, const pd_problem *probs /*host*
 /* The form pd_fit evaluates: the indicator moments m_i = sum_{x in G_i} psi(x) of
  * eq. grad are computed once per call (FP64, fixed order) and subtracted from the
  * sums of p_i psi by the FP64 reduction, instead of subtracting psi inside the
- * gradient kernel.  FP64 / FP32 only (the BF16 kernels always apply the one-hot
- * term in place; the flag is accepted and has no effect there). */
+ * gradient kernel.  In this form the grains' row coefficients are also kept in
+ * the Morton order of their centroids (maps of at most 8192 grains), and the
+ * gradient skips the rows of a tile where every term of its 64 grains lies below
+ * 2^-96 (FP64) or 2^-48 (FP32) of the pixel's largest, as the objective kernel
+ * skips such chunks in every form: a pixel loses at most N 2^-96 (N 2^-48) of its
+ * probability mass, below the rounding of its sums.  FP64 / FP32 only (the BF16
+ * kernels always apply the one-hot term in place and skip nothing; the flag is
+ * accepted and has no effect there). */
 #define PD_EVAL_ONEHOT_PRECOMPUTED 1
 
 /* Phi and grad Phi restricted to a band of pixel rows (eq. log-res and eq. grad

@@ -176,6 +176,13 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.cert = L.take(cert ? 32 : 0);  // bound (8), uncertain count (4), canonical count (8)
     R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
+    M.mask_words = (M.Npad / PD_WAVE + 31) / 32;  // far-field mask: at most 4 words
+    R.nearmask_on = !mf && !(prec == 1 && P.cert && M.d > 4) && M.mask_words <= 4;
+    R.nearmask = L.take(R.nearmask_on ? sizeof(uint32_t) * (size_t)M.rows * M.segs * M.mask_words : 0);
+    R.sorted = P.sort && M.N <= PD_ORDER_MAX;
+    R.order = L.take(R.sorted ? sizeof(int32_t) * M.N : 0);
+    R.pos = L.take(R.sorted ? sizeof(int32_t) * M.N : 0);
+    R.order_sums = L.take(R.sorted ? 3 * sizeof(int64_t) * M.N : 0);
     R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
     R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
@@ -192,6 +199,8 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.r_off = P.offR[p];
     P.max_hw = std::max(P.max_hw, std::max(M.H, M.W));
     P.max_k = std::max(P.max_k, M.K);
+    P.max_px = std::max(P.max_px, (long long)M.H * M.W);
+    P.max_n = std::max(P.max_n, M.N);
   }
   P.dmax = pd_dmax_bucket(max_d);
   P.o_maps = L.take(sizeof(MapDev) * n);
@@ -230,6 +239,12 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
       M.unc_list = nullptr;
     }
     M.onehot = P.onehot_pre && P.prec != 2 ? (double *)(base + R.onehot) : nullptr;
+    M.order = R.sorted ? (const int32_t *)(base + R.order) : nullptr;
+    M.pos = R.sorted ? (const int32_t *)(base + R.pos) : nullptr;
+    M.order_sums = R.sorted ? (void *)(base + R.order_sums) : nullptr;
+    // the far-field mask comes from the objective kernel (not from the fused
+    // certified objective of FP32 fits above degree 4, nor from the BF16 kernels)
+    M.nearmask = R.nearmask_on ? (uint32_t *)(base + R.nearmask) : nullptr;
     M.part_d = P.with_diag ? (double *)(base + R.part_d) : nullptr;
     M.diag = nullptr;
     M.want_diag = nullptr;
@@ -292,6 +307,7 @@ hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
 
 void pd_plan_tables(const EvalPlan &P, hipStream_t s) {
   pd_launch_tables(P.prec, P.d_maps, P.n, P.max_hw, s);
+  if (P.sort) pd_launch_order(P.d_maps, P.n, P.max_px, P.max_n, s);
 }
 
 void pd_plan_onehot(const EvalPlan &P, hipStream_t s) {
@@ -413,6 +429,7 @@ pd_status pd_objective_grad_impl(pd_ctx *ctx, const pd_problem *probs, int32_t n
   Arena L;
   P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   P.onehot_pre = (flags & PD_EVAL_ONEHOT_PRECOMPUTED) != 0;
+  P.sort = P.onehot_pre;
   pd_plan_layout(P, L, probs, n_probs, code, rows);
   pd_status st = pd_plan_place(ctx, P, L, mem, theta, phi_out, grad_out, s);
   if (st != PD_OK) return st;
@@ -684,6 +701,7 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   EvalPlan P;
   Arena L;
   P.onehot_pre = true;  // as in a fit
+  P.sort = true;
   P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   pd_plan_layout(P, L, probs, n_probs, code);
   const size_t o_phi = L.take(sizeof(double) * n_probs);
@@ -773,6 +791,7 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
     EvalPlan P;
     Arena L;
     P.onehot_pre = true;  // as in a fit
+  P.sort = true;
     P.target_waves = w;
     pd_plan_layout(P, L, probs, n_probs, code);
     const size_t o_phi = L.take(sizeof(double) * n_probs);

@@ -1550,6 +1550,7 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   P.target_waves = pd_tuned_waves(ctx, probs, n, eval_prec);
   P.with_diag = opts->precondition > 0;
   P.onehot_pre = true;  // indicator moments once per fit
+  P.sort = true;        // grains in spatial order for the far-field test
   P.cert = true;  // the accuracy of every evaluated point, certified
   pd_plan_layout(P, L, probs, n, eval_prec);
   const int m = opts->history;

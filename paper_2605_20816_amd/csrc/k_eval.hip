@@ -21,10 +21,16 @@
 // Kernel A (k_lse): one wave per 64-pixel row segment, lanes = pixels, loop over
 //   grains in chunks of 8 with an online max / sum of exp2 (one exp2 per pair
 //   plus one per chunk); writes lse(x) and a per-wave partial of log2 p_G.
+//   A chunk whose logits all lie PD_SKIP_F64 (FP64) or PD_SKIP_F32 (FP32) or
+//   more below the running maximum in every lane adds nothing above the rounding
+//   of the sum and is skipped after its logits; the chunks that were not skipped
+//   are recorded per 64-grain group (the far-field mask that the gradient reads).
 // Kernel B (k_grad): one wave per (pixel tile, 64 grains), lanes = grains, loop
 //   over the tile's pixels with the pixel data (P_a(x1), lse, label) as
 //   wave-uniform scalar loads; per-lane accumulators of (p - delta) P_a(x1) are
-//   folded into the K moments at the end of each row.  No cross-lane reduction
+//   folded into the K moments at the end of each row.  In the fit form a row
+//   whose segments the far-field mask marks as far for the wave's 64 grains is
+//   skipped whole.  No cross-lane reduction
 //   and no atomics: partials per tile are summed in a fixed order by k_reduce_grad,
 //   so results are bitwise reproducible.
 #include "pd_internal.h"
@@ -145,7 +151,7 @@ __device__ inline void prep_one(const MapDev &M, int r, int i, const double *src
     for (int a = 1; a < DP; ++a) out[a] = 0.0;
     return;
   }
-  const double *th = (src ? src : M.thc) + (size_t)i * K;
+  const double *th = (src ? src : M.thc) + (size_t)(M.order ? M.order[i] : i) * K;
   const double *ty = M.ty64 + (size_t)r * DP;
 #pragma unroll
   for (int a = 0; a <= D; ++a) {
@@ -271,7 +277,8 @@ __device__ inline void argmax_item(const MapDev &M, int local, int lane) {
   for (int a = 0; a < DP; ++a) px[a] = tx[a];
   const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
   const auto Cvec = pd_glb((const double *)M.C + (size_t)lr * M.Npad * DP);
-  const int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  if (M.pos && g >= 0 && g < M.N) g = pd_glb(M.pos)[g];  // the label's C row
   double bv = -INFINITY, sv = -INFINITY;
   int bi = 0;
   for (int i0 = 0; i0 < M.N; i0 += 8) {
@@ -341,7 +348,8 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
   const auto Cvec = pd_glb((const double *)M.C + (size_t)lr * M.Npad * DP);
   const int N = M.N;
-  const int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  if (M.pos && g >= 0 && g < N) g = pd_glb(M.pos)[g];  // the label's C row
   // S sums exp2(s_i - mrun) over the grains other than the pixel's label g, so
   // that r = 1 - p_g (the labelled grain's p - 1 in eq. grad, up to sign) comes
   // out as a sum of small terms instead of a difference of two numbers near 1
@@ -376,11 +384,17 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       S += (j == g) ? (T)0 : e;
     }
   }
+  // far-field mask of this row segment: one bit per 64-grain group (at most
+  // 128 groups) whose chunks were not all skipped, held by lane group % 64 in
+  // bit group / 64 (a vector register: the scalar registers hold the chunk's
+  // row coefficients)
+  unsigned nearv = (F32 && lane == 0) ? 1u : 0u;
   // grains N .. Npad-1 (read when N is not a multiple of 8) have row
   // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
   for (int i0 = F32 ? 8 : 0; i0 < N; i0 += 8) {
     T t[8];
     double cup;  // CERT: an upper bound of the chunk's largest logit, relative to mrun
+    bool far = false;  // every term of the chunk below 2^-PD_SKIP_F32 of the reference
     if constexpr (F32) {
       // FP32 exponentials: logits relative to the running reference, one
       // conversion each; the reference moves only when a lane meets a larger logit
@@ -401,6 +415,7 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       // the FP32 rounding of u widened by one unit in the last place
       cup = (double)cmu;
       cup += fabs(cup) * 0x1p-23;
+      far = __ballot(!(cmu <= (T)(-PD_SKIP_F32))) == 0;  // (a NaN is never far)
       if (__ballot(cmu > (T)0) != 0) {
         double um = u[0];
 #pragma unroll
@@ -434,6 +449,10 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       double cm = sj[0];
 #pragma unroll
       for (int j = 1; j < 8; ++j) cm = pd_max(cm, sj[j]);
+      // far field: every term of the chunk below 2^-PD_SKIP_F64 of the reference
+      // in every lane (a NaN logit is never skipped)
+      if (__ballot(!(cm <= mrun - PD_SKIP_F64)) == 0) continue;
+      if constexpr (!CERT || D <= 4) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
       const double mnew = pd_max(mrun, cm);
       S *= pd_exp2<T>(mrun - mnew);
       T e[8];
@@ -456,6 +475,9 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       bi = gt ? i0 : bi;
       bv = gt ? ca : bv;
     }
+    // far field in every lane (then the reference did not move)
+    if (far) continue;
+    if constexpr (!CERT || D <= 4) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
     if (__ballot((unsigned)(g - i0) < 8u) != 0) {
       // a label of this segment lies in the chunk: leave its term out
 #pragma unroll
@@ -491,6 +513,15 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
 
   const double tot = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
+  // (not with CERT at degree >= 5: the extra live state took that loop from 55
+  // to 120+ vector registers; such plans have no mask)
+  if ((!CERT || D <= 4) && M.nearmask != nullptr) {
+    const unsigned long long lo = __ballot(nearv & 1u), hi = __ballot(nearv & 2u);
+    if (lane < M.mask_words) {
+      const unsigned long long wv = lane < 2 ? lo : hi;
+      pd_glb(M.nearmask)[(size_t)local * M.mask_words + lane] = (unsigned)(wv >> (32 * (lane & 1)));
+    }
+  }
 }
 
 template <typename T, int DMAX>
@@ -623,6 +654,22 @@ __device__ inline void grad_block_sum(const MapDev &M, int local, double *part, 
   }
 }
 
+// Far-field mask written by the objective kernel (maps of at most 128 groups of
+// 64 grains): bit g % 32 of word
+// nearmask[((r - row0) * segs + seg) * mask_words + g / 32] is set when some
+// 8-grain chunk of the 64-grain group g was not entirely below the skip
+// threshold for the 64-pixel row segment seg of row r.  True when the group may
+// matter anywhere in columns [c0, c1) of row r (always without a mask).
+__device__ inline bool row_near(const MapDev &M, int r, int c0, int c1, int gbase) {
+  if (M.nearmask == nullptr || c0 >= c1) return true;
+  const int grp = gbase / PD_WAVE;
+  const auto w = pd_uni(M.nearmask + ((size_t)(r - M.row0) * M.segs) * M.mask_words + grp / 32);
+  const unsigned bit = 1u << (grp % 32);
+  for (int sg = c0 / PD_WAVE; sg <= (c1 - 1) / PD_WAVE; ++sg)
+    if (w[(size_t)sg * M.mask_words] & bit) return true;
+  return false;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel B: partial gradient moments per (pixel tile, 64-grain group).
 // Columns are processed 8 at a time so the wave-uniform column data (P_a(x1),
@@ -718,6 +765,8 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
   for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
   const auto txd = pd_uni((const double *)M.tx64);
   for (int r = r0; r < r1; ++r) {
+    // far field (fit form only: with HOT a labelled grain's -r weight is kept)
+    if (!HOT && !row_near(M, r, c0, c1, gbase)) continue;
     const auto cp = pd_glb((const double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
     double cf[DP];
 #pragma unroll
@@ -837,7 +886,13 @@ __device__ inline void onehot_item(const MapDev &M, int local, int lane, double 
       int off[RB];
 #pragma unroll
       for (int u = 0; u < RB; ++u)
-        off[u] = (okc && rb + u < r1) ? pd_glb(M.labels)[(size_t)(rb + u) * M.W + c] - gbase : -1;
+        off[u] = (okc && rb + u < r1) ? pd_glb(M.labels)[(size_t)(rb + u) * M.W + c] : -1;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        // labels -> the grain order of the row coefficients (fit-form plans)
+        if (M.pos && off[u] >= 0 && off[u] < M.N) off[u] = pd_glb(M.pos)[off[u]];
+        off[u] = off[u] >= 0 ? off[u] - gbase : -1;
+      }
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
         const int o = off[u];
@@ -907,7 +962,8 @@ __device__ inline void reduce_phi_block(const MapDev &M) {
 #define RG_OUT 16
 #define RG_PH 16
 __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const double *part,
-                                         const double *sub, double *dst, double scale) {
+                                         const double *sub, double *dst, double scale,
+                                         bool to_caller_order) {
   __shared__ double red[RG_PH][RG_OUT + 1];
   const int ol = threadIdx.x % RG_OUT, ph = threadIdx.x / RG_OUT;
   const int o = chunk * RG_OUT + ol;
@@ -935,7 +991,16 @@ __device__ inline void reduce_grad_block(const MapDev &M, int chunk, const doubl
     if (ph < w) red[ph][ol] += red[ph + w][ol];
     __syncthreads();
   }
-  if (ph == 0 && o < NK) dst[o] = (sub ? red[0][ol] - sub[o] : red[0][ol]) * scale;
+  if (ph == 0 && o < NK) {
+    // partials are in the order of the row coefficients; the caller's arrays in
+    // grain order
+    size_t od = o;
+    if (to_caller_order && M.order) {
+      const int i = o / M.K;
+      od = (size_t)M.order[i] * M.K + (o - i * M.K);
+    }
+    dst[od] = (sub ? red[0][ol] - sub[o] : red[0][ol]) * scale;
+  }
 }
 
 // One launch for all reductions: blocks [0, n_maps) reduce Phi of map b; the
@@ -961,10 +1026,10 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce(const MapDev *__restrict__ 
   const MapDev &M = maps[m];
   if (M.grad == nullptr || PD_GATED(M)) return;
   if (!diag) {
-    reduce_grad_block(M, b - off[m], M.part_g, M.onehot, M.grad, M.grad_scale * M.grad_sign);
+    reduce_grad_block(M, b - off[m], M.part_g, M.onehot, M.grad, M.grad_scale * M.grad_sign, true);
   } else {
     if (M.diag == nullptr || M.want_diag == nullptr || *pd_uni(M.want_diag) == 0) return;
-    reduce_grad_block(M, b - off[m], M.part_d, nullptr, M.diag, M.grad_scale / M.eps);
+    reduce_grad_block(M, b - off[m], M.part_d, nullptr, M.diag, M.grad_scale / M.eps, true);
   }
 }
 
@@ -975,7 +1040,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_reduce_onehot(const MapDev *__rest
   const int b = blockIdx.x;
   const int m = pd_find_map(off, n_maps, b);
   const MapDev &M = maps[m];
-  reduce_grad_block(M, b - off[m], M.part_g, nullptr, M.onehot, 1.0);
+  reduce_grad_block(M, b - off[m], M.part_g, nullptr, M.onehot, 1.0, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1012,19 +1077,28 @@ __device__ inline void ubar_item(const MapDev &M, int local, int lane) {
   const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
   const auto Vrow = pd_uni((const double *)M.Cv + (size_t)lr * M.Npad * DP);
   const double l = pd_glb((const double *)M.lse)[(size_t)lr * M.W + cc];
+  constexpr double SKIP = sizeof(T) == sizeof(double) ? PD_SKIP_F64 : PD_SKIP_F32;
   double acc = 0.0;
   for (int i0 = 0; i0 < M.N; i0 += 8) {
+    double sj[8];
+    bool near = false;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const auto cp = Crow + (size_t)(i0 + j) * DP;
-      const auto vp = Vrow + (size_t)(i0 + j) * DP;
-      double s = cp[0] - l, u = vp[0];
+      double s = cp[0] - l;
 #pragma unroll
-      for (int a = 1; a < DP; ++a) {
-        s = pd_fma(cp[a], px[a], s);
-        u = pd_fma(vp[a], px[a], u);
-      }
-      const double p = (double)pd_exp2<T>((T)s);
+      for (int a = 1; a < DP; ++a) s = pd_fma(cp[a], px[a], s);
+      sj[j] = s;
+      near |= !(s <= -SKIP);
+    }
+    if (__ballot(near) == 0) continue;  // far field, as in the objective
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const auto vp = Vrow + (size_t)(i0 + j) * DP;
+      double u = vp[0];
+#pragma unroll
+      for (int a = 1; a < DP; ++a) u = pd_fma(vp[a], px[a], u);
+      const double p = (double)pd_exp2<T>((T)sj[j]);
       acc = pd_fma(p, u, acc);
     }
   }
@@ -1058,6 +1132,7 @@ __device__ inline void hvp_item(const MapDev &M, int local, int lane, double *sh
   for (int k = 0; k < K; ++k) q[k] = 0.0;
   const auto txd = pd_uni((const double *)M.tx64);
   for (int r = it.r0; r < it.r1; ++r) {
+    if (!row_near(M, r, it.c0, it.c1, it.gbase)) continue;  // far field
     const size_t ro = ((size_t)(r - M.row0) * M.Npad + i) * DP;
     const auto cp = pd_glb((const double *)M.C + ro);
     const auto vp = pd_glb((const double *)M.Cv + ro);

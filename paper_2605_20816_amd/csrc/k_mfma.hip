@@ -8,7 +8,7 @@
 // products of total order <= 2 (hh, hm, mh, hl, lh, mm) are accumulated in FP32;
 // the dropped terms are below 2^-26 relative.  The gradient contraction
 // sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies values of size <= 1: p - delta
-// as one FP16 value (2^-12 relative) against the two FP16 pieces of psi, on
+// as two FP16 pieces against the two FP16 pieces of psi, on
 // v_mfma_f32_32x32x16_f16.  Log-sum-exp in FP32; Phi and grad Phi are summed in
 // FP64 in a fixed order.
 //
@@ -324,10 +324,12 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ m
 //                             = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4
 //   sL, sR, sG [32]         : lse, r = 1 - p_G and label of the tile's pixels
 // The gradient product takes the weight p (other grains) or -r (the pixel's
-// own grain: p - 1 without the cancellation near p = 1) as one FP16 value
-// (11-bit mantissa, 2^-12 relative), scaled by 2^PD_MF_WSHIFT so that small
-// weights stay normal, against the two FP16 pieces of psi; the scale is taken
-// out of the FP32 partial sums.
+// own grain: p - 1 without the cancellation near p = 1) as two FP16 pieces
+// (hi + lo, about 22 bits), scaled by 2^PD_MF_WSHIFT so that small weights stay
+// normal, against the two FP16 pieces of psi (three products: the lo x lo term is
+// below 2^-22); the scale is taken out of the FP32 partial sums.  One FP16 piece
+// (2^-12 relative per weight) put the gradient at a fitted iterate, where p - delta
+// cancels most, at the edge of a 2e-3 tolerance.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 #define PD_MF_WSHIFT 12
@@ -437,16 +439,22 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
 #pragma unroll
     for (int kb2 = 0; kb2 < 2; ++kb2) {
       const f16x8 qh = S.Q[kb2][0][lane], ql = S.Q[kb2][1][lane];
-      f16x8 x[GT];
+      f16x8 x[GT], xl[GT];
 #pragma unroll
       for (int t = 0; t < GT; ++t)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          // p - delta rounded to FP32, then to FP16 (as above, no fused form)
+          // the weight rounded to FP32, then split into two FP16 pieces (as above,
+          // no fused form)
           float q = acc[t][8 * kb2 + e];
           asm volatile("" : "+v"(q));
-          x[t][e] = (_Float16)q;
+          const _Float16 h = (_Float16)q;
+          x[t][e] = h;
+          xl[t][e] = (_Float16)(q - (float)h);
         }
+      // (w_hi + w_lo)(psi_hi + psi_lo) without w_lo psi_lo, small terms first
+#pragma unroll
+      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xl[t], qh, accg[t], 0, 0, 0);
 #pragma unroll
       for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], ql, accg[t], 0, 0, 0);
 #pragma unroll

@@ -345,6 +345,7 @@ extern "C" pd_status pd_fit_newton_cg(pd_ctx *ctx, const pd_problem *probs, int3
   PE.target_waves = PH.target_waves = pd_tuned_waves(ctx, probs, n, code);
   PE.cert = true;
   PE.onehot_pre = true;
+  PE.sort = PH.sort = true;  // no one-hot gradient in the product plan
   pd_plan_layout(PE, L, probs, n, code);
   pd_plan_layout(PH, L, probs, n, code);
   std::vector<size_t> o_cv(n), o_ub(n);

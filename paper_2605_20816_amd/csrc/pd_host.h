@@ -43,7 +43,8 @@ struct Arena {
 
 struct MapRegions {
   size_t tx64, ty64, txT, tyT, thc, C, lse, rpix, part_l, part_g, part_c, T3, lse32, part_g32, part_d,
-      onehot, cert, unc_list;
+      onehot, cert, unc_list, order, pos, order_sums, nearmask;
+  bool sorted, nearmask_on;
 };
 
 // Everything one batched evaluation / assignment needs, laid out in an arena.
@@ -58,6 +59,12 @@ struct EvalPlan {
   // arg-max (per-wave counts in part_c, the canonical pass for the rest); the
   // caller clears the cert slots between evaluations (set before layout)
   bool cert = false;
+  // row coefficients in the spatial order of the grains (k_order.hip), for the
+  // far-field test; requires the one-hot term precomputed wherever a gradient is
+  // taken (set before layout)
+  bool sort = false;
+  long long max_px = 0;
+  int max_n = 0;
   int target_waves = 8192;
   std::vector<MapDev> maps;
   std::vector<MapRegions> reg;

@@ -18,6 +18,15 @@
 
 // log2(e) and ln(2) as the nearest doubles.
 #define PD_LOG2E 1.4426950408889634074
+// Far-field threshold (base-2 logit below the reference): terms 2^s with
+// s <= -PD_SKIP_F64 (FP64) or -PD_SKIP_F32 (FP32 exponentials) are left out of
+// the sums when a whole chunk of a wave is below it.  A pixel then loses at most
+// N 2^-96 (FP64) or N 2^-48 (FP32) of probability mass, below the rounding of
+// its sums for any grain count this library takes.
+#define PD_SKIP_F64 96.0
+// Largest grain count whose spatial order is computed (one block's LDS sort).
+#define PD_ORDER_MAX 8192
+#define PD_SKIP_F32 48.0
 #define PD_LN2 0.69314718055994530942
 
 struct MapDev {
@@ -91,6 +100,15 @@ struct MapDev {
   const double *hv_in;
   void *Cv;
   double *ubar;
+  // spatial grain order of the row coefficients (fit-form plans; null = identity):
+  // C row j holds grain order[j]; pos is the inverse (labels -> C rows)
+  const int32_t *order;
+  const int32_t *pos;
+  void *order_sums;                 // [3][N] int64 column, row and pixel sums per grain
+  // far-field mask of the objective kernel (FP64/FP32 plans): per row segment,
+  // mask_words words of one bit per 64-grain group (see row_near)
+  uint32_t *nearmask;
+  int32_t mask_words;
 };
 
 
@@ -224,6 +242,10 @@ void pd_launch_assign(int dmax, const MapDev *maps, const int32_t *off, int n_ma
 void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                         int total, hipStream_t s);
 void pd_launch_assign_list(int dmax, const MapDev *maps, int n_maps, hipStream_t s);
+// Spatial grain order of maps with non-null order (fit-form plans): per-grain
+// centroid sums, then the Morton-order sort (max_px, max_n: the batch's largest
+// pixel and grain counts).
+void pd_launch_order(const MapDev *maps, int n_maps, long long max_px, int max_n, hipStream_t s);
 // Hessian-vector product stages (after the evaluation's tables, thc, C and lse):
 // row coefficients of v, the per-pixel means ubar, the per-tile partials of
 // sum_x p_i (u_i - ubar) psi into part_g (then the gradient reduction).
