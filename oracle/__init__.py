@@ -231,3 +231,4 @@ def gauge_project(v, mode: str):
 
 from .lbfgs import annealed_fit, lbfgs_fit, newton_cg_fit, newton_fit  # noqa: E402,F401
 from .recover import recover_params, to_monomial  # noqa: E402,F401
+from . import points  # noqa: E402,F401
