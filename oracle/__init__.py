@@ -57,6 +57,12 @@ def _load():
     L.orc_coord.restype = c_dbl
     L.orc_legendre.argtypes = [c_dbl, c_int, _f64p]
     L.orc_features.argtypes = [c_int, c_int, c_int, _f64p]
+    L.orc_points_num_features.argtypes = [c_int, c_int]
+    L.orc_points_num_features.restype = c_int
+    L.orc_points_features.argtypes = [c_i64, c_int, c_int, _f64p, _f64p]
+    L.orc_points_assign.argtypes = [c_i64, c_int, c_int, c_int, _f64p, _f64p, ctypes.c_void_p,
+                                    _i32p, ctypes.POINTER(c_i64)]
+    L.orc_points_assign.restype = c_i64
     L.orc_assign.argtypes = [c_int, c_int, c_int, c_int, _f64p, ctypes.c_void_p,
                              _i32p, ctypes.POINTER(c_i64)]
     L.orc_assign.restype = c_i64

@@ -322,3 +322,90 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------
+   Unstructured point sets in D = 2 or 3 dimensions (Section 2.1 with Omega any
+   finite set of points of [-1,1]^D; Section 3.3's tensor-product basis).
+   Multi-indices, degree-graded: for k = 0..d, in 2-D (k - b, b) for b = 0..k
+   (the grid's order), in 3-D (k - b - c, b, c) for c = 0..k, then b = 0..k - c. */
+int orc_points_num_features(int D, int d) {
+  return D == 2 ? (d + 1) * (d + 2) / 2 : (d + 1) * (d + 2) * (d + 3) / 6;
+}
+
+static int points_multi_index(int D, int d, int *A, int *B, int *C) {
+  int idx = 0;
+  for (int k = 0; k <= d; ++k) {
+    if (D == 2) {
+      for (int b = 0; b <= k; ++b) {
+        A[idx] = k - b;
+        B[idx] = b;
+        C[idx] = 0;
+        ++idx;
+      }
+    } else {
+      for (int c = 0; c <= k; ++c)
+        for (int b = 0; b <= k - c; ++b) {
+          A[idx] = k - b - c;
+          B[idx] = b;
+          C[idx] = c;
+          ++idx;
+        }
+    }
+  }
+  return idx;
+}
+
+/* psi(x_j) of every point: out[k*n + j] = (P_a(x_j1) P_b(x_j2)) P_c(x_j3)
+   (the last factor only in 3-D), the 1-D values from orc_legendre. */
+void orc_points_features(int64_t n, int D, int d, const double *X, double *out) {
+  int A[256], B[256], C[256];
+  int K = points_multi_index(D, d, A, B, C);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j) {
+    double P[3][16];
+    for (int q = 0; q < D; ++q) orc_legendre(X[j * D + q], d, P[q]);
+    for (int k = 0; k < K; ++k) {
+      double v = P[0][A[k]] * P[1][B[k]];
+      if (D == 3) v = v * P[2][C[k]];
+      out[(size_t)k * n + j] = v;
+    }
+  }
+}
+
+/* F_theta on a point set (smallest index on ties, -1 on a NaN score) with the
+   scores in the canonical order of score(); returns the NaN count and writes
+   the number of points with F = G to *n_correct (labels may be NULL). */
+int64_t orc_points_assign(int64_t n, int D, int N, int d, const double *theta,
+                          const double *X, const int32_t *labels, int32_t *out,
+                          int64_t *n_correct) {
+  int A[256], B[256], C[256];
+  int K = points_multi_index(D, d, A, B, C);
+  int64_t correct = 0, nan_count = 0;
+#pragma omp parallel for schedule(static) reduction(+ : correct, nan_count)
+  for (int64_t j = 0; j < n; ++j) {
+    double P[3][16], psi[256];
+    for (int q = 0; q < D; ++q) orc_legendre(X[j * D + q], d, P[q]);
+    for (int k = 0; k < K; ++k) {
+      double v = P[0][A[k]] * P[1][B[k]];
+      if (D == 3) v = v * P[2][C[k]];
+      psi[k] = v;
+    }
+    int best = 0;
+    double fbest = score(theta, psi, K);
+    int bad = isnan(fbest);
+    for (int i = 1; i < N; ++i) {
+      double f = score(theta + (size_t)i * K, psi, K);
+      if (isnan(f)) bad = 1;
+      if (f < fbest) {
+        fbest = f;
+        best = i;
+      }
+    }
+    int lab = bad ? -1 : best;
+    if (out) out[j] = lab;
+    if (bad) nan_count++;
+    if (labels && lab == labels[j]) correct++;
+  }
+  if (n_correct) *n_correct = correct;
+  return nan_count;
+}

@@ -57,7 +57,22 @@ def legendre_all(t: np.ndarray, d: int) -> np.ndarray:
 
 
 def features(X: np.ndarray, d: int) -> np.ndarray:
-    """psi(x) of every point (K x n)."""
+    """psi(x) of every point (K x n), from the C oracle's 1-D recurrence (the grid
+    oracle's, so pixel centres give the grid's design matrix bit for bit):
+    psi = (P_a(x1) P_b(x2)) P_c(x3)."""
+    from . import _load
+    X = np.ascontiguousarray(X, np.float64)
+    n, D = X.shape
+    if D not in (2, 3):
+        raise ValueError("dimension 2 or 3")
+    out = np.zeros((num_features(D, d), n))
+    _load().orc_points_features(int(n), int(D), int(d), X, out)
+    return out
+
+
+def features_numpy(X: np.ndarray, d: int) -> np.ndarray:
+    """The same products from legendre_all (Bonnet's recurrence without a fused
+    multiply-add): equal to features() to rounding."""
     X = np.asarray(X, np.float64)
     n, D = X.shape
     mi = multi_index(D, d)
@@ -87,8 +102,17 @@ def objective_grad(theta, X, labels, d: int, eps: float, grad: bool = True):
 
 
 def assign(theta, X, d: int, labels=None):
-    """F (smallest index on ties) and the number of points with F = G."""
-    h = np.asarray(theta, np.float64) @ features(X, d)
-    F = np.argmin(h, axis=0).astype(np.int32)
-    nc = int(np.sum(F == np.asarray(labels))) if labels is not None else 0
-    return F, nc
+    """F (smallest index on ties; scores theta_i0 then one FMA per feature, in
+    index order) and the number of points with F = G."""
+    import ctypes
+    from . import _load
+    X = np.ascontiguousarray(X, np.float64)
+    n, D = X.shape
+    th = np.ascontiguousarray(theta, np.float64)
+    F = np.zeros(n, np.int32)
+    nc = ctypes.c_int64(0)
+    lab = np.ascontiguousarray(labels, np.int32) if labels is not None else None
+    _load().orc_points_assign(int(n), int(D), int(th.shape[0]), int(d), th, X,
+                              lab.ctypes.data if lab is not None else None, F,
+                              ctypes.byref(nc))
+    return F, int(nc.value)

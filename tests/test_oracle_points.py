@@ -26,6 +26,11 @@ def test_legendre_closed_forms_and_orthogonality(orc):
     Q = orc.points.legendre_all(x, 6)
     G = (Q * w) @ Q.T
     assert np.allclose(G, np.diag(2.0 / (2 * np.arange(7) + 1)), atol=1e-14)
+    # the C oracle's features (fused recurrence) and numpy's agree to rounding
+    rng = np.random.default_rng(1)
+    X = rng.uniform(-1, 1, size=(500, 3))
+    A, B = orc.points.features(X, 6), orc.points.features_numpy(X, 6)
+    assert np.max(np.abs(A - B)) <= 1e-14
 
 
 def test_pixel_centres_reproduce_the_grid_oracle(orc):
