@@ -202,6 +202,56 @@ pd_status pd_hessian_vec(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t 
                          const double *const *theta /*host*/, const double *const *v /*host*/,
                          double *const *hv_out /*host*/, pd_precision prec, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Unstructured point sets in 2-D and 3-D.  Section 2.1 takes the domain as any
+ * finite set of points (nothing in the method needs a grid or two dimensions);
+ * the basis is Section 3.3's tensor product in D dimensions,
+ *   psi_alpha(x) = P_{alpha_1}(x_1) P_{alpha_2}(x_2) [P_{alpha_3}(x_3)], |alpha| <= d,
+ * formed as (P_a(x1) P_b(x2)) P_c(x3) from the three-term recurrence with one
+ * fused multiply-add per step.  Multi-indices in the degree-graded order: in 2-D
+ * (k - b, b) for b = 0..k (the grid's order), in 3-D (k - b - c, b, c) for
+ * c = 0..k, then b = 0..k - c; K = (d+1)(d+2)/2 or (d+1)(d+2)(d+3)/6.
+ * Without a grid the logit costs K FMAs per (point, grain). */
+#define PD_POINTS_DMAX2 7
+#define PD_POINTS_DMAX3 4
+#define PD_POINTS_KMAX 36
+typedef struct {
+  const double *coords;   /* DEVICE n_points x dim FP64, row-major, in [-1, 1]^dim */
+  const int32_t *labels;  /* DEVICE n_points, values in [0, n_grains)             */
+  int64_t n_points;       /* >= 1                                                 */
+  int32_t dim;            /* 2 or 3                                               */
+  int32_t n_grains;       /* >= 2                                                 */
+  int32_t degree;         /* 2-D: 0..PD_POINTS_DMAX2; 3-D: 0..PD_POINTS_DMAX3     */
+  double eps;             /* > 0                                                  */
+} pd_points;
+
+/* K of a point set of this dimension and degree (0 for an invalid dimension). */
+int32_t pd_points_num_features(int32_t dim, int32_t degree);
+
+/* Phi (eq. log-res) and grad Phi (eq. grad) of each point set, the definitions of
+ * pd_objective_grad with the sum over the points: phi_out DEVICE double[n_probs];
+ * grad_out host array of DEVICE N x K FP64 (the array or an entry may be NULL:
+ * Phi only); theta host array of DEVICE N x K FP64.  PD_FP64 (everything FP64) or
+ * PD_FP32 (logits and log-sum-exp FP64, exponentials and per-point sums FP32);
+ * PD_BF16: PD_ERR_UNSUPPORTED.  A grain whose logit lies 96 (FP64) or 48 (FP32)
+ * base-2 units below the running maximum of every point of a 64-point wave is
+ * left out of that wave's sums (at most N 2^-96 / N 2^-48 of a point's mass).
+ * Labels are a precondition (not checked).  Scratch from the context workspace
+ * (n K + 3 n + chunks N_pad K doubles).  Stream-ordered. */
+pd_status pd_points_objective_grad(pd_ctx *ctx, const pd_points *probs /*host*/, int32_t n_probs,
+                                   const double *const *theta /*host*/, double *phi_out,
+                                   double *const *grad_out /*host*/, pd_precision prec,
+                                   void *stream);
+
+/* F_theta of each point set (Section 2.1, smallest index on ties, -1 where a
+ * score is NaN) with the scores theta_i0 then one FMA per feature in index
+ * order, in FP64: labels_out host array of DEVICE int32[n_points] (the array or
+ * an entry may be NULL); n_correct_out DEVICE int64[n_probs]: #{x : F(x) = G(x)}.
+ * Stream-ordered. */
+pd_status pd_points_assign(pd_ctx *ctx, const pd_points *probs /*host*/, int32_t n_probs,
+                           const double *const *theta /*host*/, int32_t *const *labels_out /*host*/,
+                           int64_t *n_correct_out, void *stream);
+
 /* Hard assignment F_theta (Section 2.1, smallest index on ties) in FP64 with the
  * canonical score order f = theta_i0, f = fma(theta_ik, psi_k, f), k = 1..K-1,
  * so labels are bit-reproducible.  labels_out (host array; entries may be NULL)

@@ -47,6 +47,12 @@ class _Problem(ctypes.Structure):
                 ("degree", ctypes.c_int32), ("eps", ctypes.c_double)]
 
 
+class _Points(ctypes.Structure):
+    _fields_ = [("coords", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("n_grains", ctypes.c_int32), ("degree", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
 class _FitOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("gauge", ctypes.c_int), ("init", ctypes.c_int),
                 ("history", ctypes.c_int32), ("max_iter", ctypes.c_int32),
@@ -134,6 +140,15 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_void_p),
                                         ctypes.POINTER(_NewtonOpts),
                                         ctypes.POINTER(_NewtonReport), ctypes.c_void_p]),
+    "pd_points_num_features": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
+    "pd_points_objective_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Points), ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                                ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                                ctypes.c_void_p]),
+    "pd_points_assign": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Points), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "pd_mlp_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "pd_descriptors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_void_p),
@@ -231,6 +246,40 @@ class Problem:
         if lab.numel() != self.H * self.W:
             raise ValueError("labels must have H*W entries")
         return _Problem(self.H, self.W, lab.data_ptr(), self.N, self.d, float(self.eps))
+
+
+@dataclass
+class Points:
+    """An unstructured point set on the device: coords float64 (n, dim) in
+    [-1, 1]^dim (dim 2 or 3), labels int32 (n,) values in [0, N)."""
+    coords: torch.Tensor
+    labels: torch.Tensor
+    N: int
+    d: int
+    eps: float
+
+    @property
+    def dim(self) -> int:
+        return int(self.coords.shape[1])
+
+    @property
+    def n(self) -> int:
+        return int(self.coords.shape[0])
+
+    def c(self) -> _Points:
+        X, lab = self.coords, self.labels
+        if not (X.is_cuda and X.dtype == torch.float64 and X.is_contiguous() and X.dim() == 2):
+            raise ValueError("coords must be a contiguous float64 CUDA tensor (n, dim)")
+        if not (lab.is_cuda and lab.dtype == torch.int32 and lab.is_contiguous()):
+            raise ValueError("labels must be a contiguous int32 CUDA tensor")
+        if lab.numel() != X.shape[0]:
+            raise ValueError("one label per point")
+        return _Points(X.data_ptr(), lab.data_ptr(), X.shape[0], X.shape[1], self.N, self.d,
+                       float(self.eps))
+
+
+def points_num_features(dim: int, degree: int) -> int:
+    return int(lib().pd_points_num_features(dim, degree))
 
 
 def _check_thetas(probs, thetas):
@@ -416,6 +465,39 @@ class Context:
             lp = _ptrs(outs)
         self._check(lib().pd_assign(self._h, arr, n, _ptrs(thetas), lp,
                                     ctypes.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return outs, cnt
+
+    # ------------------------------------------------------------ point sets
+    def points_objective_grad(self, sets, thetas, prec="fp64", grad=True, stream=None):
+        """Phi and grad Phi of each point set.  Returns (phi float64 (n,), [grads] or None)."""
+        n = len(sets)
+        arr = (_Points * n)(*[q.c() for q in sets])
+        if len(thetas) != n:
+            raise ValueError("one theta per point set")
+        for q, t in zip(sets, thetas):
+            K = points_num_features(q.dim, q.d)
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("theta must be a contiguous float64 CUDA tensor")
+            if K and tuple(t.shape) != (q.N, K):
+                raise ValueError(f"theta must have shape (N, K) = ({q.N}, {K})")
+        dev = thetas[0].device
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        grads = [torch.empty_like(t) for t in thetas] if grad else None
+        self._check(lib().pd_points_objective_grad(self._h, arr, n, _ptrs(thetas),
+                                                   ctypes.c_void_p(phi.data_ptr()),
+                                                   _ptrs(grads) if grad else None, PREC[prec],
+                                                   _stream(stream)))
+        return phi, grads
+
+    def points_assign(self, sets, thetas, stream=None):
+        """F_theta of each point set and #correct: ([labels int32 (n,)], counts int64)."""
+        n = len(sets)
+        arr = (_Points * n)(*[q.c() for q in sets])
+        dev = thetas[0].device
+        cnt = torch.empty(n, dtype=torch.int64, device=dev)
+        outs = [torch.empty(q.n, dtype=torch.int32, device=dev) for q in sets]
+        self._check(lib().pd_points_assign(self._h, arr, n, _ptrs(thetas), _ptrs(outs),
+                                           ctypes.c_void_p(cnt.data_ptr()), _stream(stream)))
         return outs, cnt
 
     def profile_eval(self, probs, thetas, prec="fp64", reps=10, stream=None):

@@ -6,3 +6,4 @@ definitions of the diagrams it samples; it holds none of the objective, gradient
 or assignment arithmetic that is being tested.
 """
 from .maps import *  # noqa: F401,F403
+from .points import power_points  # noqa: F401
