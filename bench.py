@@ -203,6 +203,35 @@ def c5_equal_accuracy(pdl, ctx, prob, torch, synth, plain_iters, with_net):
     return out
 
 
+def points_throughput(pdl, ctx, torch, synth, n=262144, N=2000, d=4):
+    """Unstructured 3-D points (uniform in [-1, 1]^3, labelled by a random power
+    diagram of N sites), degree d (K = 35 at d = 4): one call of
+    pd_points_objective_grad (features, objective, gradient, reductions), timed
+    over 5 calls after one warm-up, FP64 and FP32.  Algorithmic flops per pair as
+    for the grid with K-FMA logits: objective 2K + 4, gradient 4K + 3."""
+    rng = np.random.default_rng(2025)
+    X, lab, Nn = synth.power_points(n, 3, N, rng)
+    K = pdl.points_num_features(3, d)
+    th = torch.as_tensor(rng.normal(size=(Nn, K)) * 0.05 / np.sqrt(K)).cuda()
+    q = pdl.Points(torch.as_tensor(X).cuda(), torch.as_tensor(lab).cuda(), Nn, d, 1e-2)
+    pairs = n * Nn
+    out = {"workload": f"{n} points in [-1,1]^3, {Nn} grains (random power diagram), d={d} (K={K}), "
+                       "eps=1e-2", "pairs": pairs}
+    for prec in ("fp64", "fp32"):
+        ctx.points_objective_grad([q], [th], prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.points_objective_grad([q], [th], prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        fl = (2 * K + 4 + 4 * K + 3) * pairs
+        out[prec] = {"ms_per_evaluation": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                     "tflops": fl / (ms * 1e-3) / 1e12,
+                     "frac": fl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec]}
+    return out
+
+
 def roofline_at_scale(pdl, ctx, torch, synth, n_maps=16):
     """The evaluation kernels at scale: the c4-style batch (about 6e8 pairs per
     evaluation) at theta = 0, FP32, with its autotuned tiles; flops per pair as in
@@ -317,6 +346,8 @@ def main():
     ap.add_argument("--c5-plain-iters", type=int, default=100,
                     help="iterations of the plain FP64 c5 fit that set the accuracy of the "
                          "equal-accuracy comparison (0 skips it)")
+    ap.add_argument("--points", type=int, default=1,
+                    help="also time the unstructured 3-D point-set path (0 skips it)")
     ap.add_argument("--no-net", action="store_true",
                     help="skip the learned warm start in the time-to-99%% comparison")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -407,6 +438,7 @@ def main():
     at_scale = roofline_at_scale(pdl, ctx, torch, synth) if args.t99_maps else None
     c5eq = (c5_equal_accuracy(pdl, ctx, prob, torch, synth, args.c5_plain_iters, not args.no_net)
             if args.c5_plain_iters else None)
+    pts = points_throughput(pdl, ctx, torch, synth) if args.points else None
 
     cpu = None
     if not args.no_cpu:
@@ -460,6 +492,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_99": t99,
         "c5_equal_accuracy": c5eq,
+        "points_3d": pts,
     }
     print(json.dumps(out))
 

@@ -1,6 +1,7 @@
 """Seeded unstructured point sets in 2-D and 3-D labelled by a random power
-diagram (nearest site in the power distance |x - y_i|^2 - w_i, first index on
-ties).  Input generation only: nothing of the method is computed here."""
+diagram (nearest site in the power distance |x - y_i|^2 - w_i, evaluated as
+(|y_i|^2 - w_i) - 2 x.y_i, first index on ties).  Input generation only: nothing
+of the method is computed here."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,10 +15,10 @@ def power_points(n: int, D: int, N: int, rng, wmax: float = 0.02):
     y = rng.uniform(-1.0, 1.0, size=(N, D))
     w = rng.uniform(0.0, wmax, size=N)
     lab = np.empty(n, np.int64)
-    for s in range(0, n, 65536):
-        xb = X[s:s + 65536]
-        d2 = ((xb[:, None, :] - y[None, :, :]) ** 2).sum(-1) - w[None, :]
-        lab[s:s + 65536] = np.argmin(d2, axis=1)
+    c = (y * y).sum(1) - w  # |x - y|^2 - w = |x|^2 - 2 x.y + (|y|^2 - w)
+    for s in range(0, n, 16384):
+        xb = X[s:s + 16384]
+        lab[s:s + 16384] = np.argmin(c[None, :] - 2.0 * (xb @ y.T), axis=1)
     keep = np.unique(lab)
     remap = np.full(N, -1, np.int64)
     remap[keep] = np.arange(keep.size)
