@@ -529,6 +529,14 @@ pd_status pd_autotune(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t n_p
  * PD_ERR_INVALID_ARG for another kind. */
 pd_status pd_probe_peak(pd_ctx *ctx, int32_t kind, double *rate_out /*host*/, void *stream);
 
+/* The elementary functions of the evaluation kernels on given arguments (a check
+ * of their accuracy): out[j] = f(in[j]) for fn 0: the FP64 2^x (arguments <= 0,
+ * as the kernels form them), 1: the FP32 2^x of (float)x, 2: the FP64 log2,
+ * 3: the FP32 log2 of (float)x; FP32 results widened to FP64.  in, out: DEVICE
+ * double[n].  Stream-ordered. */
+pd_status pd_probe_math(pd_ctx *ctx, int32_t fn, const double *in, double *out, int64_t n,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -149,6 +149,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_void_p),
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "pd_probe_math": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "pd_mlp_num_params": (ctypes.c_int64, [ctypes.c_int32]),
     "pd_descriptors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_void_p),
@@ -466,6 +468,17 @@ class Context:
         self._check(lib().pd_assign(self._h, arr, n, _ptrs(thetas), lp,
                                     ctypes.c_void_p(cnt.data_ptr()), _stream(stream)))
         return outs, cnt
+
+    def probe_math(self, fn, x, stream=None):
+        """The kernels' exp2/log2 on a float64 CUDA tensor x: fn 'exp2_f64' (x <= 0),
+        'exp2_f32', 'log2_f64' or 'log2_f32'.  Returns a float64 tensor."""
+        code = {"exp2_f64": 0, "exp2_f32": 1, "log2_f64": 2, "log2_f32": 3}[fn]
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous float64 CUDA tensor")
+        out = torch.empty_like(x)
+        self._check(lib().pd_probe_math(self._h, code, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), x.numel(), _stream(stream)))
+        return out
 
     # ------------------------------------------------------------ point sets
     def points_objective_grad(self, sets, thetas, prec="fp64", grad=True, stream=None):

@@ -269,7 +269,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_cert_argmax(const MapDev *__restri
                                                           int n_maps, int total) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
-  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  const int item = pd_xcd_block(blockIdx.x, gridDim.x) * PD_WAVES_PER_BLOCK + wave;
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse(const MapDev *__restrict__ map
                                                   int total) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
-  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  const int item = pd_xcd_block(blockIdx.x, gridDim.x) * PD_WAVES_PER_BLOCK + wave;
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_lse_cert(const MapDev *__restrict_
                                                        int total) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
-  const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
+  const int item = pd_xcd_block(blockIdx.x, gridDim.x) * PD_WAVES_PER_BLOCK + wave;
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);
   const MapDev &M = maps[m];
@@ -774,6 +774,9 @@ __global__ __launch_bounds__(PD_BLOCK) void k_grad(const MapDev *__restrict__ ma
                                                    int total) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
+  // (hardware block order: the XCD-aware order of the objective kernels made this
+  // kernel 20% slower, its many waves on one tile's column data contending for
+  // one L2)
   const int item = blockIdx.x * PD_WAVES_PER_BLOCK + wave;
   if (item >= total) return;
   const int m = pd_find_map(off, n_maps, item);

@@ -129,3 +129,40 @@ extern "C" pd_status pd_probe_peak(pd_ctx *ctx, int32_t kind, double *rate_out, 
   *rate_out = ops / (best * 1e-3);
   return PD_OK;
 }
+
+// ---------------------------------------------------------------------------
+// The evaluation kernels' exponentials and logarithms on given arguments, so
+// their accuracy can be checked against a reference library on the host.
+#include "pd_math.h"
+
+__global__ __launch_bounds__(PK_THREADS) void k_probe_math(int fn, const double *__restrict__ in,
+                                                          double *__restrict__ out, long long n) {
+  const long long j = (long long)blockIdx.x * PK_THREADS + threadIdx.x;
+  if (j >= n) return;
+  const double x = in[j];
+  double y;
+  switch (fn) {
+    case 0: y = pd_exp2<double>(x); break;
+    case 1: y = (double)pd_exp2<float>((float)x); break;
+    case 2: y = pd_log2<double>(x); break;
+    default: y = (double)pd_log2<float>((float)x); break;
+  }
+  out[j] = y;
+}
+
+extern "C" pd_status pd_probe_math(pd_ctx *ctx, int32_t fn, const double *in, double *out,
+                                   int64_t n, void *stream) {
+  if (!ctx) return PD_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (fn < 0 || fn > 3) return pd_fail(ctx, PD_ERR_INVALID_ARG, "fn must be 0..3");
+  if (n < 0 || (n > 0 && (!in || !out))) return pd_fail(ctx, PD_ERR_INVALID_ARG, "need n >= 0 and device in/out");
+  if (n == 0) return PD_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) {
+    const unsigned blocks = (unsigned)((n + PK_THREADS - 1) / PK_THREADS);
+    k_probe_math<<<blocks, PK_THREADS, 0, (hipStream_t)stream>>>(fn, in, out, n);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return pd_fail(ctx, PD_ERR_HIP, std::string("k_probe_math: ") + hipGetErrorString(e));
+  return PD_OK;
+}

@@ -146,6 +146,18 @@ inline int pd_dmax_bucket(int max_degree) {
   return max_degree <= 2 ? 2 : max_degree <= 4 ? 4 : max_degree <= 6 ? 6 : 8;
 }
 
+// XCD-aware block order.  The hardware hands block b of a launch to XCD b % 8
+// (each XCD has its own L2); renumbering so that XCD x runs a contiguous range of
+// logical blocks keeps neighbouring work items -- the row segments of one pixel
+// row, the grain groups of one pixel tile -- on one L2, which then fetches their
+// shared data (row coefficients, column data) once instead of once per XCD.
+// A bijection of [0, nb).
+__device__ inline int pd_xcd_block(int b, int nb) {
+  const int per = nb / 8, rem = nb % 8;
+  const int x = b % 8, k = b / 8;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // Wave-uniform map lookup: largest m with off[m] <= item (off has n+1 entries).
 __device__ inline int pd_find_map(const int32_t *__restrict__ off, int n, int item) {
   int lo = 0, hi = n - 1;
