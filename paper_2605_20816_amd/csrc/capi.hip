@@ -72,13 +72,14 @@ pd_status pd_reserve(pd_ctx *ctx, size_t bytes) {
 }
 
 // Tile of the gradient kernel: about `target_waves` waves per map, each over at
-// least 64 pixels, tiles at most 256 columns wide (the per-row fold into the K
-// moments is amortised over the tile width).
+// least 64 pixels, as wide as the map allows (the per-row fold into the K
+// moments is amortised over the tile width, and each tile reads its rows' row
+// coefficients once: tiles narrower than the map read them once per column tile).
 static void choose_tiles(int H, int W, int Npad, int target_waves, int &tr, int &tc) {
   const long long groups = Npad / PD_WAVE;
   long long px = (long long)H * W * groups / target_waves;
   if (px < 64) px = 64;
-  tc = (int)std::min<long long>(std::min(W, 256), px);
+  tc = (int)std::min<long long>(std::min(W, 64 * PD_WAVE), px);  // at most 64 segments
   long long rows = px / tc;
   if (rows > H) rows = H;
   if (rows < 1) rows = 1;  // also for an empty row range (no tiles then)

@@ -729,8 +729,20 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
   for (int k = 0; k < (DIAG ? K : 1); ++k) qd[k] = 0.0;
   const auto txd = pd_uni((const double *)M.tx64);
   for (int r = r0; r < r1; ++r) {
-    // far field (fit form only: with HOT a labelled grain's -r weight is kept)
-    if (!HOT && !row_near(M, r, c0, c1, gbase)) continue;
+    // far field (fit form only: with HOT a labelled grain's -r weight is kept):
+    // one bit per 64-pixel segment of the tile row that some chunk of this grain
+    // group reached (tiles are at most 64 segments wide)
+    unsigned long long segbits = ~0ull;
+    if (!HOT && M.nearmask != nullptr) {
+      const int grp = gbase / PD_WAVE;
+      const auto mrow = pd_uni(M.nearmask + ((size_t)(r - M.row0) * M.segs) * M.mask_words + grp / 32);
+      const unsigned mbit = 1u << (grp % 32);
+      segbits = 0ull;
+      const int s0 = c0 / PD_WAVE, s1 = (c1 - 1) / PD_WAVE;
+      for (int sg = s0; sg <= s1; ++sg)
+        segbits |= (mrow[(size_t)sg * M.mask_words] & mbit) ? (1ull << (sg - s0)) : 0ull;
+      if (segbits == 0ull) continue;
+    }
     const auto cp = pd_glb((const double *)M.C + ((size_t)(r - M.row0) * M.Npad + i) * DP);
     double cf[DP];
 #pragma unroll
@@ -741,13 +753,19 @@ __device__ inline void grad_item(const MapDev &M, int local, int lane, double *s
     const auto lrow = pd_uni((const double *)M.lse + (size_t)(r - M.row0) * M.W);
     const auto rrow = pd_uni((const T *)M.rpix + (size_t)(r - M.row0) * M.W);
     const auto grow = pd_uni(M.labels + (size_t)r * M.W);
-    int c = c0;
-    for (; c + CH <= c1; c += CH)
-      grad_cols<T, D, CH, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf, racc,
-                                     dacc, gbase, lane);
-    for (; c < c1; ++c)
-      grad_cols<T, D, 1, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf, racc,
-                                    dacc, gbase, lane);
+    // columns [c0, c1) in spans of one 64-pixel segment, far spans skipped
+    for (int c = c0; c < c1;) {
+      const int ce = min(c1, (c / PD_WAVE + 1) * PD_WAVE);
+      if ((segbits >> (c / PD_WAVE - c0 / PD_WAVE)) & 1ull) {
+        for (; c + CH <= ce; c += CH)
+          grad_cols<T, D, CH, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf,
+                                         racc, dacc, gbase, lane);
+        for (; c < ce; ++c)
+          grad_cols<T, D, 1, DIAG, HOT>(txd + (size_t)c * DP, lrow + c, grow + c, rrow + c, cf,
+                                        racc, dacc, gbase, lane);
+      }
+      c = ce;
+    }
     const auto ty = pd_uni(M.ty64 + (size_t)r * DP);
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
