@@ -268,29 +268,51 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
   P.d_off16R = off + 7 * (P.n + 1);
 }
 
+// A pinned staging buffer of at least `bytes` from the context's ring; the host
+// waits only if the copy that last used this slot (PD_STAGE_SLOTS uploads ago)
+// is still queued.
+hipError_t pd_stage_acquire(pd_ctx *ctx, size_t bytes, char **buf, int *slot_out) {
+  hipError_t e;
+  const int slot = ctx->stage_next;
+  ctx->stage_next = (slot + 1) % PD_STAGE_SLOTS;
+  if (ctx->staged[slot]) {
+    e = hipEventSynchronize(ctx->staged[slot]);
+    if (e != hipSuccess) return e;
+  } else {
+    e = hipEventCreateWithFlags(&ctx->staged[slot], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (bytes > ctx->stage_cap[slot]) {
+    if (ctx->stage[slot]) (void)hipHostFree(ctx->stage[slot]);
+    ctx->stage[slot] = nullptr;
+    ctx->stage_cap[slot] = 0;
+    e = hipHostMalloc((void **)&ctx->stage[slot], bytes * 2, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    ctx->stage_cap[slot] = bytes * 2;
+  }
+  *buf = ctx->stage[slot];
+  *slot_out = slot;
+  return hipSuccess;
+}
+
+// The stream-ordered copy out of a slot filled after pd_stage_acquire.
+hipError_t pd_stage_copy(pd_ctx *ctx, int slot, void *dst, size_t bytes, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dst, ctx->stage[slot], bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(ctx->staged[slot], s);
+}
+
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
   // maps and the four offset arrays are contiguous in the arena (o_maps, o_off)
   const size_t maps_bytes = sizeof(MapDev) * P.n;
   const size_t gap = P.o_off - P.o_maps;
   const size_t total = gap + sizeof(int32_t) * 8 * (P.n + 1);
-  hipError_t e;
-  if (ctx->staged) {
-    e = hipEventSynchronize(ctx->staged);
-    if (e != hipSuccess) return e;
-  } else {
-    e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-  }
-  if (total > ctx->stage_cap) {
-    if (ctx->stage) (void)hipHostFree(ctx->stage);
-    ctx->stage = nullptr;
-    ctx->stage_cap = 0;
-    e = hipHostMalloc((void **)&ctx->stage, total * 2, hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-    ctx->stage_cap = total * 2;
-  }
-  memcpy(ctx->stage, P.maps.data(), maps_bytes);
-  int32_t *o = (int32_t *)(ctx->stage + gap);
+  char *stage;
+  int slot;
+  hipError_t e = pd_stage_acquire(ctx, total, &stage, &slot);
+  if (e != hipSuccess) return e;
+  memcpy(stage, P.maps.data(), maps_bytes);
+  int32_t *o = (int32_t *)(stage + gap);
   for (int k = 0; k <= P.n; ++k) {
     o[k] = P.offA[k];
     o[(P.n + 1) + k] = P.offB[k];
@@ -301,9 +323,7 @@ hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s) {
     o[6 * (P.n + 1) + k] = P.off16B[k];
     o[7 * (P.n + 1) + k] = P.off16R[k];
   }
-  e = hipMemcpyAsync(P.d_maps, ctx->stage, total, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  return hipEventRecord(ctx->staged, s);
+  return pd_stage_copy(ctx, slot, P.d_maps, total, s);
 }
 
 void pd_plan_tables(const EvalPlan &P, hipStream_t s) {
@@ -470,8 +490,11 @@ void pd_destroy(pd_ctx *ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
-  if (ctx->stage) (void)hipHostFree(ctx->stage);
-  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+  for (int k = 0; k < PD_STAGE_SLOTS; ++k) {
+    if (ctx->staged[k]) (void)hipEventSynchronize(ctx->staged[k]);
+    if (ctx->stage[k]) (void)hipHostFree(ctx->stage[k]);
+    if (ctx->staged[k]) (void)hipEventDestroy(ctx->staged[k]);
+  }
   pd_fit_release(ctx);
   delete ctx;
 }

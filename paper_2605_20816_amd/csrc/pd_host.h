@@ -11,6 +11,8 @@
 
 struct FitState;
 
+#define PD_STAGE_SLOTS 4
+
 struct pd_ctx {
   int device = 0;
   std::string err;
@@ -19,10 +21,13 @@ struct pd_ctx {
   char *aux = nullptr;    // warm-start and network workspace, grown on demand
   size_t aux_cap = 0;
   FitState *fit = nullptr;
-  // pinned staging of the map descriptors; `staged` marks the last copy out of it
-  char *stage = nullptr;
-  size_t stage_cap = 0;
-  hipEvent_t staged = nullptr;
+  // pinned staging of the map descriptors: a ring of PD_STAGE_SLOTS buffers, each
+  // with the event of the last copy out of it, so that the host waits only when
+  // that many uploads are still in flight
+  char *stage[PD_STAGE_SLOTS] = {};
+  size_t stage_cap[PD_STAGE_SLOTS] = {};
+  hipEvent_t staged[PD_STAGE_SLOTS] = {};
+  int stage_next = 0;
   // autotuned waves per map, keyed by (precision, dmax bucket, log2 pairs, maps)
   std::map<std::tuple<int, int, int, int>, int> tuned;
   bool tune_loaded = false;
@@ -96,6 +101,10 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
 void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *phi_out,
                   double *const *grad_out, int32_t *const *labels_out, int64_t *n_correct);
 hipError_t pd_plan_upload(pd_ctx *ctx, EvalPlan &P, hipStream_t s);
+// Pinned staging ring: a buffer of >= bytes (waits only for the copy that used
+// the slot PD_STAGE_SLOTS uploads ago), then its stream-ordered copy to dst.
+hipError_t pd_stage_acquire(pd_ctx *ctx, size_t bytes, char **buf, int *slot);
+hipError_t pd_stage_copy(pd_ctx *ctx, int slot, void *dst, size_t bytes, hipStream_t s);
 // Memory for a laid-out plan (reserved in the workspace, or checked against the
 // fixed buffer: PD_ERR_UNSUPPORTED if it does not fit), then bind and upload.
 pd_status pd_plan_place(pd_ctx *ctx, EvalPlan &P, const Arena &L, const PlanMemory &mem,

@@ -147,15 +147,16 @@ inline int pd_dmax_bucket(int max_degree) {
 }
 
 // XCD-aware block order.  The hardware hands block b of a launch to XCD b % 8
-// (each XCD has its own L2); renumbering so that XCD x runs a contiguous range of
-// logical blocks keeps neighbouring work items -- the row segments of one pixel
-// row, the grain groups of one pixel tile -- on one L2, which then fetches their
-// shared data (row coefficients, column data) once instead of once per XCD.
-// A bijection of [0, nb).
+// (each XCD has its own L2).  Within every group of 64 blocks the numbering is
+// transposed so that XCD x runs the 8 consecutive logical blocks 64 g + 8 x ..
+// 64 g + 8 x + 7: neighbouring work items -- the row segments of one pixel row
+// -- share one L2, which then fetches their row coefficients once instead of
+// once per XCD, while every XCD still gets its share of each stretch of the
+// work list (a batch whose maps cost differently per block stays balanced).
+// The last nb % 64 blocks keep their order.  A bijection of [0, nb).
 __device__ inline int pd_xcd_block(int b, int nb) {
-  const int per = nb / 8, rem = nb % 8;
-  const int x = b % 8, k = b / 8;
-  return x * per + (x < rem ? x : rem) + k;
+  if (b >= nb - nb % 64) return b;
+  return (b & ~63) + 8 * (b & 7) + ((b >> 3) & 7);
 }
 
 // Wave-uniform map lookup: largest m with off[m] <= item (off has n+1 entries).

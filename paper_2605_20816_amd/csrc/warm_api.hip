@@ -58,26 +58,12 @@ void warm_layout(WarmLayout &W, Arena &L, const pd_problem *probs, int n) {
 
 // pinned staging of a small host block, ordered on stream s
 hipError_t upload(pd_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s) {
-  hipError_t e;
-  if (ctx->staged) {
-    e = hipEventSynchronize(ctx->staged);
-    if (e != hipSuccess) return e;
-  } else {
-    e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-  }
-  if (bytes > ctx->stage_cap) {
-    if (ctx->stage) (void)hipHostFree(ctx->stage);
-    ctx->stage = nullptr;
-    ctx->stage_cap = 0;
-    e = hipHostMalloc((void **)&ctx->stage, bytes * 2, hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-    ctx->stage_cap = bytes * 2;
-  }
-  memcpy(ctx->stage, src, bytes);
-  e = hipMemcpyAsync(dst, ctx->stage, bytes, hipMemcpyHostToDevice, s);
+  char *stage;
+  int slot;
+  hipError_t e = pd_stage_acquire(ctx, bytes, &stage, &slot);
   if (e != hipSuccess) return e;
-  return hipEventRecord(ctx->staged, s);
+  memcpy(stage, src, bytes);
+  return pd_stage_copy(ctx, slot, dst, bytes, s);
 }
 
 hipError_t warm_upload(pd_ctx *ctx, WarmLayout &W, char *base, hipStream_t s) {
