@@ -207,7 +207,7 @@ def points_throughput(pdl, ctx, torch, synth, n=262144, N=2000, d=4):
     """Unstructured 3-D points (uniform in [-1, 1]^3, labelled by a random power
     diagram of N sites), degree d (K = 35 at d = 4): one call of
     pd_points_objective_grad (features, objective, gradient, reductions), timed
-    over 5 calls after one warm-up, FP64 and FP32.  Algorithmic flops per pair as
+    with events over 5 calls after one warm-up, FP64 and FP32.  Algorithmic flops per pair as
     for the grid with K-FMA logits: objective 2K + 4, gradient 4K + 3."""
     rng = np.random.default_rng(2025)
     X, lab, Nn = synth.power_points(n, 3, N, rng)
@@ -220,11 +220,15 @@ def points_throughput(pdl, ctx, torch, synth, n=262144, N=2000, d=4):
     for prec in ("fp64", "fp32"):
         ctx.points_objective_grad([q], [th], prec)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        # the library launches on torch's current stream, so its events bracket
+        # exactly the five calls' kernels
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             ctx.points_objective_grad([q], [th], prec)
+        e1.record()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / 5 * 1e3
+        ms = e0.elapsed_time(e1) / 5
         fl = (2 * K + 4 + 4 * K + 3) * pairs
         out[prec] = {"ms_per_evaluation": ms, "pairs_per_s": pairs / (ms * 1e-3),
                      "tflops": fl / (ms * 1e-3) / 1e12,
