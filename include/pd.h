@@ -505,9 +505,10 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs /*host*/, int32_t
 /* Autotuner of the work decomposition (tile shapes of the gradient kernels:
  * pixel-tile size per 64-grain wave on the FP64/FP32 path, pixel-chunk length
  * per grain group on the BF16 path).  Times one evaluation of the given batch
- * for each candidate (waves per map: 1024 .. 32768; five evaluations each),
+ * for each candidate (waves per map: 1024 .. 65536; five evaluations each),
  * keeps the fastest for the batch's key (precision, largest degree, log2 of the
- * pixel-grain pairs, number of maps) in the context -- the default 8192 unless
+ * pixel-grain pairs, number of maps) in the context -- the untuned default
+ * (about 2^18 pixel-grain pairs per wave, 8192 to 65536 waves) unless
  * another is more than 2% faster, so that timing noise does not change the
  * tiling, and with it the rounding of the gradient sums, between runs -- and
  * uses it in every later plan with that key.  If

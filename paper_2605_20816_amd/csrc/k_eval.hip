@@ -101,11 +101,11 @@ __global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ 
 }
 
 // Row coefficients C[r][i][a] = sum_b thc[i][(a,b)] P_b(x2_r).  Padded grains
-// i in [N, Npad) get C = (-inf, 0, ..., 0): exp2 of their logit is 0.
+// i in [N, Npad) get C = (PD_LOGIT_FLOOR, 0, ..., 0): exp2 of their logit is 0.
 // grid: blocks over the flattened (map, r, i), offsets in off (n_maps + 1).
 template <int D>
 __device__ inline void prep_one(const MapDev &M, int r, int i, const double *src = nullptr,
-                                void *dst = nullptr, double pad0 = -INFINITY) {
+                                void *dst = nullptr, double pad0 = PD_LOGIT_FLOOR) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
   double *out = (double *)(dst ? dst : M.C) + ((size_t)(r - M.row0) * M.Npad + i) * DP;
@@ -220,11 +220,11 @@ __device__ inline void cert_finish(const MapDev &M, int local, int lane, int r, 
   if (lane == 0) pd_glb(M.part_c)[local] = wc;
 }
 
-// The certified arg-max alone (the FP64 evaluation runs it after k_lse: fused
-// into the FP64 objective loop it doubled that loop's registers): FP64 logits,
-// the chunk maxima, the best chunk and an upper bound of the others.
+// The certified arg-max alone (after the BF16 objective, whose logits are not
+// FP64): FP64 logits, the chunk maxima, the best chunk and an upper bound of the
+// others.
 template <int D>
-__device__ inline void argmax_item(const MapDev &M, int local, int lane) {
+PD_HOT_INLINE void argmax_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   if (local >= M.rows * M.segs) {
     if (lane == 0) pd_glb(M.part_c)[local] = 0;
@@ -279,8 +279,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_cert_argmax(const MapDev *__restri
 
 // ---------------------------------------------------------------------------
 // Kernel A: per-pixel base-2 log-sum-exp over grains and partial sums of log2 p_G.
-// With CERT (FP32 exponentials; the FP64 evaluation runs k_cert_argmax after
-// k_lse), also the hard assignment of every pixel at this theta, certified
+// With CERT, also the hard assignment of every pixel at this theta, certified
 // against the canonical FP64 arg-min (Section 2.1): the loop keeps the largest
 // chunk maximum (and its chunk) and an upper bound of the other chunks' maxima;
 // at the end the 8 logits of the best chunk are formed again, giving the best
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_cert_argmax(const MapDev *__restri
 // otherwise the pixel is listed for k_assign_list.  Per-wave counts of certified
 // correct pixels go to part_c[local].
 template <typename T, int D, bool CERT = false>
-__device__ inline void lse_item(const MapDev &M, int local, int lane) {
+PD_HOT_INLINE void lse_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   if (local >= M.rows * M.segs) {  // padding item (item counts are multiples of 4)
     if (lane == 0) {
@@ -317,17 +316,24 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   // S sums exp2(s_i - mrun) over the grains other than the pixel's label g, so
   // that r = 1 - p_g (the labelled grain's p - 1 in eq. grad, up to sign) comes
   // out as a sum of small terms instead of a difference of two numbers near 1
-  // Online maximum: after the first chunk a chunk's logits are formed relative
-  // to the running reference, u = (C0 - mrun) + sum_a C_a P_a(x1) (FP64), and
-  // converted once to the exponent type; the reference moves (an FP64 path) only
-  // when some lane of the wave meets a larger logit.
+  // Running reference mrun: the largest logit of the first chunk, then raised
+  // as below.  After the first chunk a chunk's logits are formed relative to it,
+  // u = (C0 - mrun) + sum_a C_a P_a(x1) (FP64).  FP32 exponentials: u is
+  // converted once to the exponent type, and the reference moves (an FP64 path)
+  // whenever some lane of the wave meets a larger logit.  FP64 exponentials: the
+  // reference is raised to a lane's chunk maximum only when some lane of the
+  // wave exceeds it by more than PD_LAZY_F64, so every term is below
+  // 2^PD_LAZY_F64 and the rescaling 2^x runs on few chunks.
   constexpr bool F32 = sizeof(T) == sizeof(float);
-  double mrun = -INFINITY;
+  // the far-field mask is left out of the FP32 certified loop at degree >= 5
+  // (the extra live state took that loop from 55 to 120+ vector registers)
+  constexpr bool MASK = !(CERT && F32 && D > 4);
+  double mrun;
   T S = (T)0;
   double bv = -INFINITY, sv = -INFINITY;  // CERT: best chunk maximum, an upper bound of the others
   int bi = 0;                             // CERT: first grain of the best chunk
-  if constexpr (F32) {
-    // chunk 0 (grains 0..7; N >= 2, padded grains have logit -inf)
+  {
+    // chunk 0 (grains 0..7; N >= 2, padded grains have the floor logit)
     double s0[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -352,10 +358,10 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
   // 128 groups) whose chunks were not all skipped, held by lane group % 64 in
   // bit group / 64 (a vector register: the scalar registers hold the chunk's
   // row coefficients)
-  unsigned nearv = (F32 && lane == 0) ? 1u : 0u;
+  unsigned nearv = lane == 0 ? 1u : 0u;
   // grains N .. Npad-1 (read when N is not a multiple of 8) have row
-  // coefficients (-inf, 0, ..., 0), so their logit is -inf with no test
-  for (int i0 = F32 ? 8 : 0; i0 < N; i0 += 8) {
+  // coefficients (PD_LOGIT_FLOOR, 0, ..., 0), so their term is 0 with no test
+  for (int i0 = 8; i0 < N; i0 += 8) {
     T t[8];
     double cup;  // CERT: an upper bound of the chunk's largest logit, relative to mrun
     bool far = false;  // every term of the chunk below 2^-PD_SKIP_F32 of the reference
@@ -400,28 +406,45 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
         cup = -INFINITY;  // recorded
       }
     } else {
-      // FP64 exponentials: absolute logits and the usual online maximum
-      double sj[8];
+      // FP64 exponentials, the lazily raised reference
+      // logits relative to the reference, u = (C0 - mrun) + sum_a C_a P_a(x1)
+      double u[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const auto cp = Crow + (size_t)(i0 + j) * DP;
-        double v = cp[0];
+        double v = cp[0] - mrun;
 #pragma unroll
         for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
-        sj[j] = v;
+        u[j] = v;
       }
-      double cm = sj[0];
+      double cmu = u[0];
 #pragma unroll
-      for (int j = 1; j < 8; ++j) cm = pd_max(cm, sj[j]);
+      for (int j = 1; j < 8; ++j) cmu = pd_max(cmu, u[j]);
+      if constexpr (CERT) {
+        // every chunk, far or not: its largest logit (absolute, widened by a
+        // relative 2^-50 for the two roundings of the relative form)
+        double ca = mrun + cmu;
+        ca += fabs(ca) * 0x1p-50;
+        const bool gt = ca > bv;
+        sv = gt ? bv : pd_max(sv, ca);
+        bi = gt ? i0 : bi;
+        bv = gt ? ca : bv;
+      }
       // far field: every term of the chunk below 2^-PD_SKIP_F64 of the reference
       // in every lane (a NaN logit is never skipped)
-      if (__ballot(!(cm <= mrun - PD_SKIP_F64)) == 0) continue;
-      if constexpr (!CERT || D <= 4) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
-      const double mnew = pd_max(mrun, cm);
-      S *= pd_exp2<T>(mrun - mnew);
+      if (__ballot(!(cmu <= -PD_SKIP_F64)) == 0) continue;
+      nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
+      if (__ballot(cmu > PD_LAZY_F64) != 0) {
+        // (every lane whose maximum grew moves; 2^0 = 1 leaves the others)
+        const double sh = cmu > 0.0 ? cmu : 0.0;  // a NaN maximum leaves it
+        S *= pd_exp2<T>(-sh);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] -= sh;
+        mrun += sh;
+      }
       T e[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) e[j] = pd_exp2<T>(sj[j] - mnew);
+      for (int j = 0; j < 8; ++j) e[j] = pd_exp2<T>(u[j]);
       if (__ballot((unsigned)(g - i0) < 8u) != 0) {
         // a label of this segment lies in the chunk: leave its term out
 #pragma unroll
@@ -429,7 +452,6 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) S += e[j];
-      mrun = mnew;
       continue;
     }
     if (CERT && cup != -INFINITY) {
@@ -441,7 +463,7 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
     }
     // far field in every lane (then the reference did not move)
     if (far) continue;
-    if constexpr (!CERT || D <= 4) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
+    if constexpr (MASK) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
     if (__ballot((unsigned)(g - i0) < 8u) != 0) {
       // a label of this segment lies in the chunk: leave its term out
 #pragma unroll
@@ -477,9 +499,8 @@ __device__ inline void lse_item(const MapDev &M, int local, int lane) {
 
   const double tot = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
-  // (not with CERT at degree >= 5: the extra live state took that loop from 55
-  // to 120+ vector registers; such plans have no mask)
-  if ((!CERT || D <= 4) && M.nearmask != nullptr) {
+  // (not from the FP32 certified loop at degree >= 5; such plans have no mask)
+  if (MASK && M.nearmask != nullptr) {
     const unsigned long long lo = __ballot(nearv & 1u), hi = __ballot(nearv & 2u);
     if (lane < M.mask_words) {
       const unsigned long long wv = lane < 2 ? lo : hi;
@@ -653,7 +674,7 @@ __device__ inline bool row_near(const MapDev &M, int r, int c0, int c1, int gbas
 // row in FP64 (an FP64 FMA issues at the non-packed FP32 rate, and one FP64
 // copy of the column data keeps the scalar registers of a chunk in budget).
 template <typename T, int D, int CH, bool DIAG, bool HOT>
-__device__ inline void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONST double *lp,
+PD_HOT_INLINE void grad_cols(const PD_AS_CONST double *pxd, const PD_AS_CONST double *lp,
                                  const PD_AS_CONST int32_t *gp, const PD_AS_CONST T *rp,
                                  const double (&cf)[D + 1], double (&racc)[D + 1],
                                  double (&dacc)[D + 1], int gbase, int lane) {
@@ -714,7 +735,7 @@ constexpr int grad_chunk() {
 }
 
 template <typename T, int D, bool DIAG, bool HOT>
-__device__ inline void grad_item(const MapDev &M, int local, int lane, double *sh) {
+PD_HOT_INLINE void grad_item(const MapDev &M, int local, int lane, double *sh) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
   constexpr int CH = grad_chunk<D, HOT>();
@@ -1048,7 +1069,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep_v(const MapDev *__restrict__ 
 
 // ubar(x) per pixel: lanes = pixels of a row segment, grains in chunks of 8.
 template <typename T, int D>
-__device__ inline void ubar_item(const MapDev &M, int local, int lane) {
+PD_HOT_INLINE void ubar_item(const MapDev &M, int local, int lane) {
   constexpr int DP = D + 1;
   if (local >= M.rows * M.segs) return;
   const int lr = local / M.segs;
@@ -1107,7 +1128,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_hvp_pix(const MapDev *__restrict__
 // Per (pixel tile, 64 grains): sum_x p_i (u_i - ubar) psi, the gradient
 // kernel's work list, partials and super-tile sums.
 template <typename T, int D>
-__device__ inline void hvp_item(const MapDev &M, int local, int lane, double *sh) {
+PD_HOT_INLINE void hvp_item(const MapDev &M, int local, int lane, double *sh) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
   const GradItem it = grad_item_of(M, local);
@@ -1267,13 +1288,8 @@ void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *o
                         int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
   if (blocks <= 0) return;
-  if (prec == 0) {
-    // FP64: the objective kernel as is, then the certified arg-max pass
-    PD_LAUNCH_BY_DMAX(k_lse, double, dmax, blocks, s, maps, off, n_maps, total);
-    pd_launch_cert_argmax(dmax, maps, off, n_maps, total, s);
-  } else {
-    PD_LAUNCH_BY_DMAX(k_lse_cert, float, dmax, blocks, s, maps, off, n_maps, total);
-  }
+  if (prec == 0) { PD_LAUNCH_BY_DMAX(k_lse_cert, double, dmax, blocks, s, maps, off, n_maps, total); }
+  else { PD_LAUNCH_BY_DMAX(k_lse_cert, float, dmax, blocks, s, maps, off, n_maps, total); }
 }
 void pd_launch_lse_assign(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                           int total, const MapDev *amaps, hipStream_t s) {

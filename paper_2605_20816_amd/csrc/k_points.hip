@@ -76,7 +76,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_pts_feat(const double *__restrict_
   }
 }
 
-// grid: K blocks; padded grains get the row (-inf, 0, ..., 0) (psi_0 = 1).
+// grid: K blocks; padded grains get the row (PD_LOGIT_FLOOR, 0, ..., 0) (psi_0 = 1).
 __global__ __launch_bounds__(PD_BLOCK) void k_pts_center(const double *__restrict__ theta, int N,
                                                          int Npad, int K, double eps,
                                                          double *__restrict__ thc) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_pts_center(const double *__restric
   const double mean = red[0] / (double)N;
   const double scale = -PD_LOG2E / eps;
   for (int i = threadIdx.x; i < Npad; i += PD_BLOCK)
-    thc[(size_t)i * K + k] = i < N ? scale * (theta[(size_t)i * K + k] - mean) : (k == 0 ? -INFINITY : 0.0);
+    thc[(size_t)i * K + k] = i < N ? scale * (theta[(size_t)i * K + k] - mean) : (k == 0 ? PD_LOGIT_FLOOR : 0.0);
 }
 
 struct PtsArgs {

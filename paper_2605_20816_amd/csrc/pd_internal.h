@@ -24,10 +24,23 @@
 // N 2^-96 (FP64) or N 2^-48 (FP32) of probability mass, below the rounding of
 // its sums for any grain count this library takes.
 #define PD_SKIP_F64 96.0
+#define PD_SKIP_F32 48.0
 // Largest grain count whose spatial order is computed (one block's LDS sort).
 #define PD_ORDER_MAX 8192
-#define PD_SKIP_F32 48.0
+// Logit of the padded grains N .. Npad-1 (their row coefficients are
+// (PD_LOGIT_FLOOR, 0, ..., 0)): finite, so that 2^(s - ref) is an ordinary
+// argument of the FP64 2^x (which takes no infinities) and gives 0; it converts
+// to -inf in FP32.
+#define PD_LOGIT_FLOOR (-0x1p1000)
+// The FP64 log-sum-exp raises its running reference only when a chunk's largest
+// logit exceeds it by more than this (base 2): the terms stay below 2^PD_LAZY_F64
+// and the rescaling 2^x runs on the few chunks that move the reference.
+#define PD_LAZY_F64 32.0
 #define PD_LN2 0.69314718055994530942
+// The per-item bodies of the evaluation kernels are always inlined into their
+// kernels: a call would pass the map descriptor through the call ABI and lose the
+// scalar loads of its wave-uniform data.
+#define PD_HOT_INLINE __device__ __attribute__((always_inline)) inline
 
 struct MapDev {
   // problem

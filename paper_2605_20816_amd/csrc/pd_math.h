@@ -8,17 +8,18 @@
 
 template <typename T> __device__ inline T pd_exp2(T x);
 template <> __device__ inline float pd_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-// FP64 2^t for t <= 0 (the only arguments the kernels form: a logit minus a
-// running maximum or minus the log-sum-exp).  Range reduction t = n + f with
-// n = rint(t), |f| <= 1/2; 2^f by the Chebyshev interpolant of degree 11 of 2^f
-// on [-1/2, 1/2] (Chebyshev nodes; its monomial coefficients, computed in
-// 50-digit arithmetic by exp2_coefficients.py beside this file; interpolation
-// error 3.2e-18 relative) in Horner form with FMAs (at most 0.80 ulp on 20000
-// sampled arguments, against 50-digit values); 2^n applied exactly by ldexp,
-// which also yields the subnormal and zero results.  Arguments below -1100 are
-// clamped (the result is 0 either way); NaN propagates through the comparison.
-__device__ inline double pd_exp2_nonpos(double t) {
-  t = (t < -1100.0) ? -1100.0 : t;
+// FP64 2^t for finite t <= 1023 or NaN (the kernels form a logit minus a running
+// reference or minus the log-sum-exp; padded grains and empty references use a
+// large finite floor, never -inf, which would give NaN here).  Range reduction
+// t = n + f with n = rint(t), |f| <= 1/2; 2^f by the Chebyshev interpolant of
+// degree 11 of 2^f on [-1/2, 1/2] (Chebyshev nodes; its monomial coefficients,
+// computed in 50-digit arithmetic by exp2_coefficients.py beside this file;
+// interpolation error 3.2e-18 relative) in Horner form with FMAs (at most 0.80
+// ulp on 20000 sampled arguments, against 50-digit values); 2^n applied exactly
+// by ldexp, which also yields the subnormal and zero results.  n is bounded below
+// by -2100 before its integer conversion (every result below 2^-1075 is 0); a NaN
+// argument makes f, and with it the result, NaN.
+__device__ inline double pd_exp2_f64(double t) {
   const double n = __builtin_rint(t);
   const double f = t - n;
   double p = 4.4558179083360645e-10;
@@ -33,9 +34,9 @@ __device__ inline double pd_exp2_nonpos(double t) {
   p = __builtin_fma(p, f, 0.24022650695910158);
   p = __builtin_fma(p, f, 0.6931471805599453);
   p = __builtin_fma(p, f, 1.0);
-  return __builtin_ldexp(p, (int)n);
+  return __builtin_ldexp(p, (int)__builtin_fmax(n, -2100.0));
 }
-template <> __device__ inline double pd_exp2<double>(double x) { return pd_exp2_nonpos(x); }
+template <> __device__ inline double pd_exp2<double>(double x) { return pd_exp2_f64(x); }
 template <typename T> __device__ inline T pd_log2(T x);
 template <> __device__ inline float pd_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
 template <> __device__ inline double pd_log2<double>(double x) { return log2(x); }

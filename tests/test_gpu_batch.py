@@ -71,7 +71,7 @@ def test_autotune_picks_candidate_and_keeps_parity(orc, batch):
                               multi_index=orc.multi_index(gm.meta["degree"])) for gm in batch]
     for prec in ("fp32", "bf16"):
         w = ctx.autotune(probs, [dev(t) for t in ths], prec)
-        assert w in (1024, 2048, 4096, 8192, 16384, 32768)
+        assert w in (1024, 2048, 4096, 8192, 16384, 32768, 65536)
         phi, g = ctx.objective_grad(probs, [dev(t) for t in ths], prec)
         for k, gm in enumerate(batch):
             pr, gr = orc.objective_grad(ths[k], gm.labels, gm.H, gm.W, gm.meta["degree"],
