@@ -178,7 +178,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     M.mask_words = (M.Npad / PD_WAVE + 31) / 32;  // far-field mask: at most 4 words
-    R.nearmask_on = !mf && !(prec == 1 && P.cert && M.d > 4) && M.mask_words <= 4;
+    R.nearmask_on = !mf && M.mask_words <= 4;
     R.nearmask = L.take(R.nearmask_on ? sizeof(uint32_t) * (size_t)M.rows * M.segs * M.mask_words : 0);
     R.sorted = P.sort && M.N <= PD_ORDER_MAX;
     R.order = L.take(R.sorted ? sizeof(int32_t) * M.N : 0);

@@ -325,9 +325,6 @@ PD_HOT_INLINE void lse_item(const MapDev &M, int local, int lane) {
   // wave exceeds it by more than PD_LAZY_F64, so every term is below
   // 2^PD_LAZY_F64 and the rescaling 2^x runs on few chunks.
   constexpr bool F32 = sizeof(T) == sizeof(float);
-  // the far-field mask is left out of the FP32 certified loop at degree >= 5
-  // (the extra live state took that loop from 55 to 120+ vector registers)
-  constexpr bool MASK = !(CERT && F32 && D > 4);
   double mrun;
   T S = (T)0;
   double bv = -INFINITY, sv = -INFINITY;  // CERT: best chunk maximum, an upper bound of the others
@@ -463,7 +460,7 @@ PD_HOT_INLINE void lse_item(const MapDev &M, int local, int lane) {
     }
     // far field in every lane (then the reference did not move)
     if (far) continue;
-    if constexpr (MASK) nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
+    nearv |= lane == ((i0 >> 6) & 63) ? (1u << ((i0 >> 12) & 1)) : 0u;
     if (__ballot((unsigned)(g - i0) < 8u) != 0) {
       // a label of this segment lies in the chunk: leave its term out
 #pragma unroll
@@ -499,8 +496,7 @@ PD_HOT_INLINE void lse_item(const MapDev &M, int local, int lane) {
 
   const double tot = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[local] = tot;
-  // (not from the FP32 certified loop at degree >= 5; such plans have no mask)
-  if (MASK && M.nearmask != nullptr) {
+  if (M.nearmask != nullptr) {
     const unsigned long long lo = __ballot(nearv & 1u), hi = __ballot(nearv & 2u);
     if (lane < M.mask_words) {
       const unsigned long long wv = lane < 2 ? lo : hi;
