@@ -398,7 +398,23 @@ typedef struct {
   int32_t anneal_levels;  /* 0 .. 30                                             */
   double anneal_factor;   /* > 1 when anneal_levels > 0                          */
   int32_t anneal_iters;   /* >= 1 when anneal_levels > 0                         */
+  /* Per-iteration metrics (may be NULL): host array of n_probs DEVICE buffers of
+   * trace_cap x PD_TRACE_FIELDS doubles (an entry may be NULL).  The k-th accepted
+   * iterate of a map (k = 1, 2, ..., counted over all levels of an eps schedule)
+   * is written to row (k - 1) % trace_cap of its buffer by the device when it is
+   * accepted: a ring that keeps the last trace_cap iterates, read after the call
+   * (rows of iterates that were not reached are left as they were). */
+  double *const *trace;
+  int32_t trace_cap;      /* >= 1 when trace is not NULL                        */
 } pd_fit_opts;
+
+/* Fields of one trace row: the iteration k, the objective+gradient evaluations
+ * so far (over all levels), Phi at the iterate (at the level's eps under a schedule), the largest
+ * |entry| of the gradient at the iterate (in the fit's gauge), the accepted step
+ * length t of the line search, and the FP64 accuracy of the iterate (NaN with
+ * PD_BF16, whose accuracy is assigned one step later and only at check
+ * iterates). */
+#define PD_TRACE_FIELDS 6
 
 typedef struct {
   int32_t status;         /* 0 target reached, 1 budget, 2 gtol, 3 line search failed,

@@ -59,7 +59,8 @@ class _FitOpts(ctypes.Structure):
                 ("target_acc", ctypes.c_double), ("gtol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("precondition", ctypes.c_int32), ("anneal_levels", ctypes.c_int32),
-                ("anneal_factor", ctypes.c_double), ("anneal_iters", ctypes.c_int32)]
+                ("anneal_factor", ctypes.c_double), ("anneal_iters", ctypes.c_int32),
+                ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
 
 
 class _Mlp(ctypes.Structure):
@@ -178,6 +179,9 @@ _SIGS = {
 }
 
 STAGES = ("tables", "center", "prep", "lse", "grad", "reduce")
+# columns of a fit trace row (pd_fit_opts.trace)
+TRACE_COLUMNS = ("iter", "evals", "phi", "grad_inf", "step", "acc")
+TRACE_FIELDS = len(TRACE_COLUMNS)
 
 
 def lib():
@@ -546,17 +550,32 @@ class Context:
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
             max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, precondition=0,
-            anneal=None, stream=None):
+            anneal=None, trace=None, stream=None):
         """Device L-BFGS fit of every map; thetas are updated in place.
         anneal: None, or (levels, factor, iters per level) for the schedule of eps.
+        trace: None, or one float64 CUDA tensor (cap, TRACE_FIELDS) per map (or
+        None): the ring of per-iteration metrics (TRACE_COLUMNS).
         Returns a list of report dicts."""
         n = len(probs)
         arr = (_Problem * n)(*[p.c() for p in probs])
         h = None if mlp is None else mlp.handle()
         al, af, ai = anneal if anneal is not None else (0, 0.0, 0)
+        tr, cap = None, 0
+        if trace is not None:
+            if len(trace) != n:
+                raise ValueError("one trace buffer (or None) per map")
+            caps = {int(t.shape[0]) for t in trace if t is not None}
+            for t in trace:
+                if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                                          and t.dim() == 2 and t.shape[1] == TRACE_FIELDS):
+                    raise ValueError("trace buffers must be contiguous float64 CUDA (cap, 6) tensors")
+            if len(caps) != 1:
+                raise ValueError("trace buffers must share one capacity")
+            tr, cap = _ptrs(trace), caps.pop()
         opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
                         check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p),
-                        int(precondition), int(al), float(af), int(ai))
+                        int(precondition), int(al), float(af), int(ai),
+                        None if tr is None else ctypes.cast(tr, ctypes.c_void_p), int(cap))
         reps = (_FitReport * n)()
         self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
                                  _stream(stream)))

@@ -90,6 +90,10 @@ struct FitDev {
   uint64_t clk_first, clk_last;
   int32_t evals_last;
   uint64_t *trace;  // optional stage stamps of the decision kernel (PD_FIT_TRACE builds)
+  // per-iteration metrics ring of the caller (pd_fit_opts.trace; NULL = off):
+  // iterate k = rec_base + iters goes to row (k - 1) % rec_cap
+  double *rec;
+  int32_t rec_cap, rec_base, rec_evals;  // rec_evals: evaluations of earlier levels
   // multi-block passes of an accepted step (maps with N K >= FIT_SPLIT_MIN_NK):
   // phase 1 = the memory's dot products are pending (k_fit_dots, k_fit_rec),
   // phase 2 = the direction is pending (k_fit_dir, k_fit_start)
@@ -895,6 +899,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
   const double t = F.t;
   FIT_STAMP(F, 5);
   double v3[3] = {0.0, 0.0, 0.0};
+  double gm = 0.0;  // largest |g| of the new iterate (traced fits)
   {
     const auto ps = pd_glb(s);
     const auto py = pd_glb(y);
@@ -906,6 +911,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     const auto pw = pd_glb((const double *)F.Dinv);
     const bool pre = F.precond != 0;
     const bool small = !F.split;
+    const bool rec = F.rec != nullptr;
     // FIT_UNROLL elements per thread at a time: every load is issued before
     // the stores (which the compiler could not otherwise move them past)
     for (int i0 = (int)threadIdx.x; i0 < n && (int)threadIdx.x < F.vt; i0 += FIT_UNROLL * F.vt) {
@@ -933,6 +939,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
           v3[2] = __builtin_fma(yi, yi, v3[2]);
           px[i] = xx[u];
           pg[i] = gr[u];
+          if (rec) gm = fmax(gm, fabs(gr[u]));
           if (small) {
             fit_vec[FV_G][i] = gr[u];
             fit_vec[FV_S][i] = si;
@@ -945,6 +952,7 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     }
   }
   blk_sums<3>(v3, red);
+  if (F.rec != nullptr) gm = blk_max(gm, red);
   FIT_STAMP(F, 6);
   const double sy = v3[0], ss = v3[1], yy = v3[2];
   const bool stored = sy > CURV_EPS * sqrt(ss) * sqrt(yy);
@@ -961,6 +969,17 @@ __device__ __attribute__((always_inline)) inline void accept_trial(FitDev &F, do
     F.iters++;
     F.clk_last = wall_clock64();
     F.evals_last = F.evals;
+    if (F.rec != nullptr) {
+      // (the certified evaluation at xt also counted its correct pixels)
+      const int k = F.rec_base + F.iters;
+      double *row = F.rec + (size_t)((k - 1) % F.rec_cap) * PD_TRACE_FIELDS;
+      row[0] = (double)k;
+      row[1] = (double)(F.rec_evals + F.evals);
+      row[2] = -ft;
+      row[3] = gm;
+      row[4] = t;
+      row[5] = F.cert ? (double)F.cnt_t / (double)F.n_pix : NAN;
+    }
   }
   __syncthreads();
   if (F.cert) {
@@ -1493,9 +1512,12 @@ static void pd_fit_eval(pd_ctx *ctx, const EvalPlan &P, int prec, const MapDev *
 
 // One level of the fit: L-BFGS on Phi at each map's own eps (the body of pd_fit
 // without a schedule of eps).
+// iter_base, eval_base (host, may be NULL): iterations and evaluations of each
+// map in earlier levels of an eps schedule (the trace counts on from there)
 static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
                            double *const *theta_inout, const pd_fit_opts *opts,
-                           pd_fit_report *reports, void *stream) {
+                           pd_fit_report *reports, void *stream,
+                           const int32_t *iter_base = nullptr, const int32_t *eval_base = nullptr) {
   using clk = std::chrono::steady_clock;
   const auto t_call = clk::now();
   if (!ctx) return PD_ERR_INVALID_ARG;
@@ -1519,6 +1541,8 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (opts->max_iter < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "max_iter must be >= 0");
   if (opts->check_every < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "check_every must be >= 1");
   if (!(opts->gtol >= 0.0)) return pd_fail(ctx, PD_ERR_INVALID_ARG, "gtol must be >= 0");
+  if (opts->trace && opts->trace_cap < 1)
+    return pd_fail(ctx, PD_ERR_INVALID_ARG, "trace_cap must be >= 1 with a trace");
   for (int p = 0; p < n; ++p) {
     if (!theta_inout[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "theta_inout entry is NULL");
   }
@@ -1646,6 +1670,10 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     }
     f.active = flags + p;
     f.assign_pending = flags + n + p;
+    f.rec = opts->trace ? opts->trace[p] : nullptr;
+    f.rec_cap = opts->trace ? opts->trace_cap : 1;
+    f.rec_base = iter_base ? iter_base[p] : 0;
+    f.rec_evals = eval_base ? eval_base[p] : 0;
     xt[p] = f.xt;
     graw[p] = f.graw;
   }
@@ -1872,8 +1900,17 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     ok.anneal_levels = 0;
     ok.max_iter = budget;
     if (k > 0) ok.init = PD_INIT_GIVEN;  // from the last level's theta
+    std::vector<double *> trk(nl, nullptr);
+    std::vector<int32_t> base(nl), ebase(nl);
+    for (int q = 0; q < nl; ++q) {
+      if (opts->trace) trk[q] = opts->trace[live[q]];
+      base[q] = reports[live[q]].iters;
+      ebase[q] = reports[live[q]].evals;
+    }
+    ok.trace = opts->trace ? trk.data() : nullptr;
     std::vector<pd_fit_report> rk(nl);
-    const pd_status st = fit_level(ctx, pk.data(), nl, tk.data(), &ok, rk.data(), stream);
+    const pd_status st = fit_level(ctx, pk.data(), nl, tk.data(), &ok, rk.data(), stream,
+                                   base.data(), ebase.data());
     if (st != PD_OK) return st;
     std::vector<int> next;
     for (int q = 0; q < nl; ++q) {

@@ -40,6 +40,52 @@ def test_first_iterates_match_oracle(pd, orc, iters):
     assert x[-1].tolist() == [0.0, 0.0, 0.0]
 
 
+def test_trace_follows_the_oracle_records(pd, orc):
+    """The per-iteration metrics ring of pd_fit: the first 8 FP64 iterates of the
+    c1 map against the oracle's records (Phi, accepted step, evaluation count,
+    accuracy), the gradient norm at the last iterate against the oracle's
+    gradient there, and rows of iterates not reached left as they were."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    ref = oracle_fit(orc, gm, 1, 1e-2, target_acc=2.0, max_iter=8)
+    tr = torch.full((12, pdl.TRACE_FIELDS), -7.0, dtype=torch.float64, device="cuda")
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="zero", max_iter=8,
+                  target_acc=2.0, trace=[tr])[0]
+    T = tr.cpu().numpy()
+    assert rep["iters"] == 8 and np.all(T[8:] == -7.0)
+    recs = ref["records"]
+    assert T[:8, 0].tolist() == list(range(1, 9))
+    assert T[:8, 1].tolist() == list(1 + np.cumsum([r["evals"] for r in recs]))
+    assert T[7, 1] == rep["evals"]
+    for k, r in enumerate(recs):
+        assert abs(T[k, 2] - r["phi"]) <= 1e-10 * abs(r["phi"]), k
+        assert abs(T[k, 4] - r["t"]) <= 1e-7 * abs(r["t"]), k
+        assert abs(T[k, 5] - r["acc"]) <= 2.0 / (gm.H * gm.W), k
+    assert T[7, 2] == rep["phi"] and T[7, 5] == rep["acc"]
+    _, g = orc.objective_grad(th.cpu().numpy(), gm.labels, gm.H, gm.W, 1, 1e-2)
+    gi = np.max(np.abs(g[:-1]))  # the fit's gauge: the last grain's row is fixed
+    assert abs(T[7, 3] - gi) <= 1e-9 * gi
+
+
+def test_trace_ring_over_an_eps_schedule(pd):
+    """Eight iterations over three levels of an eps schedule into a ring of 4:
+    iterates 5..8 remain, numbered across the levels, in rows (k - 1) % 4."""
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    tr = torch.zeros((4, pdl.TRACE_FIELDS), dtype=torch.float64, device="cuda")
+    th = dev(np.zeros((gm.N, 3)))
+    rep = ctx.fit([problem(pdl, gm, 1, 1e-2)], [th], "fp64", init="zero", max_iter=8,
+                  target_acc=2.0, anneal=(2, 4.0, 3), trace=[tr])[0]
+    T = tr.cpu().numpy()
+    assert rep["iters"] == 8
+    for k in range(5, 9):
+        assert T[(k - 1) % 4, 0] == k
+    ev = [T[(k - 1) % 4, 1] for k in range(5, 9)]
+    assert all(a < b for a, b in zip(ev, ev[1:])) and ev[-1] == rep["evals"]
+    assert np.all(T[:, 4] > 0) and np.all(T[:, 3] >= 0)
+
+
 def test_power_diagram_fit_reaches_99(pd, orc):
     """Section 5.4 protocol on the 64x64 N = 8 power-diagram map: theta = 0,
     eps = 1e-2, FP64 L-BFGS to >= 99% pixel accuracy; the same iteration count as

@@ -3,7 +3,8 @@ configurations bench.py times, against the FP64 oracle:
 
 * the 256x256 c2 map after the fit steps of a run and at a fitted (>= 99%
   accuracy) iterate;
-* the 16-map c4-style batch under its autotuned tiles;
+* the 16-map c4-style batch under its autotuned tiles, and all 64 maps of the
+  c4 workload as one batch (row bands);
 * the 1024x1024 degree-4 c3 map after 20 FP32 iterations and at a fitted
   iterate (row bands there: the oracle's cost);
 * the 2048x2048 degree-6 c5 map (N = 4895) in row bands of 8 rows at the top,
@@ -112,6 +113,46 @@ def test_c4_batch_autotuned(orc):
     check(ctx, orc, probs, maps, ths, "fp64", 1e-10, 1e-10)
     check(ctx, orc, probs, maps, ths, "fp32", 2e-3, 2e-3)
     check(ctx, orc, probs, maps, ths, "bf16", 2e-3, 2e-3)
+    ctx.close()
+
+
+def test_c4_all_64_maps_in_one_batch(orc):
+    """The whole 64-map c4 workload as one batch under autotuned tiles, after 30
+    batched FP32 iterations: per map a band of 4 rows at the top and one in the
+    middle (the oracle's cost), FP64/FP32 in both gradient forms and BF16, and
+    those rows' assignment bit for bit."""
+    import paper_2605_20816_amd as pdl
+    ctx = pdl.Context(0)
+    maps = [synth.config_c4_map(j) for j in range(64)]
+    probs = [pdl.Problem(dev(g.labels, torch.int32), g.H, g.W, g.N, g.meta["degree"],
+                         g.meta["eps"]) for g in maps]
+    ths = [torch.zeros((p.N, pdl.num_features(p.d)), dtype=torch.float64, device="cuda")
+           for p in probs]
+    assert ctx.autotune(probs, ths, "fp32") > 0
+    reps = ctx.fit(probs, ths, "fp32", init="zero", max_iter=30, target_acc=2.0, history=16,
+                   precondition=20)
+    assert all(r["iters"] > 0 for r in reps)
+    xs = [t.cpu().numpy() for t in ths]
+    for band_of in (lambda g: (0, 4), lambda g: (g.H // 2, g.H // 2 + 4)):
+        bands = [band_of(g) for g in maps]
+        refs = []
+        for g, p, x, (r0, r1) in zip(maps, probs, xs, bands):
+            v, gr = orc.objective_rows(x, g.labels, p.H, p.W, p.d, p.eps, r0, r1)
+            n = p.H * p.W
+            refs.append((v / n, -gr / (p.eps * n)))
+        for prec, forms in (("fp64", (False, True)), ("fp32", (False, True)), ("bf16", (False,))):
+            for form in forms:
+                phi, gs = ctx.objective_grad_rows(probs, ths, bands, prec, onehot_precomputed=form)
+                worst = 0.0
+                for k, (pr, gr) in enumerate(refs):
+                    ep, eg = rel(float(phi[k]), pr), gerr(gs[k].cpu().numpy(), gr)
+                    worst = max(worst, ep, eg)
+                    assert ep <= TOL[prec] and eg <= TOL[prec], (k, prec, form, bands[k])
+                print(f"64 maps {prec}{' fit form' if form else ''} rows {bands[0]}..: worst {worst:.1e}")
+        outs, _ = ctx.assign(probs, ths)
+        for k, (g, p, x, (r0, r1)) in enumerate(zip(maps, probs, xs, bands)):
+            Fb, _, nn = orc.assign_rows(x, p.H, p.W, p.d, r0, r1, g.labels)
+            assert nn == 0 and np.array_equal(outs[k].cpu().numpy()[r0 * p.W:r1 * p.W], Fb), k
     ctx.close()
 
 
