@@ -507,7 +507,8 @@ typedef enum {
   PD_STAGE_TABLES = 0,  /* 1-D Legendre tables (and the one-hot term's moments) */
   PD_STAGE_CENTER = 1,  /* grain-mean removal and eps scaling of theta          */
   PD_STAGE_PREP = 2,    /* row coefficients C[r][i][a]                          */
-  PD_STAGE_LSE = 3,     /* per-pixel log-sum-exp and partial sums of log p_G    */
+  PD_STAGE_LSE = 3,     /* per-pixel log-sum-exp and partial sums of log p_G,
+                           with the certified arg-max (the kernel pd_fit runs)  */
   PD_STAGE_GRAD = 4,    /* partial sums of p psi (the one-hot term precomputed,
                            as in pd_fit)                                        */
   PD_STAGE_REDUCE = 5,  /* fixed-order reductions to Phi and grad Phi           */

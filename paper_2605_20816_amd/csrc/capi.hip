@@ -741,6 +741,8 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   Arena L;
   P.onehot_pre = true;  // as in a fit
   P.sort = true;
+  // the FP64/FP32 objective stage times the certified kernel a fit runs
+  P.cert = code != 2;
   P.target_waves = pd_tuned_waves(ctx, probs, n_probs, code);
   pd_plan_layout(P, L, probs, n_probs, code);
   const size_t o_phi = L.take(sizeof(double) * n_probs);
@@ -753,6 +755,10 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   for (int p = 0; p < n_probs; ++p) g[p] = (double *)(ctx->ws + o_g[p]);
   pd_plan_bind(P, ctx->ws, theta, (double *)(ctx->ws + o_phi), g.data(), nullptr, nullptr);
   PD_HIP(ctx, pd_plan_upload(ctx, P, s));
+  // certificate slots (bound, uncertain count, canonical count) start at zero;
+  // the timed repetitions below add to them, and nothing reads them after
+  if (P.cert)
+    for (int p = 0; p < n_probs; ++p) PD_HIP(ctx, hipMemsetAsync(P.maps[p].cert, 0, 32, s));
   hipEvent_t ev[PD_NUM_STAGES + 1];
   for (auto &e : ev) PD_HIP(ctx, hipEventCreate(&e));
   // one untimed evaluation first (loads the kernels' code on first use)
@@ -776,7 +782,8 @@ pd_status pd_profile_eval(pd_ctx *ctx, const pd_problem *probs, int32_t n_probs,
   } else {
     for (int r = 0; r < reps; ++r) pd_launch_prep(P.prec, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
     PD_HIP(ctx, hipEventRecord(ev[3], s));
-    for (int r = 0; r < reps; ++r) pd_launch_lse(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
+    for (int r = 0; r < reps; ++r)
+      pd_launch_lse_cert(P.prec, P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
     PD_HIP(ctx, hipEventRecord(ev[4], s));
     for (int r = 0; r < reps; ++r)
       pd_launch_grad(P.prec, P.dmax, P.d_maps, P.d_offB, P.n, P.offB[P.n], false, !P.onehot_pre, s);
