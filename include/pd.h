@@ -406,7 +406,32 @@ typedef struct {
    * (rows of iterates that were not reached are left as they were). */
   double *const *trace;
   int32_t trace_cap;      /* >= 1 when trace is not NULL                        */
+  /* L-BFGS state (may be NULL): host array of n_probs DEVICE buffers of
+   * pd_fit_state_size(N_p, degree_p, history) doubles.  On return each map's
+   * state is written there: a header of PD_FIT_STATE_HEADER doubles (format tag,
+   * N, K, history, pairs held, ring head, accepted iterations so far, gamma,
+   * preconditioner period, gauge), then the ring of history + 1 slots of s and y
+   * (N K each), rho, the Gram matrices s_j.y_k and y_j.y_k ((history + 1)^2 each,
+   * the latter in the D^-1 metric with the preconditioner) and D^-1 (N K; only
+   * meaningful with precondition > 0).  With resume = 1 the fit starts from that
+   * state instead of an empty memory: theta_inout must hold the iterate it was
+   * written with (PD_INIT_GIVEN), history, gauge, precondition and the map's N
+   * and degree must match the header (else PD_ERR_INVALID_ARG), and the
+   * iteration count continues from the header's (max_iter counts the iterations
+   * of this call; check_every, the preconditioner refreshes and the trace
+   * numbering follow the total).  The first direction after a resume comes from
+   * the two-loop recursion over the stored pairs; the uninterrupted fit forms it
+   * in the compact form, so a resumed trajectory equals the uninterrupted one to
+   * rounding, not bit for bit.  Not combined with an eps schedule. */
+  double *const *state;
+  int32_t resume;         /* 0 or 1                                             */
 } pd_fit_opts;
+
+#define PD_FIT_STATE_HEADER 16
+/* Doubles of one map's L-BFGS state buffer (pd_fit_opts.state); 0 for invalid
+ * arguments (n_grains < 2, degree outside 1..PD_MAX_DEGREE, history outside
+ * 1..32).  Host only. */
+int64_t pd_fit_state_size(int32_t n_grains, int32_t degree, int32_t history);
 
 /* Fields of one trace row: the iteration k, the objective+gradient evaluations
  * so far (over all levels), Phi at the iterate (at the level's eps under a schedule), the largest

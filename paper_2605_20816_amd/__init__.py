@@ -60,7 +60,8 @@ class _FitOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("precondition", ctypes.c_int32), ("anneal_levels", ctypes.c_int32),
                 ("anneal_factor", ctypes.c_double), ("anneal_iters", ctypes.c_int32),
-                ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
+                ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32),
+                ("state", ctypes.c_void_p), ("resume", ctypes.c_int32)]
 
 
 class _Mlp(ctypes.Structure):
@@ -94,6 +95,7 @@ _SIGS = {
     "pd_destroy": (None, [ctypes.c_void_p]),
     "pd_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "pd_num_features": (ctypes.c_int32, [ctypes.c_int32]),
+    "pd_fit_state_size": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "pd_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_validate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Problem), ctypes.c_int32,
@@ -207,6 +209,11 @@ def exported_symbols():
 def num_features(d: int) -> int:
     """Section 3.1: K_d = (d+1)(d+2)/2."""
     return int(lib().pd_num_features(int(d)))
+
+
+def fit_state_size(n_grains: int, degree: int, history: int) -> int:
+    """Doubles of one map's L-BFGS state buffer (pd_fit_state_size); 0 if invalid."""
+    return int(lib().pd_fit_state_size(int(n_grains), int(degree), int(history)))
 
 
 def mlp_num_params(k_out: int) -> int:
@@ -550,11 +557,14 @@ class Context:
 
     def fit(self, probs, thetas, prec="fp64", gauge="last", init="given", history=10,
             max_iter=2000, target_acc=0.99, gtol=0.0, check_every=1, mlp=None, precondition=0,
-            anneal=None, trace=None, stream=None):
+            anneal=None, trace=None, state=None, resume=False, stream=None):
         """Device L-BFGS fit of every map; thetas are updated in place.
         anneal: None, or (levels, factor, iters per level) for the schedule of eps.
         trace: None, or one float64 CUDA tensor (cap, TRACE_FIELDS) per map (or
         None): the ring of per-iteration metrics (TRACE_COLUMNS).
+        state: None, or one float64 CUDA tensor of fit_state_size(N, d, history)
+        entries per map: receives the L-BFGS state; with resume=True the fit
+        continues from it (init="given", theta the iterate it was written with).
         Returns a list of report dicts."""
         n = len(probs)
         arr = (_Problem * n)(*[p.c() for p in probs])
@@ -572,10 +582,21 @@ class Context:
             if len(caps) != 1:
                 raise ValueError("trace buffers must share one capacity")
             tr, cap = _ptrs(trace), caps.pop()
+        st = None
+        if state is not None:
+            if len(state) != n:
+                raise ValueError("one state buffer (or None) per map")
+            for p, t in zip(probs, state):
+                if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                                          and t.numel() == fit_state_size(p.N, p.d, history)):
+                    raise ValueError("state buffers must be contiguous float64 CUDA tensors of "
+                                     "fit_state_size(N, d, history) entries")
+            st = _ptrs(state)
         opts = _FitOpts(PREC[prec], GAUGE[gauge], INIT[init], history, max_iter, target_acc, gtol,
                         check_every, None if h is None else ctypes.cast(h, ctypes.c_void_p),
                         int(precondition), int(al), float(af), int(ai),
-                        None if tr is None else ctypes.cast(tr, ctypes.c_void_p), int(cap))
+                        None if tr is None else ctypes.cast(tr, ctypes.c_void_p), int(cap),
+                        None if st is None else ctypes.cast(st, ctypes.c_void_p), int(bool(resume)))
         reps = (_FitReport * n)()
         self._check(lib().pd_fit(self._h, arr, n, _ptrs(thetas), ctypes.byref(opts), reps,
                                  _stream(stream)))

@@ -45,6 +45,8 @@
 #define FIT_PART_W (5 * FIT_MAX_HISTORY + 8)
 // elements per thread whose loads a one-block vector pass issues together
 #define FIT_UNROLL 4
+// format tag of a saved L-BFGS state (first header entry)
+#define FIT_STATE_TAG 20605.0
 
 enum { PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_ACCEPT_NEXT = 3, PH_STOP = 4 };
 enum { ST_RUNNING = -1, ST_TARGET = 0, ST_BUDGET = 1, ST_GTOL = 2, ST_LSFAIL = 3, ST_NONFINITE = 4 };
@@ -94,6 +96,9 @@ struct FitDev {
   // iterate k = rec_base + iters goes to row (k - 1) % rec_cap
   double *rec;
   int32_t rec_cap, rec_base, rec_evals;  // rec_evals: evaluations of earlier levels
+  // the memory, gamma, D^-1 and the iteration count were loaded from a saved
+  // state: the start keeps them and takes its direction from the stored pairs
+  int32_t resumed;
   // multi-block passes of an accepted step (maps with N K >= FIT_SPLIT_MIN_NK):
   // phase 1 = the memory's dot products are pending (k_fit_dots, k_fit_rec),
   // phase 2 = the direction is pending (k_fit_dir, k_fit_start)
@@ -111,6 +116,21 @@ struct FitDev {
 #else
 #define FIT_STAMP(F, k) do { } while (0)
 #endif
+
+// Doubles of a saved state after its header up to D^-1: the ring of s and y
+// (m + 1 slots of N K each), rho (m + 1) and the two Gram matrices ((m + 1)^2
+// each), laid out as in the fit's own vectors.
+static inline size_t fit_state_ring(size_t NK, int m) {
+  const size_t M1 = (size_t)m + 1;
+  return 2 * M1 * NK + M1 + 2 * M1 * M1;
+}
+
+extern "C" int64_t pd_fit_state_size(int32_t n_grains, int32_t degree, int32_t history) {
+  if (n_grains < 2 || degree < 1 || degree > PD_MAX_DEGREE || history < 1 || history > FIT_MAX_HISTORY)
+    return 0;
+  const size_t NK = (size_t)n_grains * ((degree + 1) * (degree + 2) / 2);
+  return (int64_t)(PD_FIT_STATE_HEADER + fit_state_ring(NK, history) + NK);
+}
 
 struct FitState {
   hipStream_t stream = nullptr;
@@ -1147,6 +1167,80 @@ __device__ inline void consume_acc(FitDev &F, long long n_correct) {
   __shared__ FitDev sF;                             \
   __shared__ int action;
 
+// Start of a resumed fit.  A fit that stops at its budget has stored its last
+// pair (s, y, rho) but skipped the rest of that accepted step, which the
+// uninterrupted fit would have done: the preconditioner refresh due at that
+// iterate (from the Hessian diagonal of this start's evaluation), the Gram
+// entries of the new pair and, with the preconditioner, gamma.  So the Gram
+// matrices of the live pairs are formed again here (s_j.y_k, and y_j.y_k in the
+// metric of H0), gamma too with the preconditioner; then g = graw and d = -H g by
+// the two-loop recursion over the stored pairs (newest to oldest, then back),
+// H0 = gamma I or gamma D^-1.  Every dot product is a fixed-order block sum.
+__device__ __attribute__((always_inline)) inline void resumed_direction(FitDev &F, double *red) {
+  const int n = F.NK, M1 = F.m + 1, L = F.hist_len;
+  __shared__ double alpha[FIT_MAX_HISTORY + 1];
+  if (F.precond && (F.iters % F.precond) == 0) refresh_dinv(F, red);
+  for (int a = 0; a < L; ++a) {
+    const int ja = (F.hist_head + a) % M1;
+    const double *sa = F.S + (size_t)ja * n, *ya = F.Y + (size_t)ja * n;
+    for (int b = 0; b < L; ++b) {
+      const int jb = (F.hist_head + b) % M1;
+      const double *yb = F.Y + (size_t)jb * n;
+      double v[2] = {0.0, 0.0};
+      for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
+        v[0] = __builtin_fma(sa[i], yb[i], v[0]);
+        v[1] = __builtin_fma(F.precond ? ya[i] * F.Dinv[i] : ya[i], yb[i], v[1]);
+      }
+      blk_sums<2>(v, red);
+      if (threadIdx.x == 0) {
+        F.SY[ja * M1 + jb] = v[0];
+        F.YY[ja * M1 + jb] = v[1];
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && F.precond && L > 0) {
+    const int jn = (F.hist_head + L - 1) % M1;
+    F.gamma = F.SY[jn * M1 + jn] / F.YY[jn * M1 + jn];
+  }
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
+    F.g[i] = F.graw[i];
+    F.d[i] = F.graw[i];  // q
+  }
+  __syncthreads();
+  for (int k = L - 1; k >= 0; --k) {
+    const int slot = (F.hist_head + k) % M1;
+    const double *sk = F.S + (size_t)slot * n, *yk = F.Y + (size_t)slot * n;
+    double v[1] = {0.0};
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt)
+      v[0] = __builtin_fma(sk[i], F.d[i], v[0]);
+    blk_sums<1>(v, red);
+    const double a = F.rho[slot] * v[0];
+    if (threadIdx.x == 0) alpha[k] = a;
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt)
+      F.d[i] = __builtin_fma(-a, yk[i], F.d[i]);
+    __syncthreads();
+  }
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt)
+    F.d[i] = F.gamma * (F.precond ? F.Dinv[i] * F.d[i] : F.d[i]);  // r
+  __syncthreads();
+  for (int k = 0; k < L; ++k) {
+    const int slot = (F.hist_head + k) % M1;
+    const double *sk = F.S + (size_t)slot * n, *yk = F.Y + (size_t)slot * n;
+    double v[1] = {0.0};
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt)
+      v[0] = __builtin_fma(yk[i], F.d[i], v[0]);
+    blk_sums<1>(v, red);
+    const double c = alpha[k] - F.rho[slot] * v[0];
+    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt)
+      F.d[i] = __builtin_fma(c, sk[i], F.d[i]);
+    __syncthreads();
+  }
+  for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) F.d[i] = -F.d[i];
+  if (threadIdx.x == 0) fit_staged = 0;
+  __syncthreads();
+}
+
 __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, double *red, int *slots,
                             double *coef, double *gSY, double *gYY, int *action_p, double ft);
 
@@ -1224,13 +1318,17 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
   FIT_STAMP(F, 1);
   if (threadIdx.x == 0) F.evals++;
   if (F.phase == PH_INIT) {
-    if (F.precond) refresh_dinv(F, red);
-    for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
-      F.g[i] = F.graw[i];
-      F.d[i] = F.precond ? -F.Dinv[i] * F.graw[i] : -F.graw[i];
+    if (F.resumed) {
+      resumed_direction(F, red);
+    } else {
+      if (F.precond) refresh_dinv(F, red);
+      for (int i = (int)threadIdx.x; i < n && (int)threadIdx.x < F.vt; i += F.vt) {
+        F.g[i] = F.graw[i];
+        F.d[i] = F.precond ? -F.Dinv[i] * F.graw[i] : -F.graw[i];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && F.precond) *F.want_diag = (1 % F.precond) == 0 ? 1 : 0;
+    if (threadIdx.x == 0 && F.precond) *F.want_diag = ((F.iters + 1) % F.precond) == 0 ? 1 : 0;
     if (threadIdx.x == 0) {
       F.f = ft;
       F.clk_first = F.clk_last = wall_clock64();
@@ -1243,12 +1341,12 @@ __device__ __attribute__((always_inline)) inline void decide_body(FitDev &F, dou
         if (F.acc >= F.target_acc) {
           F.clk_target = wall_clock64();
           fit_stop(F, ST_TARGET);
-        } else if (F.max_iter == 0) {
+        } else if (F.iters >= F.max_iter) {
           fit_stop(F, ST_BUDGET);
         }
       } else {
         *F.assign_pending = 1;
-        if (F.max_iter == 0) F.phase = PH_STOP;
+        if (F.iters >= F.max_iter) F.phase = PH_STOP;
       }
     }
     __syncthreads();
@@ -1455,16 +1553,21 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit_init(FitDev *Fs, int zero_s
   if (threadIdx.x == 0) {
     F.status = ST_RUNNING;
     F.phase = PH_INIT;
-    F.iters = F.evals = F.ls_evals = F.hist_len = F.hist_head = F.reset_tried = 0;
+    F.evals = F.ls_evals = F.reset_tried = 0;
+    if (!F.resumed) {
+      F.iters = F.hist_len = F.hist_head = 0;
+      F.gamma = 1.0;
+    }
     F.t = 0.0;
-    F.gamma = 1.0;
     F.acc = -1.0;
     F.clk_target = 0;
     F.clk_first = F.clk_last = 0;
     F.evals_last = 0;
     *F.active = 1;
     *F.assign_pending = 0;
-    if (F.want_diag) *F.want_diag = F.precond ? 1 : 0;
+    // the start's evaluation takes the Hessian diagonal for the first refresh (a
+    // resumed fit: when its iteration count is a refresh iterate)
+    if (F.want_diag) *F.want_diag = (F.precond && (!F.resumed || (F.iters % F.precond) == 0)) ? 1 : 0;
     if (F.cert) {
       *F.cert_slot = 0.0;
       *F.unc_count = 0;
@@ -1549,6 +1652,14 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (prec == 2)
     for (int p = 0; p < n; ++p)
       if (probs[p].degree > 6) return pd_fail(ctx, PD_ERR_UNSUPPORTED, "PD_BF16 supports degree <= 6");
+  if (opts->resume != 0 && opts->resume != 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "resume must be 0 or 1");
+  if (opts->resume) {
+    if (!opts->state) return pd_fail(ctx, PD_ERR_INVALID_ARG, "resume needs the state buffers");
+    if (opts->init != PD_INIT_GIVEN)
+      return pd_fail(ctx, PD_ERR_INVALID_ARG, "resume needs PD_INIT_GIVEN (the iterate of the state)");
+    for (int p = 0; p < n; ++p)
+      if (!opts->state[p]) return pd_fail(ctx, PD_ERR_INVALID_ARG, "resume: a state entry is NULL");
+  }
   if (opts->precondition < 0) return pd_fail(ctx, PD_ERR_INVALID_ARG, "precondition must be >= 0");
   if (opts->precondition > 0 && opts->gauge != PD_GAUGE_LAST_ZERO)
     return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the diagonal preconditioner keeps PD_GAUGE_LAST_ZERO");
@@ -1566,6 +1677,31 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   hipStream_t s = ctx->fit->stream;
   // the fit starts after the caller's earlier work on its stream
   FIT_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+
+  // ---- a saved L-BFGS state to resume from: its header must match
+  const int m_hist = opts->history;
+  std::vector<double> hdr((size_t)PD_FIT_STATE_HEADER * n, 0.0);
+  if (opts->resume) {
+    for (int p = 0; p < n; ++p)
+      FIT_HIP(ctx, hipMemcpyAsync(hdr.data() + (size_t)PD_FIT_STATE_HEADER * p, opts->state[p],
+                                  sizeof(double) * PD_FIT_STATE_HEADER, hipMemcpyDeviceToHost, s));
+    FIT_HIP(ctx, hipStreamSynchronize(s));
+    for (int p = 0; p < n; ++p) {
+      const double *h = hdr.data() + (size_t)PD_FIT_STATE_HEADER * p;
+      const int K = (probs[p].degree + 1) * (probs[p].degree + 2) / 2;
+      const bool ok = h[0] == FIT_STATE_TAG && h[1] == probs[p].n_grains && h[2] == K &&
+                      h[3] == m_hist && h[4] >= 0 && h[4] <= m_hist && h[5] >= 0 && h[5] <= m_hist &&
+                      h[6] >= 0 && h[6] + opts->max_iter <= 2e9 && h[8] == opts->precondition &&
+                      h[9] == (double)opts->gauge;
+      if (!ok)
+        return pd_fail(ctx, PD_ERR_INVALID_ARG,
+                       "resume: state " + std::to_string(p) +
+                           " was not written for this map, history, gauge and preconditioner");
+    }
+  }
+
+  std::vector<double> hdr_iters0(n, 0.0);
+  for (int p = 0; p < n; ++p) hdr_iters0[p] = hdr[(size_t)PD_FIT_STATE_HEADER * p + 6];
 
   // ---- layout: evaluation plan + fit state
   const int eval_prec = prec == 2 ? 2 : prec;
@@ -1670,6 +1806,15 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     }
     f.active = flags + p;
     f.assign_pending = flags + n + p;
+    if (opts->resume) {
+      const double *h = hdr.data() + (size_t)PD_FIT_STATE_HEADER * p;
+      f.resumed = 1;
+      f.hist_len = (int32_t)h[4];
+      f.hist_head = (int32_t)h[5];
+      f.iters = (int32_t)h[6];
+      f.gamma = h[7];
+      f.max_iter = f.iters + opts->max_iter;
+    }
     f.rec = opts->trace ? opts->trace[p] : nullptr;
     f.rec_cap = opts->trace ? opts->trace_cap : 1;
     f.rec_base = iter_base ? iter_base[p] : 0;
@@ -1734,6 +1879,14 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     for (int p = 0; p < n; ++p)
       FIT_HIP(ctx, hipMemcpyAsync(F[p].x, theta_inout[p], sizeof(double) * F[p].NK,
                                   hipMemcpyDeviceToDevice, s));
+  if (opts->resume)
+    for (int p = 0; p < n; ++p) {
+      const size_t NK = (size_t)F[p].NK;
+      FIT_HIP(ctx, hipMemcpyAsync(F[p].S, opts->state[p] + PD_FIT_STATE_HEADER,
+                                  sizeof(double) * fit_state_ring(NK, m), hipMemcpyDeviceToDevice, s));
+      FIT_HIP(ctx, hipMemcpyAsync(F[p].Dinv, opts->state[p] + PD_FIT_STATE_HEADER + fit_state_ring(NK, m),
+                                  sizeof(double) * NK, hipMemcpyDeviceToDevice, s));
+    }
   const auto t_stamp = clk::now();
   k_fit_stamp<<<(n + 255) / 256, 256, 0, s>>>(dF, n);
   pd_plan_tables(P, s);
@@ -1805,6 +1958,33 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
                                 hipMemcpyDeviceToDevice, s));
   FIT_HIP(ctx, hipStreamSynchronize(s));
   const auto t_end = clk::now();
+  // ---- the L-BFGS state of every map, for a later resume
+  if (opts->state) {
+    for (int p = 0; p < n; ++p) {
+      if (!opts->state[p]) continue;
+      const FitDev &f = F[p];
+      double *h = hdr.data() + (size_t)PD_FIT_STATE_HEADER * p;
+      for (int k = 0; k < PD_FIT_STATE_HEADER; ++k) h[k] = 0.0;
+      h[0] = FIT_STATE_TAG;
+      h[1] = f.N;
+      h[2] = f.K;
+      h[3] = f.m;
+      h[4] = f.hist_len;
+      h[5] = f.hist_head;
+      h[6] = f.iters;
+      h[7] = f.gamma;
+      h[8] = f.precond;
+      h[9] = f.gauge;
+      const size_t NK = (size_t)f.NK;
+      FIT_HIP(ctx, hipMemcpyAsync(opts->state[p], h, sizeof(double) * PD_FIT_STATE_HEADER,
+                                  hipMemcpyHostToDevice, s));
+      FIT_HIP(ctx, hipMemcpyAsync(opts->state[p] + PD_FIT_STATE_HEADER, f.S,
+                                  sizeof(double) * fit_state_ring(NK, f.m), hipMemcpyDeviceToDevice, s));
+      FIT_HIP(ctx, hipMemcpyAsync(opts->state[p] + PD_FIT_STATE_HEADER + fit_state_ring(NK, f.m), f.Dinv,
+                                  sizeof(double) * NK, hipMemcpyDeviceToDevice, s));
+    }
+    FIT_HIP(ctx, hipStreamSynchronize(s));
+  }
 #ifdef PD_FIT_TRACE
   if (const char *path = getenv("PD_FIT_TRACE_OUT")) {
     std::vector<uint64_t> h((size_t)256 * 16 * n);
@@ -1823,7 +2003,7 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     pd_fit_report &r = reports[p];
     const FitDev &f = F[p];
     r.status = f.status == ST_RUNNING ? ST_BUDGET : f.status;
-    r.iters = f.iters;
+    r.iters = f.iters - (opts->resume ? (int32_t)hdr_iters0[p] : 0);
     r.evals = f.evals;
     r.phi = -f.f;
     r.acc = (double)h_nc[p] / (double)f.n_pix;
@@ -1867,6 +2047,8 @@ extern "C" pd_status pd_fit(pd_ctx *ctx, const pd_problem *probs, int32_t n,
   if (opts->anneal_levels < 0 || opts->anneal_levels > 30)
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_levels must be in [0, 30]");
   if (opts->anneal_levels == 0) return fit_level(ctx, probs, n, theta_inout, opts, reports, stream);
+  if (opts->state || opts->resume)
+    return pd_fail(ctx, PD_ERR_UNSUPPORTED, "the L-BFGS state is not kept across an eps schedule");
   if (!(opts->anneal_factor > 1.0) || !std::isfinite(opts->anneal_factor))
     return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_factor must be finite and > 1");
   if (opts->anneal_iters < 1) return pd_fail(ctx, PD_ERR_INVALID_ARG, "anneal_iters must be >= 1");

@@ -31,3 +31,16 @@ def test_num_features_host():
     for d in range(0, 9):
         assert pdl.num_features(d) == (d + 1) * (d + 2) // 2
     assert pdl.num_features(-1) == 0 and pdl.num_features(9) == 0
+
+
+def test_fit_state_size_host():
+    """pd_fit_state_size: header, the ring of history + 1 slots of s and y, rho,
+    the two Gram matrices and D^-1; 0 for arguments pd_fit would reject."""
+    for N, d, m in [(2, 1, 1), (7, 3, 10), (4895, 6, 10), (100, 8, 32)]:
+        K = (d + 1) * (d + 2) // 2
+        NK = N * K
+        want = 16 + 2 * (m + 1) * NK + (m + 1) + 2 * (m + 1) ** 2 + NK
+        assert pdl.fit_state_size(N, d, m) == want
+    assert pdl.fit_state_size(4895, 6, 10) * 8 < 32e6  # the c5 state: about 25 MB
+    for bad in [(1, 2, 10), (10, 0, 10), (10, 9, 10), (10, 2, 0), (10, 2, 33)]:
+        assert pdl.fit_state_size(*bad) == 0

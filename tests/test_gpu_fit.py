@@ -377,6 +377,69 @@ def test_split_path_iterates_match_oracle(pd, orc, split_path, iters, pre):
     assert abs(rep["phi"] - ref["phi"]) <= 1e-9 * abs(ref["phi"])
 
 
+@pytest.mark.parametrize("case", ["single-block", "multi-block-preconditioned"])
+def test_resumed_fit_follows_the_uninterrupted_one(pd, orc, case):
+    """k0 iterations with the L-BFGS state written out, then k1 more resumed from
+    it: the iterate, Phi and the evaluation count of the uninterrupted run (the
+    oracle's L-BFGS, which takes every direction by the two-loop recursion), the
+    iteration count continued in the state's header and in the trace.  The
+    multi-block map (N K = 1300) refreshes its preconditioner at iterations 5
+    and 10, before and after the resume."""
+    pdl, ctx = pd
+    if case == "single-block":
+        gm, d, eps, pre, k0, k1, m = synth.config_c1(), 1, 1e-2, 0, 3, 5, 10
+    else:
+        gm, d, eps, pre, k0, k1, m = poly_map(7, 96, 96, 130, 3), 3, 1e-3, 5, 6, 6, 10
+    K = pdl.num_features(d)
+    obj = lambda th: orc.objective_grad(th, gm.labels, gm.H, gm.W, d, eps)
+    kw = {}
+    if pre:
+        kw = dict(precondition=lambda th: orc.hessian_diag(th, gm.labels, gm.H, gm.W, d, eps),
+                  diag_every=pre)
+    ref = orc.lbfgs_fit(obj, np.zeros((gm.N, K)), target_acc=2.0, max_iter=k0 + k1, history=m, **kw)
+    prob = problem(pdl, gm, d, eps)
+    st = torch.full((pdl.fit_state_size(gm.N, d, m),), np.nan, dtype=torch.float64, device="cuda")
+    th = dev(np.zeros((gm.N, K)))
+    r0 = ctx.fit([prob], [th], "fp64", init="zero", max_iter=k0, target_acc=2.0, history=m,
+                 precondition=pre, state=[st])[0]
+    h = st[:16].cpu().numpy()
+    assert r0["iters"] == k0 and h[6] == k0 and h[3] == m and h[1] == gm.N and h[2] == K
+    tr = torch.zeros((k0 + k1, pdl.TRACE_FIELDS), dtype=torch.float64, device="cuda")
+    r1 = ctx.fit([prob], [th], "fp64", init="given", max_iter=k1, target_acc=2.0, history=m,
+                 precondition=pre, state=[st], resume=True, trace=[tr])[0]
+    assert r1["iters"] == k1 and st[6].item() == k0 + k1
+    T = tr.cpu().numpy()
+    assert T[k0:, 0].tolist() == list(range(k0 + 1, k0 + k1 + 1))  # numbering continues
+    assert r0["evals"] + r1["evals"] - 1 == ref["evals"]  # the resume re-evaluates its start
+    x = th.cpu().numpy()
+    err = np.max(np.abs(x - ref["theta"])) / np.max(np.abs(ref["theta"]))
+    print(f"{case}: resumed after {k0} of {k0 + k1} iterations, {err:.1e} from the oracle")
+    assert err <= 1e-7
+    assert abs(r1["phi"] - ref["phi"]) <= 1e-9 * abs(ref["phi"])
+
+
+def test_resume_argument_checks(pd):
+    pdl, ctx = pd
+    gm = synth.config_c1()
+    prob = problem(pdl, gm, 1, 1e-2)
+    th = dev(np.zeros((gm.N, 3)))
+    st = torch.zeros((pdl.fit_state_size(gm.N, 1, 10),), dtype=torch.float64, device="cuda")
+    with pytest.raises(pdl.PdError):  # nothing written there yet
+        ctx.fit([prob], [th], "fp64", init="given", max_iter=2, state=[st], resume=True)
+    with pytest.raises(pdl.PdError):  # resume without a state
+        ctx.fit([prob], [th], "fp64", init="given", max_iter=2, resume=True)
+    ctx.fit([prob], [th], "fp64", init="zero", max_iter=2, target_acc=2.0, state=[st])
+    with pytest.raises(pdl.PdError):  # another preconditioner than the state's
+        ctx.fit([prob], [th], "fp64", init="given", max_iter=2, history=10, precondition=3,
+                state=[st], resume=True)
+    with pytest.raises(pdl.PdError):  # a resume starts from the given iterate
+        ctx.fit([prob], [th], "fp64", init="zero", max_iter=2, state=[st], resume=True)
+    with pytest.raises(pdl.PdError):  # not across an eps schedule
+        ctx.fit([prob], [th], "fp64", init="given", max_iter=2, anneal=(1, 2.0, 1), state=[st])
+    r = ctx.fit([prob], [th], "fp64", init="given", max_iter=0, target_acc=2.0, state=[st], resume=True)[0]
+    assert r["iters"] == 0 and st[6].item() == 2
+
+
 def test_split_path_batch_reaches_99(pd, orc, split_path):
     """A batch where every map takes the multi-block path reaches 99% like the
     single-block path, and the accuracy the fit reports is the oracle's."""
