@@ -419,10 +419,13 @@ typedef struct {
    * and degree must match the header (else PD_ERR_INVALID_ARG), and the
    * iteration count continues from the header's (max_iter counts the iterations
    * of this call; check_every, the preconditioner refreshes and the trace
-   * numbering follow the total).  The first direction after a resume comes from
-   * the two-loop recursion over the stored pairs; the uninterrupted fit forms it
-   * in the compact form, so a resumed trajectory equals the uninterrupted one to
-   * rounding, not bit for bit.  Not combined with an eps schedule. */
+   * numbering follow the total).  At a resume the Gram matrices of the stored
+   * pairs (and, with the preconditioner, gamma and a refresh due at that iterate)
+   * are formed again, since a fit that stops at its budget skips them for its
+   * last pair, and the first direction comes from the two-loop recursion over the
+   * stored pairs; the uninterrupted fit forms it in the compact form, so a
+   * resumed trajectory equals the uninterrupted one to rounding, not bit for
+   * bit.  Not combined with an eps schedule. */
   double *const *state;
   int32_t resume;         /* 0 or 1                                             */
 } pd_fit_opts;
