@@ -418,6 +418,31 @@ def test_resumed_fit_follows_the_uninterrupted_one(pd, orc, case):
     assert abs(r1["phi"] - ref["phi"]) <= 1e-9 * abs(ref["phi"])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_resumed_reduced_precision_fit_follows_the_uninterrupted_one(pd, prec):
+    """The same split of a fit in FP32 and BF16 evaluations (k0 = 4, k1 = 6 on a
+    degree-3 map with the preconditioner every 3 iterations): against the
+    uninterrupted fit in the same precision, whose evaluations are deterministic,
+    the resumed iterate differs only by the rounding of the first direction."""
+    pdl, ctx = pd
+    gm, d, eps, m = poly_map(3, 64, 64, 16, 3), 3, 1e-3, 8
+    K = pdl.num_features(d)
+    prob = problem(pdl, gm, d, eps)
+    kw = dict(target_acc=2.0, history=m, precondition=3)
+    ta = dev(np.zeros((gm.N, K)))
+    ra = ctx.fit([prob], [ta], prec, init="zero", max_iter=10, **kw)[0]
+    st = torch.zeros((pdl.fit_state_size(gm.N, d, m),), dtype=torch.float64, device="cuda")
+    tb = dev(np.zeros((gm.N, K)))
+    r0 = ctx.fit([prob], [tb], prec, init="zero", max_iter=4, state=[st], **kw)[0]
+    r1 = ctx.fit([prob], [tb], prec, init="given", max_iter=6, state=[st], resume=True, **kw)[0]
+    assert ra["iters"] == 10 and r0["iters"] + r1["iters"] == 10
+    assert r0["evals"] + r1["evals"] - 1 == ra["evals"]
+    a, b = ta.cpu().numpy(), tb.cpu().numpy()
+    err = np.max(np.abs(a - b)) / np.max(np.abs(a))
+    print(f"{prec}: resumed after 4 of 10 iterations, {err:.1e} from the uninterrupted fit")
+    assert err <= 1e-9
+
+
 def test_resume_argument_checks(pd):
     pdl, ctx = pd
     gm = synth.config_c1()
