@@ -437,7 +437,7 @@ typedef struct {
 int64_t pd_fit_state_size(int32_t n_grains, int32_t degree, int32_t history);
 
 /* Fields of one trace row: the iteration k, the objective+gradient evaluations
- * so far (over all levels), Phi at the iterate (at the level's eps under a schedule), the largest
+ * of this call so far (over all levels), Phi at the iterate (at the level's eps under a schedule), the largest
  * |entry| of the gradient at the iterate (in the fit's gauge), the accepted step
  * length t of the line search, and the FP64 accuracy of the iterate (NaN with
  * PD_BF16, whose accuracy is assigned one step later and only at check
