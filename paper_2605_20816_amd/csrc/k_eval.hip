@@ -100,22 +100,21 @@ __global__ __launch_bounds__(PD_BLOCK) void k_center(const MapDev *__restrict__ 
     M.thc[(size_t)i * M.K + k] = scale * (M.theta[(size_t)i * M.K + k] - mean);
 }
 
-// Row coefficients C[r][i][a] = sum_b thc[i][(a,b)] P_b(x2_r).  Padded grains
-// i in [N, Npad) get C = (PD_LOGIT_FLOOR, 0, ..., 0): exp2 of their logit is 0.
-// grid: blocks over the flattened (map, r, i), offsets in off (n_maps + 1).
+// Row coefficients C[r][i][a] = sum_b thc[i][(a,b)] P_b(x2_r) of one (row, grain)
+// item into out (DP values).  Padded grains i in [N, Npad) get
+// (pad0, 0, ..., 0): with pad0 = PD_LOGIT_FLOOR exp2 of their logit is 0.
 template <int D>
-__device__ inline void prep_one(const MapDev &M, int r, int i, const double *src = nullptr,
-                                void *dst = nullptr, double pad0 = PD_LOGIT_FLOOR) {
+__device__ inline void prep_one(const MapDev &M, int r, int i, const double *src, double *out,
+                                double pad0) {
   constexpr int DP = D + 1;
   constexpr int K = (D + 1) * (D + 2) / 2;
-  double *out = (double *)(dst ? dst : M.C) + ((size_t)(r - M.row0) * M.Npad + i) * DP;
   if (i >= M.N) {
     out[0] = pad0;
 #pragma unroll
     for (int a = 1; a < DP; ++a) out[a] = 0.0;
     return;
   }
-  const double *th = (src ? src : M.thc) + (size_t)(M.order ? M.order[i] : i) * K;
+  const double *th = src + (size_t)(M.order ? M.order[i] : i) * K;
   const double *ty = M.ty64 + (size_t)r * DP;
 #pragma unroll
   for (int a = 0; a <= D; ++a) {
@@ -124,6 +123,28 @@ __device__ inline void prep_one(const MapDev &M, int r, int i, const double *src
     for (int b = 1; a + b <= D; ++b) v = __builtin_fma(th[pd_alpha_index(a, b)], ty[b], v);
     out[a] = v;
   }
+}
+
+// The block's PD_BLOCK consecutive items (flat index (r - row0) Npad + i, from f0)
+// of the coefficients of src (N x K) into dst (rows x Npad x DP).  An item's DP
+// values are contiguous in dst, so the block's output is one span: staged in LDS
+// and stored with consecutive lanes on consecutive doubles (one store per item and
+// coefficient left a stride of DP doubles between lanes and every cache line
+// written piecewise).  Every thread of the block calls this.
+__device__ inline void prep_block(const MapDev &M, long long f0, const double *src, double *dst,
+                                  double pad0) {
+  __shared__ double pst[PD_BLOCK * (PD_DMAX + 1)];
+  const long long total = (long long)M.rows * M.Npad;
+  const long long flat = f0 + threadIdx.x;
+  const int DP = M.DP;
+  if (flat < total) {
+    const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
+    PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i, src, pst + threadIdx.x * DP, pad0)));
+  }
+  __syncthreads();
+  const long long nv = total - f0 < PD_BLOCK ? total - f0 : PD_BLOCK;
+  double *out = dst + f0 * DP;
+  for (long long e = threadIdx.x; e < nv * DP; e += PD_BLOCK) out[e] = pst[e];
 }
 
 // Rounding bound of grain i's logit against the canonical FP64 score (see
@@ -174,9 +195,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep(const MapDev *__restrict__ ma
     if (threadIdx.x == 0)
       atomicMax((unsigned long long *)M.cert, (unsigned long long)__double_as_longlong(bred[0]));
   }
-  if (flat >= (long long)M.rows * M.Npad) return;
-  const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
-  PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i)));
+  prep_block(M, flat - threadIdx.x, M.thc, (double *)M.C, PD_LOGIT_FLOOR);
 }
 
 // The certified arg-max of one pixel per lane (see lse_item): the 8 logits of
@@ -1057,10 +1076,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k_prep_v(const MapDev *__restrict__ 
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
-  const long long flat = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
-  if (flat >= (long long)M.rows * M.Npad) return;
-  const int lr = (int)(flat / M.Npad), i = (int)(flat - (long long)lr * M.Npad);
-  PD_DISPATCH_D(M.d, (prep_one<D>(M, M.row0 + lr, i, M.hv_in, M.Cv, 0.0)));
+  prep_block(M, (long long)(blockIdx.x - off[m]) * PD_BLOCK, M.hv_in, (double *)M.Cv, 0.0);
 }
 
 // ubar(x) per pixel: lanes = pixels of a row segment, grains in chunks of 8.
