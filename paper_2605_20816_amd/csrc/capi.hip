@@ -104,11 +104,6 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
   P.max_k = 0;
   int max_d = 1;
   for (int p = 0; p < n; ++p) max_d = std::max(max_d, probs[p].degree);
-  // BF16 path: the matrix-core kernels run 16-feature blocks up to the batch's
-  // largest degree (one block to degree 4, two above), so every map's thc pieces
-  // are padded to that width: a map of lower degree reads zeros, not the next
-  // grain's row, in the blocks beyond its own features
-  const int kp_batch = pd_dmax_bucket(max_d) <= 4 ? 16 : 32;
   const size_t tsz = prec == 0 ? 8 : 4;  // FP32 tables for the FP32 and BF16 paths
   for (int p = 0; p < n; ++p) {
     const pd_problem &q = probs[p];
@@ -143,12 +138,13 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.r_items = (M.N * M.K + 15) / 16;  // gradient-reduction blocks of 16 outputs
     const long long n_px = (long long)M.rows * M.W;  // evaluated pixels
     const bool mf = prec == 2;
-    // BF16 matrix-core path: 32-pixel tiles; k16_lse blocks of 16 tiles;
-    // k16_grad waves = pixel chunks x 128-grain groups (about 4096 waves)
-    M.Kp = kp_batch;
+    // BF16 matrix-core path: 32-pixel tiles inside one row (ceil(W / 32) per
+    // row); k16_lse blocks = row segments of 16 tiles; k16_grad waves = pixel
+    // chunks x 64-grain groups
+    const int tw = (M.W + 31) / 32;
     M.n32 = (int)((n_px + 31) / 32 * 32);
-    M.tiles32 = M.n32 / 32;
-    M.a16_items = (M.tiles32 + 15) / 16;
+    M.tiles32 = M.rows * tw;
+    M.a16_items = M.rows * ((tw + 15) / 16);
     M.ggroups = (M.Npad + 32 * PD_MF_GROUP_TILES - 1) / (32 * PD_MF_GROUP_TILES);
     {
       // about target_waves / 2 waves of k16_grad (4 grain groups per block)
@@ -165,14 +161,14 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.tyT = L.take(tsz * M.H * M.DP);
     R.thc = L.take(sizeof(double) * M.N * M.K);
     // FP64 row coefficients and log-sum-exp in both VALU modes
-    // (the BF16 path needs them only for the certified arg-max of a fit)
+    // (the BF16 path needs the coefficients only for the certified arg-max of a fit)
     R.C = L.take(mf && !P.cert ? 0 : sizeof(double) * (size_t)M.rows * M.Npad * M.DP);
     R.lse = L.take(mf ? 0 : sizeof(double) * n_px);
     R.rpix = L.take(mf ? sizeof(float) * (size_t)M.n32 : tsz * n_px);
     R.part_l = L.take(sizeof(double) * std::max(M.a_items, 4 * M.a16_items));
     R.part_g = L.take(mf ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
     R.part_d = L.take(mf || !P.with_diag ? 0 : sizeof(double) * (size_t)M.stiles * M.Npad * M.K);
-    R.part_c = L.take(sizeof(int64_t) * M.a_items);
+    R.part_c = L.take(sizeof(int64_t) * (mf ? std::max(M.a_items, 4 * M.a16_items) : M.a_items));
     const bool cert = P.cert;
     R.cert = L.take(cert ? 32 : 0);  // bound (8), uncertain count (4), canonical count (8)
     R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
@@ -184,14 +180,14 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.order = L.take(R.sorted ? sizeof(int32_t) * M.N : 0);
     R.pos = L.take(R.sorted ? sizeof(int32_t) * M.N : 0);
     R.order_sums = L.take(R.sorted ? 3 * sizeof(int64_t) * M.N : 0);
-    R.T3 = L.take(mf ? 3 * sizeof(uint16_t) * (size_t)M.Npad * M.Kp : 0);
+    R.T3 = L.take(mf ? 3 * 8 * sizeof(uint16_t) * (size_t)M.rows * M.Npad : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
     R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
     P.offA[p + 1] = P.offA[p] + M.a_items;
     P.offB[p + 1] = P.offB[p] + M.b_items;
     P.offP[p + 1] = P.offP[p] + (int)(((long long)M.rows * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
     P.offR[p + 1] = P.offR[p] + M.r_items;
-    P.off16P[p + 1] = P.off16P[p] + (int)(((long long)M.Npad * M.Kp + PD_BLOCK - 1) / PD_BLOCK);
+    P.off16P[p + 1] = P.off16P[p] + (int)(((long long)M.rows * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
     P.off16A[p + 1] = P.off16A[p] + M.a16_items;
     P.off16B[p + 1] = P.off16B[p] + M.b16_items;
     P.off16R[p + 1] = P.off16R[p] + (M.N * M.K + 15) / 16;

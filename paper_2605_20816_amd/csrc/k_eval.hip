@@ -239,63 +239,6 @@ __device__ inline void cert_finish(const MapDev &M, int local, int lane, int r, 
   if (lane == 0) pd_glb(M.part_c)[local] = wc;
 }
 
-// The certified arg-max alone (after the BF16 objective, whose logits are not
-// FP64): FP64 logits, the chunk maxima, the best chunk and an upper bound of the
-// others.
-template <int D>
-PD_HOT_INLINE void argmax_item(const MapDev &M, int local, int lane) {
-  constexpr int DP = D + 1;
-  if (local >= M.rows * M.segs) {
-    if (lane == 0) pd_glb(M.part_c)[local] = 0;
-    return;
-  }
-  const int lr = local / M.segs;
-  const int r = M.row0 + lr;
-  const int c = (local - lr * M.segs) * PD_WAVE + lane;
-  const bool valid = c < M.W;
-  const int cc = valid ? c : M.W - 1;
-  const auto tx = pd_glb(M.tx64 + (size_t)cc * DP);
-  double px[DP];
-#pragma unroll
-  for (int a = 0; a < DP; ++a) px[a] = tx[a];
-  const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
-  const auto Cvec = pd_glb((const double *)M.C + (size_t)lr * M.Npad * DP);
-  int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
-  if (M.pos && g >= 0 && g < M.N) g = pd_glb(M.pos)[g];  // the label's C row
-  double bv = -INFINITY, sv = -INFINITY;
-  int bi = 0;
-  for (int i0 = 0; i0 < M.N; i0 += 8) {
-    double cm = -INFINITY;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const auto cp = Crow + (size_t)(i0 + j) * DP;
-      double v = cp[0];
-#pragma unroll
-      for (int a = 1; a < DP; ++a) v = pd_fma(cp[a], px[a], v);
-      cm = pd_max(cm, v);
-    }
-    const bool gt = cm > bv;
-    sv = gt ? bv : pd_max(sv, cm);
-    bi = gt ? i0 : bi;
-    bv = gt ? cm : bv;
-  }
-  cert_finish<D>(M, local, lane, r, c, valid, g, px, Cvec, bi, sv);
-}
-
-template <int DMAX>
-__global__ __launch_bounds__(PD_BLOCK) void k_cert_argmax(const MapDev *__restrict__ maps,
-                                                          const int32_t *__restrict__ off,
-                                                          int n_maps, int total) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
-  const int lane = threadIdx.x % PD_WAVE;
-  const int item = pd_xcd_block(blockIdx.x, gridDim.x) * PD_WAVES_PER_BLOCK + wave;
-  if (item >= total) return;
-  const int m = pd_find_map(off, n_maps, item);
-  const MapDev &M = maps[m];
-  if (PD_GATED(M)) return;
-  PD_DISPATCH_UPTO(DMAX, M.d, (argmax_item<D>(M, item - off[m], lane)));
-}
-
 // ---------------------------------------------------------------------------
 // Kernel A: per-pixel base-2 log-sum-exp over grains and partial sums of log2 p_G.
 // With CERT, also the hard assignment of every pixel at this theta, certified
@@ -1285,17 +1228,6 @@ void pd_launch_lse(int prec, int dmax, const MapDev *maps, const int32_t *off, i
     case 6: KERNEL<T, 6, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;          \
     default: KERNEL<T, 8, H><<<blocks, PD_BLOCK, 0, s>>>(__VA_ARGS__); break;         \
   }
-void pd_launch_cert_argmax(int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                           int total, hipStream_t s) {
-  const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
-  if (blocks <= 0) return;
-  switch (dmax) {
-    case 2: k_cert_argmax<2><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
-    case 4: k_cert_argmax<4><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
-    case 6: k_cert_argmax<6><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
-    default: k_cert_argmax<8><<<blocks, PD_BLOCK, 0, s>>>(maps, off, n_maps, total); break;
-  }
-}
 void pd_launch_lse_cert(int prec, int dmax, const MapDev *maps, const int32_t *off, int n_maps,
                         int total, hipStream_t s) {
   const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;

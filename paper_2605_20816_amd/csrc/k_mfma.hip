@@ -1,30 +1,40 @@
 // k_mfma.hip -- BF16 matrix-core objective/gradient path (v_mfma_f32_32x32x16_bf16).
 //
 // Logits in base 2, s_i(x) = thc_i . psi(x) with thc = -(log2 e / eps)(theta -
-// mean), are a GEMM with inner dimension K (padded to 16 or 32).  At eps = 1e-3
-// the logits reach |s| ~ 1e3..1e4 while the softmax needs them to ~1e-3, i.e.
-// about 22 significant bits.  Both operands are therefore split into three
-// bf16 pieces (hi + mid + lo, each the rounding of the remainder) and the six
-// products of total order <= 2 (hh, hm, mh, hl, lh, mm) are accumulated in FP32;
-// the dropped terms are below 2^-26 relative.  The gradient contraction
-// sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies values of size <= 1: p - delta
-// as two FP16 pieces against the two FP16 pieces of psi, on
-// v_mfma_f32_32x32x16_f16.  Log-sum-exp in FP32; Phi and grad Phi are summed in
-// FP64 in a fixed order.
+// mean), factor over the rows of the grid (the separable Legendre basis):
+// s_i(r, c) = sum_a C_a(r, i) P_a(x1_c) with C_a(r, i) = sum_b thc_i(a, b) P_b(x2_r),
+// a contraction of inner dimension d + 1 <= 8 per pixel row.  At eps = 1e-3 the
+// logits reach |s| ~ 1e3..1e4 while the softmax needs them to ~1e-3, i.e. about
+// 22 significant bits, so both operands are split into three bf16 pieces (hi +
+// mid + lo, each the rounding of the remainder) and the six products of total
+// order <= 2 (hh, hm, mh, hl, lh, mm) are accumulated in FP32; the dropped terms
+// are below 2^-26 relative.  Since one operand piece fills only half of the
+// instruction's 16-deep inner dimension, each instruction takes two of the six
+// products: the lanes of the first half carry one piece pair, those of the
+// second half another, so a 32 x 32 tile of logits costs three instructions:
+//   [Ym | Yh] x [Xh | Xm] = mh + hm,  [Yl | Yh] x [Xh | Xl] = lh + hl,
+//   [Yh | Ym] x [Xh | Xm] = hh + mm    (Y: row coefficients, X: P_a(x1)).
+// The gradient contraction sum_x (p_i(x) - delta_{i,G(x)}) psi(x) multiplies
+// values of size <= 1: p - delta as two FP16 pieces against the two FP16 pieces
+// of psi, on v_mfma_f32_32x32x16_f16.  Log-sum-exp in FP32; Phi and grad Phi are
+// summed in FP64 in a fixed order.
 //
 // Operand/accumulator lane layout of the 32x32x16 instruction (lane l, half
 // h = l / 32): A[i][k] at lane i + 32 (k / 8), element k % 8; B[k][j] at lane
 // j + 32 (k / 8), element k % 8; D[i][j] at lane j + 32 ((i / 4) % 2),
 // register 4 (i / 8) + i % 4.
 //
-// k16_lse:  block = 4 waves x 4 pixel tiles of 32 pixels; the three pieces of
-//           thc for 128 grains at a time are staged in LDS and shared; S = thc
-//           psi^T puts one pixel per lane column and 16 grains per lane, so the
-//           online max / sum of exp2 stays in-lane (halves merged at the end).
-// k16_grad: wave = (pixel chunk, 64 grains); thc pieces and the 2 x 32 x 32
-//           gradient accumulators stay in registers across the chunk; S^T = psi
-//           thc^T puts one grain per lane column, so p - delta feeds the gradient
-//           product directly as its A operand.
+// Pixel tiles are 32 consecutive pixels of one row (ceil(W / 32) per row, the
+// last one partial), so a tile has one set of row coefficients.
+// k16_lse:  block = one row segment of 16 tiles, tile 4 t + w for wave w; the
+//           pieces of C for 256 grains at a time are staged in LDS and shared;
+//           S = C X^T puts one pixel per lane column and 16 grains per lane, so
+//           the online max / sum of exp2 stays in-lane (halves merged at the end).
+// k16_grad: wave = (pixel chunk, 64 grains); the C pieces of its grains stay in
+//           registers while the chunk stays in one row, and the 2 x 32 x 32
+//           gradient accumulators across the chunk; S^T = X C^T puts one grain
+//           per lane column, so p - delta feeds the gradient product directly as
+//           its A operand.
 #include "pd_host.h"
 
 #include <math.h>
@@ -33,7 +43,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 #define MF_TILES_PER_WAVE 4     // pixel tiles per wave in k16_lse
-#define MF_GRAIN_STAGE 128      // grains staged in LDS per step of k16_lse
+#define MF_SEG_TILES 16         // tiles per k16_lse block (one row segment)
+#define MF_GRAIN_STAGE 256      // grains staged in LDS per step of k16_lse
 
 // Exponents (a, b) of feature k in the degree-graded order (degree <= 8).
 __constant__ signed char c_fa[45] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0,
@@ -44,69 +55,6 @@ __constant__ signed char c_fb[45] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4
                                      0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5, 6, 7, 8};
 
 __device__ inline float bf_to_f(__bf16 h) { return (float)h; }
-
-// Exponents of feature k in the graded order, at compile time.
-__host__ __device__ constexpr int feat_deg(int k) {
-  int d = 0;
-  while ((d + 1) * (d + 2) / 2 <= k) ++d;
-  return d;
-}
-__host__ __device__ constexpr int feat_b(int k) { return k - feat_deg(k) * (feat_deg(k) + 1) / 2; }
-__host__ __device__ constexpr int feat_a(int k) { return feat_deg(k) - feat_b(k); }
-
-// Row and column of flat pixel pbase + o from those of pbase (o < 32).
-__device__ inline void pix_rc(int r0, int c0, int o, int W, int &r, int &c) {
-  c = c0 + o;
-  r = r0;
-  while (c >= W) {
-    c -= W;
-    ++r;
-  }
-}
-
-// P_a(x1) and P_b(x2) of one pixel for a, b <= the largest exponent that the
-// 16 * NKB features need (zero beyond the degree or outside the map).
-template <int NKB>
-struct PixTables {
-  static constexpr int AM = feat_deg(16 * NKB - 1);
-  float px[AM + 1], py[AM + 1];
-};
-template <int NKB>
-__device__ inline void pixel_tables(const MapDev &M, int r, int c, bool valid, PixTables<NKB> &t) {
-  // global (not flat) loads: they must not hold up the LDS waits of the
-  // products that run while they are in flight
-  const auto tx = pd_glb((const float *)M.txT), ty = pd_glb((const float *)M.tyT);
-#pragma unroll
-  for (int a = 0; a <= PixTables<NKB>::AM; ++a) {
-    t.px[a] = (valid && a <= M.d) ? tx[c * M.DP + a] : 0.f;
-    t.py[a] = (valid && a <= M.d) ? ty[r * M.DP + a] : 0.f;
-  }
-}
-// The 8 features of block kb for lane half h: v[kb][e] = psi_{16 kb + 8 h + e}
-// (zero beyond K).
-template <int NKB>
-__device__ inline void feats_from_tables(const MapDev &M, const PixTables<NKB> &t, int half,
-                                         float (&v)[NKB][8]) {
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k0 = 16 * kb + e, k1 = 16 * kb + 8 + e;
-      const float f0 = t.px[feat_a(k0)] * t.py[feat_b(k0)];
-      const float f1 = t.px[feat_a(k1)] * t.py[feat_b(k1)];
-      const float f = half ? f1 : f0;
-      const int k = half ? k1 : k0;
-      v[kb][e] = k < M.K ? f : 0.f;
-    }
-}
-// All 16 * NKB features of one pixel, the 8 of block kb for lane half h.
-template <int NKB>
-__device__ inline void pixel_feats(const MapDev &M, int r, int c, bool valid, int half,
-                                   float (&v)[NKB][8]) {
-  PixTables<NKB> t;
-  pixel_tables<NKB>(M, r, c, valid, t);
-  feats_from_tables<NKB>(M, t, half, v);
-}
 
 // Three-piece split of 8 FP32 values.
 __device__ inline void split3(const float (&v)[8], bf16x8 &h, bf16x8 &m, bf16x8 &l) {
@@ -122,116 +70,186 @@ __device__ inline void split3(const float (&v)[8], bf16x8 &h, bf16x8 &m, bf16x8 
   }
 }
 
-__device__ inline void split2(const float (&v)[8], bf16x8 &h, bf16x8 &l) {
+// The pixel-side operands of one pixel: P_a(x1) for a <= d (zero beyond, and
+// for a pixel outside the row), split in three; xa = [h | m] and xb = [h | l]
+// by lane half.
+__device__ inline void pixel_operands(const MapDev &M, int c, bool valid, int half, bf16x8 &xa,
+                                      bf16x8 &xb) {
+  const auto tx = pd_glb((const float *)M.txT);
+  float v[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 a = (__bf16)v[e];
-    h[e] = a;
-    l[e] = (__bf16)(v[e] - bf_to_f(a));
-  }
+  for (int a = 0; a < 8; ++a) v[a] = (valid && a <= M.d) ? tx[c * M.DP + a] : 0.f;
+  bf16x8 h, m, l;
+  split3(v, h, m, l);
+  xa = half ? m : h;
+  xb = half ? l : h;
 }
 
-// acc += (ah + am + al)(bh + bm + bl) up to second-order terms, small first.
-__device__ inline f32x16 mfma6(const bf16x8 &ah, const bf16x8 &am, const bf16x8 &al,
-                               const bf16x8 &bh, const bf16x8 &bm, const bf16x8 &bl, f32x16 acc) {
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+// acc += the six order <= 2 products of the pieces (small terms first): y1 =
+// [m | h], y2 = [l | h], y3 = [h | m] on the row-coefficient side.
+__device__ inline f32x16 mfma3(const bf16x8 &y1, const bf16x8 &y2, const bf16x8 &y3,
+                               const bf16x8 &xa, const bf16x8 &xb, f32x16 acc, bool y_is_a) {
+  if (y_is_a) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(y2, xb, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(y1, xa, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(y3, xa, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xb, y2, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, y1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, y3, acc, 0, 0, 0);
+  }
   return acc;
 }
 
 // ---------------------------------------------------------------------------
-// thc (FP64, N x K) -> three bf16 pieces [3][Npad][Kp], zero-padded.
+// Rounding bound of grain i's logits for the certified arg-max of a fit: the
+// FP64 row-factorised logits against the canonical scores (as for the FP64
+// objective: 2D + 8 roundings of the row-coefficient form, K + 4 of the canonical
+// dot product, both relative to sum |thc| resp. (log2 e / eps) sum |theta|, with
+// |P_a| <= 1), plus 2^-17 sum |thc| for the matrix-core logits that rank the
+// chunks (piece splitting and dropped products below 2^-24 of sum |thc|, the FP32
+// tables 2^-24, at most 48 FP32 roundings in the three products: < 2^-18.3).
+__device__ inline double cert_bound16(const MapDev &M, int i) {
+  const double *th = M.thc + (size_t)i * M.K;
+  const double *x = M.theta + (size_t)i * M.K;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < M.K; ++k) {
+    a += fabs(th[k]);
+    b += fabs(x[k]);
+  }
+  constexpr double u = 0x1p-53;
+  return 2.0 * ((2 * M.d + 8) * u * a + (PD_LOG2E / M.eps) * (M.K + 4) * u * b) + 0x1p-17 * a;
+}
+
+// Row coefficients C_a(r, i) = sum_b thc_i(a, b) P_b(x2_r) in FP64 for every
+// evaluated row and grain, stored as three bf16 pieces: T3[rr][piece][Npad][8]
+// (zero for a > d and for padding grains).  For the certified arg-max of a fit
+// (M.cert set) also the FP64 values, C[rr][i][a] (a <= d), and, in the blocks of
+// the first row, the largest logit rounding bound over the grains (block
+// maximum, one atomic per block; the fit clears the slot after each evaluation).
 __global__ __launch_bounds__(PD_BLOCK) void k16_prep(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps) {
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
   const long long e = (long long)(blockIdx.x - off[m]) * PD_BLOCK + threadIdx.x;
-  const long long tot = (long long)M.Npad * M.Kp;
-  if (e >= tot) return;
-  const int i = (int)(e / M.Kp), k = (int)(e - (long long)i * M.Kp);
-  const double v = (i < M.N && k < M.K) ? M.thc[(size_t)i * M.K + k] : 0.0;
-  const __bf16 h = (__bf16)(float)v;
-  const double r1 = v - (double)bf_to_f(h);
-  const __bf16 md = (__bf16)(float)r1;
-  const double r2 = r1 - (double)bf_to_f(md);
-  const __bf16 lo = (__bf16)(float)r2;
-  __bf16 *T = (__bf16 *)M.T3;
-  T[e] = h;
-  T[tot + e] = md;
-  T[2 * tot + e] = lo;
+  if (M.cert != nullptr && (long long)(blockIdx.x - off[m]) * PD_BLOCK < M.Npad) {
+    __shared__ double bred[PD_BLOCK];
+    bred[threadIdx.x] = e < M.N ? cert_bound16(M, (int)e) : 0.0;
+    __syncthreads();
+    for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const double o = bred[threadIdx.x + w];
+        // NaN wins (it makes every pixel uncertain, and the canonical pass flags it)
+        if (!(o <= bred[threadIdx.x])) bred[threadIdx.x] = o;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      atomicMax((unsigned long long *)M.cert, (unsigned long long)__double_as_longlong(bred[0]));
+  }
+  if (e >= (long long)M.rows * M.Npad) return;
+  const int rr = (int)(e / M.Npad), i = (int)(e - (long long)rr * M.Npad);
+  double c[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) c[a] = 0.0;
+  if (i < M.N) {
+    const double *py = M.ty64 + (size_t)(M.row0 + rr) * M.DP;
+    const double *th = M.thc + (size_t)i * M.K;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; a + b < 8; ++b)
+        if (a + b <= M.d) c[a] = __builtin_fma(th[(a + b) * (a + b + 1) / 2 + b], py[b], c[a]);
+  }
+  bf16x8 h, md, lo;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double v = c[a];
+    h[a] = (__bf16)(float)v;
+    const double r1 = v - (double)bf_to_f(h[a]);
+    md[a] = (__bf16)(float)r1;
+    lo[a] = (__bf16)(float)(r1 - (double)bf_to_f(md[a]));
+  }
+  bf16x8 *T = (bf16x8 *)M.T3 + (size_t)rr * 3 * M.Npad + i;
+  T[0] = h;
+  T[(size_t)M.Npad] = md;
+  T[(size_t)2 * M.Npad] = lo;
+  if (M.cert != nullptr) {
+    double *C = (double *)M.C + (size_t)e * M.DP;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (a <= M.d) C[a] = c[a];
+  }
 }
 
 // ---------------------------------------------------------------------------
-template <int NKB>
-__device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
+// With CERT, also the hard assignment of every pixel at this theta, certified
+// against the canonical FP64 arg-min (Section 2.1): each lane keeps, per pixel,
+// the largest maximum of its 16-grain chunks (its chunk) and the largest of the
+// other chunks' maxima, from the matrix-core logits; at the end the best chunk's
+// 16 logits are formed again in FP64 from the FP64 row coefficients.  If the
+// best grain leads the runner-up (the chunk's second, the other half's best, or
+// the other chunks' maxima, which bound theirs within the matrix-core error)
+// by more than twice the rounding bound of cert_bound16, the canonical scores
+// have the same strict minimum there; otherwise the pixel is listed for
+// k_assign_list.  Per-wave counts of certified correct pixels go to part_c.
+template <bool CERT>
+__device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
   constexpr int TPW = MF_TILES_PER_WAVE;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
   const int lane = threadIdx.x % PD_WAVE;
   const int half = lane / 32, col = lane % 32;
-  const int Kp = M.Kp;
-  const int tile0 = blk * (4 * TPW) + wave * TPW;
-  // B operands: psi^T of this wave's tiles (pixel = column), three pieces
-  bf16x8 bh[TPW][NKB], bm[TPW][NKB], bl[TPW][NKB];
-  // p: index among the evaluated pixels (rows row0 .. row0 + rows - 1, row-major);
-  // q = pix0 + p: index in the whole map
-  const int npx = M.rows * M.W, pix0 = M.row0 * M.W;
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int p = (tile0 + t) * 32 + col;
-    const int q = pix0 + p;
-    const int r = q / M.W, c = q - r * M.W;
-    float v[NKB][8];
-    pixel_feats<NKB>(M, r, c, p < npx, half, v);
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) split3(v[kb], bh[t][kb], bm[t][kb], bl[t][kb]);
-  }
-  // S sums over the grains other than the pixel's label (r = 1 - p_G, below)
+  const int tw = (M.W + 31) / 32, segs = (tw + MF_SEG_TILES - 1) / MF_SEG_TILES;
+  const int rr = blk / segs, seg = blk - rr * segs;  // evaluated row, segment
+  const int r = M.row0 + rr;
+  // B operands: P_a(x1) of this wave's tiles (pixel = column); tile t holds
+  // columns (seg * 16 + 4 t + wave) * 32 + col
+  bf16x8 xa[TPW], xb[TPW];
   float mrun[TPW], S[TPW];
   int lab[TPW];
+  float bv[TPW], sv[TPW];  // CERT: best chunk maximum, largest other chunk maximum
+  int bi[TPW];             // CERT: grain base of the best chunk
+  int ntile = 0;  // this wave's tiles that start inside the row (wave-uniform)
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
+    const int c0 = (seg * MF_SEG_TILES + 4 * t + wave) * 32;
+    const int c = c0 + col;
+    const bool valid = c < M.W;
+    if (c0 < M.W) ntile = t + 1;
+    pixel_operands(M, c, valid, half, xa[t], xb[t]);
+    // S sums over the grains other than the pixel's label (r = 1 - p_G, below)
     mrun[t] = -INFINITY;
     S[t] = 0.f;
-    const int p = (tile0 + t) * 32 + col;
-    lab[t] = p < npx ? pd_glb(M.labels)[pix0 + p] : -1;
+    bv[t] = -INFINITY;
+    sv[t] = -INFINITY;
+    bi[t] = 0;
+    lab[t] = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
   }
-  const long long tot = (long long)M.Npad * Kp;
-  const __bf16 *T = (const __bf16 *)M.T3;
+  const bf16x8 *T = (const bf16x8 *)M.T3 + (size_t)rr * 3 * M.Npad;
   for (int g0 = 0; g0 < M.Npad; g0 += MF_GRAIN_STAGE) {
     const int gcnt = min(MF_GRAIN_STAGE, M.Npad - g0);
     __syncthreads();
-    // stage the three pieces of grains [g0, g0 + gcnt): sT[piece][g][Kp]
-    const int words = gcnt * Kp / 8;  // 16-byte units per piece
-    for (int w = threadIdx.x; w < 3 * words; w += PD_BLOCK) {
-      const int piece = w / words, q = w - piece * words;
-      const bf16x8 v = *(const bf16x8 *)(T + piece * tot + (size_t)g0 * Kp + (size_t)q * 8);
-      *(bf16x8 *)(sT + (size_t)piece * MF_GRAIN_STAGE * Kp + (size_t)q * 8) = v;
+    // stage the three pieces of grains [g0, g0 + gcnt): sT[piece][g]
+    for (int w = threadIdx.x; w < 3 * gcnt; w += PD_BLOCK) {
+      const int piece = w / gcnt, q = w - piece * gcnt;
+      sT[piece * MF_GRAIN_STAGE + q] = T[(size_t)piece * M.Npad + g0 + q];
     }
     __syncthreads();
+    if (ntile == 0) continue;
     for (int gt = 0; gt < gcnt; gt += 32) {
-      bf16x8 ah[NKB], am[NKB], al[NKB];
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        const size_t o = (size_t)(gt + col) * Kp + kb * 16 + half * 8;
-        ah[kb] = *(const bf16x8 *)(sT + o);
-        am[kb] = *(const bf16x8 *)(sT + (size_t)MF_GRAIN_STAGE * Kp + o);
-        al[kb] = *(const bf16x8 *)(sT + (size_t)2 * MF_GRAIN_STAGE * Kp + o);
-      }
+      const bf16x8 *sg = sT + gt + col;
+      const bf16x8 yh = sg[0], ym = sg[MF_GRAIN_STAGE], yl = sg[2 * MF_GRAIN_STAGE];
+      const bf16x8 y1 = half ? yh : ym, y2 = half ? yh : yl, y3 = half ? ym : yh;
       const int gbase = g0 + gt;
       const bool partial = gbase + 32 > M.N;
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
+        if (t >= ntile) break;
         f32x16 acc;
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb)
-          acc = mfma6(ah[kb], am[kb], al[kb], bh[t][kb], bm[t][kb], bl[t][kb], acc);
+        acc = mfma3(y1, y2, y3, xa[t], xb[t], acc, true);
         if (partial) {
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
@@ -245,6 +263,12 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
         // rows that are all padding grains (-inf) contribute nothing; skipping them
         // also avoids exp2(-inf - (-inf)) while this lane's maximum is still -inf
         if (cm == -INFINITY) continue;
+        if constexpr (CERT) {
+          const bool gt = cm > bv[t];
+          sv[t] = gt ? bv[t] : fmaxf(sv[t], cm);
+          bi[t] = gt ? gbase : bi[t];
+          bv[t] = gt ? cm : bv[t];
+        }
         const float mn = fmaxf(mrun[t], cm);
         float s = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mn);
         if (__ballot((unsigned)(lab[t] - gbase) < 32u) != 0) {
@@ -265,64 +289,121 @@ __device__ inline void lse16_block(const MapDev &M, int blk, __bf16 *sT) {
   }
   // merge the two halves (lanes l and l + 32 hold the same pixel)
   double ell = 0.0;
+  long long n_ok = 0;
+  const double bound =
+      CERT ? __longlong_as_double((long long)*pd_uni((const unsigned long long *)M.cert)) : 0.0;
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
+    if constexpr (CERT) {
+      const int c = (seg * MF_SEG_TILES + 4 * t + wave) * 32 + col;
+      const bool valid = c < M.W;
+      // FP64 logits of this lane's best chunk: grains bi + 8 (j / 4) + 4 half + j % 4
+      double v1 = -INFINITY, v2 = -INFINITY;
+      int j1 = -1;
+      if (valid && bv[t] > -INFINITY) {
+        const double *px = M.tx64 + (size_t)c * M.DP;
+        double pa[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) pa[a] = a <= M.d ? px[a] : 0.0;
+        const double *C = (const double *)M.C + (size_t)rr * M.Npad * M.DP;
+#pragma unroll 1
+        for (int j = 0; j < 16; ++j) {
+          const int g = bi[t] + (j / 4) * 8 + half * 4 + (j % 4);
+          if (g >= M.N) continue;
+          const double *cp = C + (size_t)g * M.DP;
+          double v = cp[0];
+#pragma unroll
+          for (int a = 1; a < 8; ++a)
+            if (a <= M.d) v = __builtin_fma(cp[a], pa[a], v);
+          if (v > v1) {
+            v2 = v1;
+            v1 = v;
+            j1 = g;
+          } else {
+            v2 = fmax(v2, v);
+          }
+        }
+      }
+      const double v1o = __shfl_xor(v1, 32, PD_WAVE), v2o = __shfl_xor(v2, 32, PD_WAVE);
+      const int j1o = __shfl_xor(j1, 32, PD_WAVE);
+      const float svo = __shfl_xor(sv[t], 32, PD_WAVE);
+      const bool mine = v1 >= v1o;
+      const double top = mine ? v1 : v1o;
+      const int jt = mine ? j1 : j1o;
+      const double run = fmax(mine ? v2 : v2o, mine ? v1o : v1);
+      const double others = (double)fmaxf(sv[t], svo);
+      const bool sure = (top - fmax(run, others)) > 2.0 * bound;  // false for NaN
+      const bool act = half == 0 && valid;
+      n_ok += (act && sure && jt == lab[t]) ? 1 : 0;
+      const bool unsure = act && !sure;
+      const unsigned long long um = __ballot(unsure);
+      if (um != 0) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(M.unc_count, __popcll(um));
+        base = __shfl(base, 0, PD_WAVE);
+        const int pos = base + __popcll(um & ((1ull << lane) - 1ull));
+        if (unsure && pos < M.rows * M.W) pd_glb(M.unc_list)[pos] = r * M.W + c;
+      }
+    }
     const float mo = __shfl_xor(mrun[t], 32, PD_WAVE);
     const float so = __shfl_xor(S[t], 32, PD_WAVE);
     const float mm = fmaxf(mrun[t], mo);
     // the other grains' sum (both halves), then the label's own term
     const float sx = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mm) + so * __builtin_amdgcn_exp2f(mo - mm);
-    const int p = (tile0 + t) * 32 + col;
-    if (half == 0 && p < M.n32) {
-      float lse = INFINITY, rr = 0.f;
-      if (p < npx) {
-        const int q = pix0 + p;
-        const int g = lab[t];
-        if (g >= 0 && g < M.N) {
-          // exact FP64 logit of the true grain
-          const int r = q / M.W, c = q - r * M.W;
-          const double *px = M.tx64 + (size_t)c * M.DP, *py = M.ty64 + (size_t)r * M.DP;
-          const double *th = M.thc + (size_t)g * M.K;
-          double sg = 0.0;
-          for (int k = 0; k < M.K; ++k) sg = __builtin_fma(th[k], px[c_fa[k]] * py[c_fb[k]], sg);
-          const float tot = sx + __builtin_amdgcn_exp2f((float)(sg - (double)mm));
-          lse = mm + __builtin_amdgcn_logf(tot);
-          rr = sx / tot;
-          ell += sg - (double)lse;
-        } else {
-          lse = mm + __builtin_amdgcn_logf(sx);
-          ell = NAN;
-        }
+    const int c = (seg * MF_SEG_TILES + 4 * t + wave) * 32 + col;
+    if (half == 0 && c < M.W) {
+      const size_t p = (size_t)rr * M.W + c;  // index among the evaluated pixels
+      float lse, rr_p = 0.f;
+      const int g = lab[t];
+      if (g >= 0 && g < M.N) {
+        // exact FP64 logit of the true grain
+        const double *px = M.tx64 + (size_t)c * M.DP, *py = M.ty64 + (size_t)r * M.DP;
+        const double *th = M.thc + (size_t)g * M.K;
+        double sg = 0.0;
+        for (int k = 0; k < M.K; ++k) sg = __builtin_fma(th[k], px[c_fa[k]] * py[c_fb[k]], sg);
+        const float tot = sx + __builtin_amdgcn_exp2f((float)(sg - (double)mm));
+        lse = mm + __builtin_amdgcn_logf(tot);
+        rr_p = sx / tot;
+        ell += sg - (double)lse;
+      } else {
+        lse = mm + __builtin_amdgcn_logf(sx);
+        ell = NAN;
       }
       pd_glb(M.lse32)[p] = lse;
-      pd_glb((float *)M.rpix)[p] = rr;
+      pd_glb((float *)M.rpix)[p] = rr_p;
     }
   }
   const double tot_l = pd_wave_sum(ell);
   if (lane == 0) pd_glb(M.part_l)[blk * 4 + wave] = tot_l;
+  if constexpr (CERT) {
+    const long long wc = pd_wave_sum_i64(n_ok);
+    if (lane == 0) pd_glb(M.part_c)[blk * 4 + wave] = wc;
+  }
 }
 
-template <int NKB>
+template <bool CERT>
 __global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ maps,
                                                     const int32_t *__restrict__ off, int n_maps,
                                                     int total) {
-  __shared__ __align__(16) __bf16 sT[3 * MF_GRAIN_STAGE * 16 * NKB];
+  __shared__ bf16x8 sT[3 * MF_GRAIN_STAGE];
   if ((int)blockIdx.x >= total) return;
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
-  lse16_block<NKB>(M, blockIdx.x - off[m], sT);
+  lse16_block<CERT>(M, blockIdx.x - off[m], sT);
 }
 
 // ---------------------------------------------------------------------------
 // k16_grad: block = 4 waves on one pixel chunk, wave w on grain group 4 q + w.
 // Per 32-pixel tile the four waves build the shared operands once in LDS (two
 // buffers: tile t + 1 is built while tile t's products run):
-//   sA  [3][NKB][64] x 16 B : psi rows (pixel = row) for the logit product
+//   sX  [2][64]      x 16 B : P_a(x1) pieces [h|m], [h|l] (pixel = row) for the
+//                             logit product
 //   sQ  [2][2][64]   x 16 B : psi^T (feature = column) in FP16 hi/lo for the
 //                             gradient product, inner index h*8+e of block kb2
 //                             = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4
-//   sL, sR, sG [32]         : lse, r = 1 - p_G and label of the tile's pixels
+//   sL, sR, sG [32]         : PD_MF_WSHIFT - lse, r = 1 - p_G and label of the
+//                             tile's pixels
 // The gradient product takes the weight p (other grains) or -r (the pixel's
 // own grain: p - 1 without the cancellation near p = 1) as two FP16 pieces
 // (hi + lo, about 22 bits), scaled by 2^PD_MF_WSHIFT so that small weights stay
@@ -334,7 +415,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 #define PD_MF_WSHIFT 12
 struct GradLds {
-  bf16x8 A[3][2][64];
+  bf16x8 X[2][64];
   f16x8 Q[2][2][64];
   float L[32];
   float R[32];
@@ -342,7 +423,6 @@ struct GradLds {
   int lo, hi;
 };
 
-template <int NKB>
 __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh)[2]) {
   constexpr int GT = PD_MF_GROUP_TILES;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
@@ -354,27 +434,26 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   const bool active = grp < M.ggroups;
   const int g0 = min(grp, M.ggroups - 1) * (GT * 32);
   const int gtn = min(GT, (M.Npad - g0) / 32);
-  const int Kp = M.Kp;
-  const long long tot = (long long)M.Npad * Kp;
-  const __bf16 *T = (const __bf16 *)M.T3;
-  bf16x8 th[GT][NKB], tm[GT][NKB], tl[GT][NKB];
+  const int tw = (M.W + 31) / 32;  // tiles per row
+  // row-coefficient operands of this wave's grains, for the row cur_rr
+  bf16x8 y1[GT], y2[GT], y3[GT];
+  int cur_rr = -1;
+  auto load_rowc = [&](int rr) {
+    const bf16x8 *T = (const bf16x8 *)M.T3 + (size_t)rr * 3 * M.Npad;
 #pragma unroll
-  for (int t = 0; t < GT; ++t) {
-    const int g = min(g0 + t * 32 + col, M.Npad - 1);
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      const size_t o = (size_t)g * Kp + kb * 16 + half * 8;
-      th[t][kb] = *(const bf16x8 *)(T + o);
-      tm[t][kb] = *(const bf16x8 *)(T + tot + o);
-      tl[t][kb] = *(const bf16x8 *)(T + 2 * tot + o);
+    for (int t = 0; t < GT; ++t) {
+      const int g = min(g0 + t * 32 + col, M.Npad - 1);
+      const bf16x8 yh = T[g], ym = T[(size_t)M.Npad + g], yl = T[(size_t)2 * M.Npad + g];
+      y1[t] = half ? yh : ym;
+      y2[t] = half ? yh : yl;
+      y3[t] = half ? ym : yh;
     }
-  }
+  };
   f32x16 accg[GT];
 #pragma unroll
   for (int t = 0; t < GT; ++t)
 #pragma unroll
     for (int j = 0; j < 16; ++j) accg[t][j] = 0.f;
-  const int npx = M.rows * M.W, pix0 = M.row0 * M.W;  // evaluated pixels, first one
   const int pt0 = chunk * M.chunk_tiles;
   const int pt1 = min(pt0 + M.chunk_tiles, M.tiles32);
   const int fcol = col < M.K ? col : 0;
@@ -382,59 +461,37 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   const bool fvalid = col < M.K;
   const float *txf = (const float *)M.txT, *tyf = (const float *)M.tyT;
   auto compute_tile = [&](const GradLds &S) {
-    bf16x8 ph[NKB], pm[NKB], pl[NKB];
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      ph[kb] = S.A[0][kb][lane];
-      pm[kb] = S.A[1][kb][lane];
-      pl[kb] = S.A[2][kb][lane];
-    }
-    float lrow[16];
-    int grow[16];
+    const bf16x8 xa = S.X[0][lane], xb = S.X[1][lane];
+    // the logit accumulators start at the pixel's PD_MF_WSHIFT - lse (S.L), so
+    // the products leave s - lse + PD_MF_WSHIFT and exp2 gives the weight p
+    // scaled by 2^PD_MF_WSHIFT directly
+    f32x16 acc[GT];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        lrow[4 * b + r] = S.L[8 * b + 4 * half + r];
-        grow[4 * b + r] = S.G[8 * b + 4 * half + r];
+        const float l0 = S.L[8 * b + 4 * half + r];
+#pragma unroll
+        for (int t = 0; t < GT; ++t) acc[t][4 * b + r] = l0;
       }
-    constexpr float wscale = (float)(1 << PD_MF_WSHIFT);
-    f32x16 acc[GT];
+#pragma unroll
+    for (int t = 0; t < GT; ++t) acc[t] = mfma3(y1[t], y2[t], y3[t], xa, xb, acc[t], false);
 #pragma unroll
     for (int t = 0; t < GT; ++t)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[t][j] = 0.f;
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pm[kb], tm[t][kb], acc[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl[kb], th[t][kb], acc[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], tl[t][kb], acc[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pm[kb], th[t][kb], acc[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], tm[t][kb], acc[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph[kb], th[t][kb], acc[t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < GT; ++t)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]) * wscale;
+      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j]);
     if (S.hi >= g0 && S.lo < g0 + GT * 32) {
-      float rrow[16];
+      constexpr float wscale = (float)(1 << PD_MF_WSHIFT);
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) rrow[4 * b + r] = S.R[8 * b + 4 * half + r];
+        for (int r = 0; r < 4; ++r) {
+          const int gr = S.G[8 * b + 4 * half + r];
+          const float rv = -S.R[8 * b + 4 * half + r] * wscale;
 #pragma unroll
-      for (int t = 0; t < GT; ++t) {
-        const int grain = g0 + t * 32 + col;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[t][j] = (grow[j] == grain) ? -rrow[j] * wscale : acc[t][j];
-      }
+          for (int t = 0; t < GT; ++t)
+            acc[t][4 * b + r] = (gr == g0 + t * 32 + col) ? rv : acc[t][4 * b + r];
+        }
     }
 #pragma unroll
     for (int kb2 = 0; kb2 < 2; ++kb2) {
@@ -444,13 +501,14 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
       for (int t = 0; t < GT; ++t)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          // the weight rounded to FP32, then split into two FP16 pieces (as above,
-          // no fused form)
-          float q = acc[t][8 * kb2 + e];
-          asm volatile("" : "+v"(q));
-          const _Float16 h = (_Float16)q;
-          x[t][e] = h;
-          xl[t][e] = (_Float16)(q - (float)h);
+          // two FP16 pieces of the FP32 weight: the high one is the weight with
+          // its 13 low significand bits cleared (11 bits, exact in FP16 for
+          // |q| <= 2^12 down to 2^-14), the low one the exact FP32 remainder
+          // rounded to FP16
+          const float q = acc[t][8 * kb2 + e];
+          const float qh = __uint_as_float(__float_as_uint(q) & 0xffffe000u);
+          x[t][e] = (_Float16)qh;
+          xl[t][e] = (_Float16)(q - qh);
         }
       // (w_hi + w_lo)(psi_hi + psi_lo) without w_lo psi_lo, small terms first
 #pragma unroll
@@ -461,46 +519,49 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
       for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], qh, accg[t], 0, 0, 0);
     }
   };
-  // Per tile the waves' roles: wave 0 the psi rows, waves 1-2 the psi^T pieces,
-  // wave 3 lse and labels.  The global data of tile pt + 1 is loaded before tile
-  // pt's products and written to the other LDS buffer after them, so one
-  // barrier per tile separates building from use.
-  PixTables<NKB> tab;     // wave 0
+  // Per tile the waves' roles: wave 0 the P_a(x1) pieces, waves 1-2 the psi^T
+  // pieces, wave 3 lse and labels.  The global data of tile pt + 1 is loaded
+  // before tile pt's products and written to the other LDS buffer after them, so
+  // one barrier per tile separates building from use.
+  float vx[8];            // wave 0
   float qx[8], qy[8];     // waves 1-2
   float lse_l = 0.f;      // wave 3 (lanes < 32)
   float r_l = 0.f;
   int lab_l = -1;
   auto load_tile = [&](int pt) {
-    const int pbase = pt * 32;
-    const int r0 = (pix0 + pbase) / M.W, c0 = pix0 + pbase - r0 * M.W;
+    const int rr = pt / tw;
+    const int c0 = (pt - rr * tw) * 32;
+    const int r = M.row0 + rr;
     if (wave == 0) {
-      int r, c;
-      pix_rc(r0, c0, col, M.W, r, c);
-      pixel_tables<NKB>(M, r, c, pbase + col < npx, tab);
+      const int c = c0 + col;
+      const bool ok = c < M.W;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) vx[a] = (ok && a <= M.d) ? pd_glb(txf)[c * M.DP + a] : 0.f;
     } else if (wave <= 2) {
       const int kb2 = wave - 1;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int o = 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
-        int r, c;
-        pix_rc(r0, c0, o, M.W, r, c);
-        const bool ok = fvalid && pbase + o < npx;
+        const int c = c0 + 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
+        const bool ok = fvalid && c < M.W;
         qx[e] = ok ? pd_glb(txf)[c * M.DP + fa] : 0.f;
         qy[e] = ok ? pd_glb(tyf)[r * M.DP + fb] : 0.f;
       }
     } else if (lane < 32) {
-      const int p = pbase + lane;
-      lse_l = pd_glb(M.lse32)[p];
-      r_l = pd_glb((const float *)M.rpix)[p];
-      lab_l = p < npx ? pd_glb(M.labels)[pix0 + p] : -1;
+      const int c = c0 + lane;
+      const bool ok = c < M.W;
+      const size_t p = (size_t)rr * M.W + c;
+      // pixels past the row's end: lse = +inf gives them weight 0
+      lse_l = ok ? pd_glb(M.lse32)[p] : INFINITY;
+      r_l = ok ? pd_glb((const float *)M.rpix)[p] : 0.f;
+      lab_l = ok ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
     }
   };
   auto build_tile = [&](GradLds &S) {
     if (wave == 0) {
-      float v[NKB][8];
-      feats_from_tables<NKB>(M, tab, half, v);
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) split3(v[kb], S.A[0][kb][lane], S.A[1][kb][lane], S.A[2][kb][lane]);
+      bf16x8 h, m, l;
+      split3(vx, h, m, l);
+      S.X[0][lane] = half ? m : h;
+      S.X[1][lane] = half ? l : h;
     } else if (wave <= 2) {
       const int kb2 = wave - 1;
       f16x8 qh, ql;
@@ -520,7 +581,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     } else {
       int g = -1, lo = 0x7fffffff, hi = -1;
       if (lane < 32) {
-        S.L[lane] = lse_l;
+        S.L[lane] = (float)PD_MF_WSHIFT - lse_l;
         S.R[lane] = r_l;
         g = lab_l;
         S.G[lane] = g;
@@ -543,6 +604,11 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   }
   for (int pt = pt0; pt < pt1; ++pt) {
     GradLds &cur = sh[(pt - pt0) & 1];
+    const int rr = pt / tw;
+    if (active && rr != cur_rr) {
+      load_rowc(rr);  // the chunk entered a new row (in flight across the barrier)
+      cur_rr = rr;
+    }
     if (pt + 1 < pt1) load_tile(pt + 1);
     __syncthreads();  // cur is built; the other buffer's readers (tile pt - 1) are done
     if (active) {
@@ -565,7 +631,6 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   }
 }
 
-template <int NKB>
 __global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
                                                      int total) {
@@ -574,7 +639,7 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ 
   const int m = pd_find_map(off, n_maps, blockIdx.x);
   const MapDev &M = maps[m];
   if (PD_GATED(M)) return;
-  grad16_block<NKB>(M, blockIdx.x - off[m], sh);
+  grad16_block(M, blockIdx.x - off[m], sh);
 }
 
 // Phi from the per-wave partials, grad from the chunk partials (fixed order).
@@ -622,22 +687,18 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict_
 // ---------------------------------------------------------------------------
 // Host side.
 
-static int nkb_for(int dmax) { return dmax <= 4 ? 1 : 2; }
-
 void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
-  const int nkb = nkb_for(P.dmax);
   if (stage == 0) {
-    k16_prep<<<P.off16P[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16P, P.n);
+    if (P.off16P[P.n] > 0) k16_prep<<<P.off16P[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16P, P.n);
   } else if (stage == 1) {
     const int total = P.off16A[P.n];
     if (total <= 0) return;  // no rows to evaluate (empty row bands)
-    if (nkb == 1) k16_lse<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
-    else k16_lse<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
+    if (P.cert) k16_lse<true><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
+    else k16_lse<false><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16A, P.n, total);
   } else if (stage == 2) {
     const int total = P.off16B[P.n];  // blocks: chunks x ceil(grain groups / 4)
     if (total <= 0) return;
-    if (nkb == 1) k16_grad<1><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
-    else k16_grad<2><<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
+    k16_grad<<<total, PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16B, P.n, total);
   } else {
     k16_reduce<<<P.n + P.off16R[P.n], PD_BLOCK, 0, s>>>(P.d_maps, P.d_off16R, P.n);
   }
@@ -646,13 +707,8 @@ void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
 void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   for (int st = 0; st < 4; ++st) pd_bf16_launch(P, st, s);
-  if (P.cert) {
-    // the certified arg-max of every pixel (FP64 row coefficients), as in the
-    // FP64 evaluation of a fit
-    pd_launch_prep(0, P.d_maps, P.d_offP, P.n, P.offP[P.n], s);
-    pd_launch_cert_argmax(P.dmax, P.d_maps, P.d_offA, P.n, P.offA[P.n], s);
-    pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
-  }
+  // the pixels that the certified arg-max of k16_lse left undecided
+  if (P.cert) pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
 }
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,

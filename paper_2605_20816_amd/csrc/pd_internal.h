@@ -95,12 +95,12 @@ struct MapDev {
   const int32_t *gate;
   // FP32 row table and the BF16 matrix-core path
   void *tyT;                        // [H][DP] P_b(x2) in the evaluation type
-  void *T3;                         // [3][Npad][Kp] bf16 pieces of thc
-  float *lse32;                     // [n32] base-2 log-sum-exp of the evaluated pixels
-                                    // (+inf on padding pixels)
+  void *T3;                         // [rows][3][Npad][8] bf16 pieces of the row
+                                    // coefficients C_a (a <= d, zero beyond)
+  float *lse32;                     // [rows * W] base-2 log-sum-exp of the evaluated pixels
   float *part_g32;                  // [chunks][Npad][32] partial gradient moments
-  int32_t Kp, n32, tiles32;         // feature width of the BF16 pieces; evaluated pixels
-                                    // rounded up to 32; 32-pixel tiles
+  int32_t n32, tiles32;             // evaluated pixels rounded up to 32; 32-pixel
+                                    // tiles (ceil(W / 32) per row)
   int32_t a16_items, b16_items;     // blocks of k16_lse; waves of k16_grad
   int32_t chunk_tiles, chunks, ggroups;
   // Hessian diagonal sum_x p_i (1 - p_i) psi_k^2 / (eps^2 n) of -Phi (eq. hess),
@@ -279,6 +279,4 @@ void pd_launch_hvp(int prec, int dmax, const MapDev *maps, const int32_t *off_p,
                    const int32_t *off_a, const int32_t *off_b, int n_maps, int blocks_p,
                    int total_a, int total_b, hipStream_t s);
 // The certified arg-max pass alone (FP64 row coefficients from k_prep).
-void pd_launch_cert_argmax(int dmax, const MapDev *maps, const int32_t *off, int n_maps,
-                           int total, hipStream_t s);
 void pd_launch_validate(const MapDev *maps, int n_maps, int32_t *bad, hipStream_t s);

@@ -112,6 +112,26 @@ def test_fp32_fit_reaches_99(pd, orc):
     assert rep["status"] == "target"
     _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
     assert nc / (gm.H * gm.W) >= 0.99
+    assert nc / (gm.H * gm.W) == rep["acc"]
+
+
+@pytest.mark.parametrize("d,eps,iters", [(6, 1e-3, 25), (4, 1e-3, 60), (3, 1e-2, 40)])
+def test_bf16_fit_accuracy_is_the_canonical_one(pd, orc, d, eps, iters):
+    """The accuracy a BF16 fit reports is certified inside the matrix-core
+    objective (chunk maxima of the matrix-core logits, the best chunk again in
+    FP64, the undecided pixels by the canonical arg-min): it is exactly the
+    oracle's count at the returned iterate, early in the fit (many close logits)
+    and later."""
+    pdl, ctx = pd
+    gm = poly_map(70 + d, 96, 80, 40, d)
+    K = pdl.num_features(d)
+    th = dev(np.zeros((gm.N, K)))
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "bf16", init="zero", max_iter=iters,
+                  target_acc=2.0)[0]
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, d, gm.labels)
+    print(f"d={d} eps={eps}: {rep['iters']} iterations, accuracy {rep['acc']:.4f}")
+    assert rep["iters"] > 0
+    assert nc / (gm.H * gm.W) == rep["acc"]
 
 
 def test_nonseparable_fit_matches_newton(pd, orc):
@@ -184,6 +204,26 @@ def test_bf16_fit_reaches_99(pd, orc):
     assert rep["status"] == "target"
     _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, 1, gm.labels)
     assert nc / (gm.H * gm.W) >= 0.99
+    assert nc / (gm.H * gm.W) == rep["acc"]
+
+
+@pytest.mark.parametrize("d,eps,iters", [(6, 1e-3, 25), (4, 1e-3, 60), (3, 1e-2, 40)])
+def test_bf16_fit_accuracy_is_the_canonical_one(pd, orc, d, eps, iters):
+    """The accuracy a BF16 fit reports is certified inside the matrix-core
+    objective (chunk maxima of the matrix-core logits, the best chunk again in
+    FP64, the undecided pixels by the canonical arg-min): it is exactly the
+    oracle's count at the returned iterate, early in the fit (many close logits)
+    and later."""
+    pdl, ctx = pd
+    gm = poly_map(70 + d, 96, 80, 40, d)
+    K = pdl.num_features(d)
+    th = dev(np.zeros((gm.N, K)))
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "bf16", init="zero", max_iter=iters,
+                  target_acc=2.0)[0]
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, d, gm.labels)
+    print(f"d={d} eps={eps}: {rep['iters']} iterations, accuracy {rep['acc']:.4f}")
+    assert rep["iters"] > 0
+    assert nc / (gm.H * gm.W) == rep["acc"]
 
 
 def test_given_start_is_moved_into_the_gauge(pd, orc):
