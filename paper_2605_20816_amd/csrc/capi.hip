@@ -147,12 +147,14 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     M.a16_items = M.rows * ((tw + 15) / 16);
     M.ggroups = (M.Npad + 32 * PD_MF_GROUP_TILES - 1) / (32 * PD_MF_GROUP_TILES);
     {
-      // about target_waves / 2 waves of k16_grad (4 grain groups per block)
+      // about target_waves / 2 waves of k16_grad (4 grain groups per block), in
+      // chunks of whole rows (its gradient partials are per row)
       long long ct = (long long)M.tiles32 * ((M.ggroups + 3) / 4 * 4) / std::max(1, P.target_waves / 2);
-      if (ct > M.tiles32) ct = M.tiles32;
-      if (ct < 1) ct = 1;
-      M.chunk_tiles = (int)ct;
-      M.chunks = (M.tiles32 + M.chunk_tiles - 1) / M.chunk_tiles;  // 0 for no pixels
+      long long cr = (ct + tw / 2) / tw;
+      if (cr > M.rows) cr = M.rows;
+      if (cr < 1) cr = 1;
+      M.chunk_tiles = (int)cr * tw;
+      M.chunks = (M.rows + (int)cr - 1) / (int)cr;  // 0 for no rows
     }
     M.b16_items = M.chunks * ((M.ggroups + 3) / 4);  // k16_grad blocks
     R.tx64 = L.take(sizeof(double) * M.W * M.DP);
@@ -182,7 +184,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     R.order_sums = L.take(R.sorted ? 3 * sizeof(int64_t) * M.N : 0);
     R.T3 = L.take(mf ? 3 * 8 * sizeof(uint16_t) * (size_t)M.rows * M.Npad : 0);
     R.lse32 = L.take(mf ? sizeof(float) * M.n32 : 0);
-    R.part_g32 = L.take(mf ? sizeof(float) * (size_t)M.chunks * M.Npad * 32 : 0);
+    R.part_g32 = L.take(mf ? sizeof(float) * 8 * (size_t)M.rows * M.Npad : 0);
     P.offA[p + 1] = P.offA[p] + M.a_items;
     P.offB[p + 1] = P.offB[p] + M.b_items;
     P.offP[p + 1] = P.offP[p] + (int)(((long long)M.rows * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
@@ -190,7 +192,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     P.off16P[p + 1] = P.off16P[p] + (int)(((long long)M.rows * M.Npad + PD_BLOCK - 1) / PD_BLOCK);
     P.off16A[p + 1] = P.off16A[p] + M.a16_items;
     P.off16B[p + 1] = P.off16B[p] + M.b16_items;
-    P.off16R[p + 1] = P.off16R[p] + (M.N * M.K + 15) / 16;
+    P.off16R[p + 1] = P.off16R[p] + (M.N + 7) / 8;
     M.a_off = P.offA[p];
     M.b_off = P.offB[p];
     M.r_off = P.offR[p];

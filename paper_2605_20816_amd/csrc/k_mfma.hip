@@ -30,11 +30,13 @@
 //           pieces of C for 256 grains at a time are staged in LDS and shared;
 //           S = C X^T puts one pixel per lane column and 16 grains per lane, so
 //           the online max / sum of exp2 stays in-lane (halves merged at the end).
-// k16_grad: wave = (pixel chunk, 64 grains); the C pieces of its grains stay in
-//           registers while the chunk stays in one row, and the 2 x 32 x 32
-//           gradient accumulators across the chunk; S^T = X C^T puts one grain
-//           per lane column, so p - delta feeds the gradient product directly as
-//           its A operand.
+// k16_grad: wave = (chunk of whole rows, 64 grains); the C pieces of its grains
+//           stay in registers while the chunk stays in one row; S^T = X C^T puts
+//           one grain per lane column, so p - delta feeds the gradient product
+//           directly as its A operand.  The gradient factors over the rows too:
+//           per row G_i(r, a) = sum_c (p - delta)_i(r, c) P_a(x1_c) (inner
+//           dimension = pixels, 8 columns a), written per row; k16_reduce forms
+//           grad_(a, b) = sum_r P_b(x2_r) G_i(r, a) in FP64.
 #include "pd_host.h"
 
 #include <math.h>
@@ -399,18 +401,21 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ m
 // buffers: tile t + 1 is built while tile t's products run):
 //   sX  [2][64]      x 16 B : P_a(x1) pieces [h|m], [h|l] (pixel = row) for the
 //                             logit product
-//   sQ  [2][2][64]   x 16 B : psi^T (feature = column) in FP16 hi/lo for the
-//                             gradient product, inner index h*8+e of block kb2
-//                             = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4
-//   sL, sR, sG [32]         : PD_MF_WSHIFT - lse, r = 1 - p_G and label of the
+//   sQ  [2][2][64]   x 16 B : P_a(x1) of the tile's pixels as the B operands of
+//                             the gradient product, per 16-pixel block kb2 (inner
+//                             index h*8+e = pixel 16 kb2 + 8 (e / 4) + 4 h + e % 4):
+//                             columns [P_hi | P_lo | 0 | 0] and [0 | 0 | P_hi | 0]
+//                             (8 columns a each, FP16 pieces)
+//   sL, sR, sG [32]         : lse - PD_MF_WSHIFT, r = 1 - p_G and label of the
 //                             tile's pixels
 // The gradient product takes the weight p (other grains) or -r (the pixel's
 // own grain: p - 1 without the cancellation near p = 1) as two FP16 pieces
 // (hi + lo, about 22 bits), scaled by 2^PD_MF_WSHIFT so that small weights stay
-// normal, against the two FP16 pieces of psi (three products: the lo x lo term is
-// below 2^-22); the scale is taken out of the FP32 partial sums.  One FP16 piece
-// (2^-12 relative per weight) put the gradient at a fitted iterate, where p - delta
-// cancels most, at the edge of a 2e-3 tolerance.
+// normal, against the two FP16 pieces of P_a: w_hi P_hi and w_hi P_lo in one
+// instruction (columns 0-7 and 8-15), w_lo P_hi in another (columns 16-23); the
+// three column groups are added at the end of each row and the scale taken out.
+// One FP16 piece (2^-12 relative per weight) put the gradient at a fitted
+// iterate, where p - delta cancels most, at the edge of a 2e-3 tolerance.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 #define PD_MF_WSHIFT 12
@@ -456,30 +461,31 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     for (int j = 0; j < 16; ++j) accg[t][j] = 0.f;
   const int pt0 = chunk * M.chunk_tiles;
   const int pt1 = min(pt0 + M.chunk_tiles, M.tiles32);
-  const int fcol = col < M.K ? col : 0;
-  const int fa = c_fa[fcol], fb = c_fb[fcol];
-  const bool fvalid = col < M.K;
-  const float *txf = (const float *)M.txT, *tyf = (const float *)M.tyT;
+  // this lane's column of the gradient product: a = col % 8 in group col / 8
+  const int qa = col & 7, qgrp = col >> 3;
+  const bool qvalid = qgrp < 3 && qa <= M.d;
+  const float *txf = (const float *)M.txT;
   auto compute_tile = [&](const GradLds &S) {
     const bf16x8 xa = S.X[0][lane], xb = S.X[1][lane];
-    // the logit accumulators start at the pixel's PD_MF_WSHIFT - lse (S.L), so
-    // the products leave s - lse + PD_MF_WSHIFT and exp2 gives the weight p
-    // scaled by 2^PD_MF_WSHIFT directly
-    f32x16 acc[GT];
+    // the logits exactly as k16_lse formed them (the same products from zero, so
+    // that the weights are those of its log-sum-exp); S.L holds lse - PD_MF_WSHIFT
+    // (exact in FP32), so exp2 gives the weight p scaled by 2^PD_MF_WSHIFT
+    float lrow[16];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float l0 = S.L[8 * b + 4 * half + r];
+      for (int r = 0; r < 4; ++r) lrow[4 * b + r] = S.L[8 * b + 4 * half + r];
+    f32x16 acc[GT];
 #pragma unroll
-        for (int t = 0; t < GT; ++t) acc[t][4 * b + r] = l0;
-      }
+    for (int t = 0; t < GT; ++t) {
 #pragma unroll
-    for (int t = 0; t < GT; ++t) acc[t] = mfma3(y1[t], y2[t], y3[t], xa, xb, acc[t], false);
+      for (int j = 0; j < 16; ++j) acc[t][j] = 0.f;
+      acc[t] = mfma3(y1[t], y2[t], y3[t], xa, xb, acc[t], false);
+    }
 #pragma unroll
     for (int t = 0; t < GT; ++t)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j]);
+      for (int j = 0; j < 16; ++j) acc[t][j] = __builtin_amdgcn_exp2f(acc[t][j] - lrow[j]);
     if (S.hi >= g0 && S.lo < g0 + GT * 32) {
       constexpr float wscale = (float)(1 << PD_MF_WSHIFT);
 #pragma unroll
@@ -495,7 +501,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     }
 #pragma unroll
     for (int kb2 = 0; kb2 < 2; ++kb2) {
-      const f16x8 qh = S.Q[kb2][0][lane], ql = S.Q[kb2][1][lane];
+      const f16x8 qa_op = S.Q[kb2][0][lane], qb = S.Q[kb2][1][lane];
       f16x8 x[GT], xl[GT];
 #pragma unroll
       for (int t = 0; t < GT; ++t)
@@ -511,12 +517,11 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
           xl[t][e] = (_Float16)(q - qh);
         }
       // (w_hi + w_lo)(psi_hi + psi_lo) without w_lo psi_lo, small terms first
+      // w_lo P_hi (columns 16-23), then w_hi P_hi and w_hi P_lo (columns 0-15)
 #pragma unroll
-      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xl[t], qh, accg[t], 0, 0, 0);
+      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xl[t], qb, accg[t], 0, 0, 0);
 #pragma unroll
-      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], ql, accg[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], qh, accg[t], 0, 0, 0);
+      for (int t = 0; t < GT; ++t) accg[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x[t], qa_op, accg[t], 0, 0, 0);
     }
   };
   // Per tile the waves' roles: wave 0 the P_a(x1) pieces, waves 1-2 the psi^T
@@ -524,7 +529,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   // before tile pt's products and written to the other LDS buffer after them, so
   // one barrier per tile separates building from use.
   float vx[8];            // wave 0
-  float qx[8], qy[8];     // waves 1-2
+  float qx[8];            // waves 1-2
   float lse_l = 0.f;      // wave 3 (lanes < 32)
   float r_l = 0.f;
   int lab_l = -1;
@@ -542,9 +547,8 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = c0 + 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
-        const bool ok = fvalid && c < M.W;
-        qx[e] = ok ? pd_glb(txf)[c * M.DP + fa] : 0.f;
-        qy[e] = ok ? pd_glb(tyf)[r * M.DP + fb] : 0.f;
+        const bool ok = qvalid && c < M.W;
+        qx[e] = ok ? pd_glb(txf)[c * M.DP + qa] : 0.f;
       }
     } else if (lane < 32) {
       const int c = c0 + lane;
@@ -564,24 +568,23 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
       S.X[1][lane] = half ? l : h;
     } else if (wave <= 2) {
       const int kb2 = wave - 1;
-      f16x8 qh, ql;
+      f16x8 qa8, qb8;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        // psi in FP32 first, then its two FP16 pieces (the empty asm keeps the
-        // product from being folded into a mixed-precision FMA that would round
-        // it to FP16 once, without the FP32 step)
-        float v = qx[e] * qy[e];
-        asm volatile("" : "+v"(v));
+        // the two FP16 pieces of the FP32 table value P_a(x1)
+        const float v = qx[e];
         const _Float16 h = (_Float16)v;
-        qh[e] = h;
-        ql[e] = (_Float16)(v - (float)h);
+        const _Float16 l = (_Float16)(v - (float)h);
+        const _Float16 z = (_Float16)0.f;
+        qa8[e] = qgrp == 0 ? h : (qgrp == 1 ? l : z);
+        qb8[e] = qgrp == 2 ? h : z;
       }
-      S.Q[kb2][0][lane] = qh;
-      S.Q[kb2][1][lane] = ql;
+      S.Q[kb2][0][lane] = qa8;
+      S.Q[kb2][1][lane] = qb8;
     } else {
       int g = -1, lo = 0x7fffffff, hi = -1;
       if (lane < 32) {
-        S.L[lane] = (float)PD_MF_WSHIFT - lse_l;
+        S.L[lane] = lse_l - (float)PD_MF_WSHIFT;
         S.R[lane] = r_l;
         g = lab_l;
         S.G[lane] = g;
@@ -602,6 +605,23 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     load_tile(pt0);
     build_tile(sh[0]);
   }
+  // G of row rr for this wave's grains: column groups added (lanes col, col + 8,
+  // col + 16), the scale taken out, written by the lanes col < 8; then cleared
+  auto flush_row = [&](int rr) {
+    float *out = M.part_g32 + (size_t)rr * M.Npad * 8;
+#pragma unroll
+    for (int t = 0; t < GT; ++t) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const float v = accg[t][j];
+        const float s1 = __shfl_down(v, 8, PD_WAVE), s2 = __shfl_down(v, 16, PD_WAVE);
+        const int g = g0 + t * 32 + (j / 4) * 8 + half * 4 + (j % 4);
+        if (col < 8 && t < gtn)
+          pd_glb(out)[(size_t)g * 8 + col] = ((v + s1) + s2) * (1.f / (float)(1 << PD_MF_WSHIFT));
+        accg[t][j] = 0.f;
+      }
+    }
+  };
   for (int pt = pt0; pt < pt1; ++pt) {
     GradLds &cur = sh[(pt - pt0) & 1];
     const int rr = pt / tw;
@@ -613,21 +633,9 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     __syncthreads();  // cur is built; the other buffer's readers (tile pt - 1) are done
     if (active) {
       compute_tile(cur);
+      if (pt + 1 == pt1 || (pt + 1) / tw != rr) flush_row(rr);  // the row's last tile
     }
     if (pt + 1 < pt1) build_tile(sh[(pt - pt0 + 1) & 1]);
-  }
-  if (!active) return;
-  // accg[t]: rows = grains g0 + 32 t + (8 b + 4 h + r), column = feature col
-  const int FW = 32;
-  float *out = M.part_g32 + (size_t)chunk * M.Npad * FW;
-#pragma unroll
-  for (int t = 0; t < GT; ++t) {
-    if (t >= gtn) break;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int g = g0 + t * 32 + (j / 4) * 8 + half * 4 + (j % 4);
-      pd_glb(out)[(size_t)g * FW + col] = accg[t][j] * (1.f / (float)(1 << PD_MF_WSHIFT));
-    }
   }
 }
 
@@ -642,7 +650,9 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ 
   grad16_block(M, blockIdx.x - off[m], sh);
 }
 
-// Phi from the per-wave partials, grad from the chunk partials (fixed order).
+// Phi from the per-wave partials; grad_(a, b) of grain i = sum_r P_b(x2_r)
+// G_i(r, a) in FP64 from the row partials: block = 8 grains x 32 row phases
+// (rows r = phase mod 32 in order, then a fixed butterfly over the phases).
 __global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict__ maps,
                                                        const int32_t *__restrict__ off, int n_maps) {
   if ((int)blockIdx.x < n_maps) {
@@ -664,24 +674,34 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict_
   const int m = pd_find_map(off, n_maps, b);
   const MapDev &M = maps[m];
   if (M.grad == nullptr || PD_GATED(M)) return;
-  // 16 consecutive outputs x 16 chunk phases; phase sums added by a fixed tree
-  __shared__ double red[16][17];
-  const int ol = threadIdx.x % 16, ph = threadIdx.x / 16;
-  const int o = (b - off[m]) * 16 + ol;
-  double s = 0.0;
-  if (o < M.N * M.K) {
-    const int i = o / M.K, k = o - i * M.K;
-    const size_t stride = (size_t)M.Npad * 32;
-    const auto src = pd_glb(M.part_g32 + (size_t)i * 32 + k);
-    for (int c = ph; c < M.chunks; c += 16) s += (double)src[(size_t)c * stride];
+  const int i = (b - off[m]) * 8 + (int)threadIdx.x / 32, ph = threadIdx.x % 32;
+  double acc[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) acc[k] = 0.0;
+  if (i < M.N) {
+    for (int rr = ph; rr < M.rows; rr += 32) {
+      typedef float f32x4 __attribute__((ext_vector_type(4)));
+      const auto gp = pd_glb((const f32x4 *)(M.part_g32 + ((size_t)rr * M.Npad + i) * 8));
+      const f32x4 ga = gp[0], gb = gp[1];
+      const float gv[8] = {ga[0], ga[1], ga[2], ga[3], gb[0], gb[1], gb[2], gb[3]};
+      const double *py = M.ty64 + (size_t)(M.row0 + rr) * M.DP;
+#pragma unroll
+      for (int a = 0; a < 7; ++a)
+#pragma unroll
+        for (int bb = 0; a + bb < 7; ++bb)
+          if (a + bb <= M.d) {
+            const int k = (a + bb) * (a + bb + 1) / 2 + bb;
+            acc[k] = __builtin_fma((double)gv[a], py[bb], acc[k]);
+          }
+    }
   }
-  red[ph][ol] = s;
-  __syncthreads();
-  for (int w = 8; w > 0; w >>= 1) {
-    if (ph < w) red[ph][ol] += red[ph + w][ol];
-    __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 28; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o, PD_WAVE);
+    if (ph == 0 && i < M.N && k < M.K) M.grad[(size_t)i * M.K + k] = v * (M.grad_scale * M.grad_sign);
   }
-  if (ph == 0 && o < M.N * M.K) M.grad[o] = red[0][ol] * (M.grad_scale * M.grad_sign);
 }
 
 // ---------------------------------------------------------------------------

@@ -98,7 +98,8 @@ struct MapDev {
   void *T3;                         // [rows][3][Npad][8] bf16 pieces of the row
                                     // coefficients C_a (a <= d, zero beyond)
   float *lse32;                     // [rows * W] base-2 log-sum-exp of the evaluated pixels
-  float *part_g32;                  // [chunks][Npad][32] partial gradient moments
+  float *part_g32;                  // [rows][Npad][8] per-row gradient moments
+                                    // sum_c w_i(r, c) P_a(x1_c) of the BF16 path
   int32_t n32, tiles32;             // evaluated pixels rounded up to 32; 32-pixel
                                     // tiles (ceil(W / 32) per row)
   int32_t a16_items, b16_items;     // blocks of k16_lse; waves of k16_grad
