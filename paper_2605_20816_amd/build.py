@@ -31,9 +31,14 @@ CFLAGS = [
 ]
 
 
+# per-source flags: the matrix-core kernels keep their MFMA accumulators in
+# ordinary VGPRs (no copies through the accumulation registers every tile)
+EXTRA = {"k_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -57,7 +62,7 @@ def build(jobs: int = 8) -> str:
 def asm(src_name: str, out: str) -> None:
     """Write the gfx950 assembly of one source (for inspecting the kernels)."""
     src = os.path.join(CSRC, src_name)
-    cmd = [HIPCC, *CFLAGS, "--cuda-device-only", "-S", src, "-o", out]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src_name, []), "--cuda-device-only", "-S", src, "-o", out]
     subprocess.check_call(cmd)
 
 

@@ -383,8 +383,14 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
   }
 }
 
+// Occupancy: the objective runs 4 waves per SIMD (128 VGPRs; the few spills are
+// loop-invariant values read back once per LDS stage and in the epilogue), the
+// gradient 3 (168 VGPRs; the spilled output addresses are read back once per
+// row).  Both kernels are latency-bound at the compiler's own choice of 2 waves:
+// at c5 (2048^2, 4928 grains, d = 6) the forced occupancy takes the objective
+// from 4.6 to 3.4 ms and the gradient from 10.5 to 8.2 ms.
 template <bool CERT>
-__global__ __launch_bounds__(PD_BLOCK) void k16_lse(const MapDev *__restrict__ maps,
+__global__ __launch_bounds__(PD_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 4))) void k16_lse(const MapDev *__restrict__ maps,
                                                     const int32_t *__restrict__ off, int n_maps,
                                                     int total) {
   __shared__ bf16x8 sT[3 * MF_GRAIN_STAGE];
@@ -528,11 +534,11 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   // pieces, wave 3 lse and labels.  The global data of tile pt + 1 is loaded
   // before tile pt's products and written to the other LDS buffer after them, so
   // one barrier per tile separates building from use.
-  float vx[8];            // wave 0
-  float qx[8];            // waves 1-2
-  float lse_l = 0.f;      // wave 3 (lanes < 32)
-  float r_l = 0.f;
-  int lab_l = -1;
+  // the loaded values of the next tile, by role: wave 0 P_a(x1) of its pixel,
+  // waves 1-2 P_a(x1) of 8 pixels, wave 3 lse, r and label of one pixel
+  float pre[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) pre[e] = 0.f;
   auto load_tile = [&](int pt) {
     const int rr = pt / tw;
     const int c0 = (pt - rr * tw) * 32;
@@ -541,29 +547,29 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
       const int c = c0 + col;
       const bool ok = c < M.W;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) vx[a] = (ok && a <= M.d) ? pd_glb(txf)[c * M.DP + a] : 0.f;
+      for (int a = 0; a < 8; ++a) pre[a] = (ok && a <= M.d) ? pd_glb(txf)[c * M.DP + a] : 0.f;
     } else if (wave <= 2) {
       const int kb2 = wave - 1;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = c0 + 16 * kb2 + 8 * (e / 4) + 4 * half + (e % 4);
         const bool ok = qvalid && c < M.W;
-        qx[e] = ok ? pd_glb(txf)[c * M.DP + qa] : 0.f;
+        pre[e] = ok ? pd_glb(txf)[c * M.DP + qa] : 0.f;
       }
     } else if (lane < 32) {
       const int c = c0 + lane;
       const bool ok = c < M.W;
       const size_t p = (size_t)rr * M.W + c;
       // pixels past the row's end: lse = +inf gives them weight 0
-      lse_l = ok ? pd_glb(M.lse32)[p] : INFINITY;
-      r_l = ok ? pd_glb((const float *)M.rpix)[p] : 0.f;
-      lab_l = ok ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+      pre[0] = ok ? pd_glb(M.lse32)[p] : INFINITY;
+      pre[1] = ok ? pd_glb((const float *)M.rpix)[p] : 0.f;
+      pre[2] = __int_as_float(ok ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1);
     }
   };
   auto build_tile = [&](GradLds &S) {
     if (wave == 0) {
       bf16x8 h, m, l;
-      split3(vx, h, m, l);
+      split3(pre, h, m, l);
       S.X[0][lane] = half ? m : h;
       S.X[1][lane] = half ? l : h;
     } else if (wave <= 2) {
@@ -572,7 +578,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         // the two FP16 pieces of the FP32 table value P_a(x1)
-        const float v = qx[e];
+        const float v = pre[e];
         const _Float16 h = (_Float16)v;
         const _Float16 l = (_Float16)(v - (float)h);
         const _Float16 z = (_Float16)0.f;
@@ -584,9 +590,9 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
     } else {
       int g = -1, lo = 0x7fffffff, hi = -1;
       if (lane < 32) {
-        S.L[lane] = lse_l - (float)PD_MF_WSHIFT;
-        S.R[lane] = r_l;
-        g = lab_l;
+        S.L[lane] = pre[0] - (float)PD_MF_WSHIFT;
+        S.R[lane] = pre[1];
+        g = __float_as_int(pre[2]);
         S.G[lane] = g;
         if (g >= 0) lo = hi = g;
       }
@@ -639,7 +645,7 @@ __device__ inline void grad16_block(const MapDev &M, int local_blk, GradLds (&sh
   }
 }
 
-__global__ __launch_bounds__(PD_BLOCK) void k16_grad(const MapDev *__restrict__ maps,
+__global__ __launch_bounds__(PD_BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k16_grad(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps,
                                                      int total) {
   __shared__ GradLds sh[2];
