@@ -63,9 +63,10 @@ typedef enum {
  *   PD_FP32: logits, running maxima and log-sum-exp formed in FP64 from FP64 row
  *            coefficients; exponentials and per-row partial sums in FP32; FP64
  *            reductions.
- *   PD_BF16: logit and gradient contractions on BF16 matrix cores (three-piece
- *            split logit operands, FP16 gradient weights, FP32 accumulation),
- *            FP32 log-sum-exp, FP64 reductions. */
+ *   PD_BF16: logit and gradient contractions on the matrix cores, per pixel row
+ *            on the row coefficients (three-piece bf16 logit operands, FP16
+ *            gradient weights, FP32 accumulation), FP32 log-sum-exp, FP64
+ *            reductions; degree <= 6. */
 typedef enum { PD_FP64 = 0, PD_FP32 = 1, PD_BF16 = 2 } pd_precision;
 
 /* Gauge of the fit (Lemma 4.2, Remark 4.3).  LAST_ZERO keeps theta_{N-1} = 0

@@ -174,6 +174,7 @@ void pd_plan_layout(EvalPlan &P, Arena &L, const pd_problem *probs, int n, int p
     const bool cert = P.cert;
     R.cert = L.take(cert ? 32 : 0);  // bound (8), uncertain count (4), canonical count (8)
     R.unc_list = L.take(cert ? sizeof(int32_t) * n_px : 0);
+    R.btile = L.take(cert && mf ? sizeof(float) * (size_t)(M.Npad / 32) : 0);
     R.onehot = L.take(mf ? 0 : sizeof(double) * (size_t)M.N * M.K);
     M.mask_words = (M.Npad / PD_WAVE + 31) / 32;  // far-field mask: at most 4 words
     R.nearmask_on = !mf && M.mask_words <= 4;
@@ -231,11 +232,13 @@ void pd_plan_bind(EvalPlan &P, char *base, const double *const *theta, double *p
       M.unc_count = (int32_t *)(base + R.cert + 8);
       M.fb_count = (int64_t *)(base + R.cert + 16);
       M.unc_list = (int32_t *)(base + R.unc_list);
+      M.btile = (float *)(base + R.btile);
     } else {
       M.cert = nullptr;
       M.unc_count = nullptr;
       M.fb_count = nullptr;
       M.unc_list = nullptr;
+      M.btile = nullptr;
     }
     M.onehot = P.onehot_pre && P.prec != 2 ? (double *)(base + R.onehot) : nullptr;
     M.order = R.sorted ? (const int32_t *)(base + R.order) : nullptr;

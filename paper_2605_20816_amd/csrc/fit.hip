@@ -1797,8 +1797,10 @@ static pd_status fit_level(pd_ctx *ctx, const pd_problem *probs, int32_t n,
     f.phi_t = phi_t + p;
     f.cscale = -PD_LOG2E / M.eps;
     f.cert = P.cert ? 1 : 0;
-    // per-wave counts of the certified objective (k16_lse waves on the BF16 path)
-    f.c_items = P.cert ? (prec == 2 ? 4 * M.a16_items : M.a_items) : M.a_items / PD_WAVES_PER_BLOCK;
+    // per-wave counts of the certified objective (on the BF16 path those of
+    // k16_lse or of its FP64 fallback k16_recert, the rest zeroed)
+    f.c_items = P.cert ? (prec == 2 ? std::max(M.a_items, 4 * M.a16_items) : M.a_items)
+                       : M.a_items / PD_WAVES_PER_BLOCK;
     f.nchunk = coff[p + 1] - coff[p];
     f.split = f.nchunk > 0 ? 1 : 0;
     if (f.split) {

@@ -104,13 +104,14 @@ __device__ inline f32x16 mfma3(const bf16x8 &y1, const bf16x8 &y2, const bf16x8 
 }
 
 // ---------------------------------------------------------------------------
-// Rounding bound of grain i's logits for the certified arg-max of a fit: the
-// FP64 row-factorised logits against the canonical scores (as for the FP64
-// objective: 2D + 8 roundings of the row-coefficient form, K + 4 of the canonical
-// dot product, both relative to sum |thc| resp. (log2 e / eps) sum |theta|, with
-// |P_a| <= 1), plus 2^-17 sum |thc| for the matrix-core logits that rank the
-// chunks (piece splitting and dropped products below 2^-24 of sum |thc|, the FP32
-// tables 2^-24, at most 48 FP32 roundings in the three products: < 2^-18.3).
+// Rounding bounds of grain i's logits for the certified arg-max of a fit.
+// cert_bound16: the FP64 row-factorised logits against the canonical scores (as
+// for the FP64 objective: 2D + 8 roundings of the row-coefficient form, K + 4 of
+// the canonical dot product, relative to sum |thc| resp. (log2 e / eps) sum
+// |theta|, with |P_a| <= 1).  mfma_bound16: the matrix-core logits against the
+// exact ones, 2^-17 sum |thc| (piece splitting and dropped products below 2^-24
+// of sum |thc|, the FP32 tables 2^-24, at most 48 FP32 roundings in the three
+// products: < 2^-18.3).
 __device__ inline double cert_bound16(const MapDev &M, int i) {
   const double *th = M.thc + (size_t)i * M.K;
   const double *x = M.theta + (size_t)i * M.K;
@@ -120,15 +121,22 @@ __device__ inline double cert_bound16(const MapDev &M, int i) {
     b += fabs(x[k]);
   }
   constexpr double u = 0x1p-53;
-  return 2.0 * ((2 * M.d + 8) * u * a + (PD_LOG2E / M.eps) * (M.K + 4) * u * b) + 0x1p-17 * a;
+  return 2.0 * ((2 * M.d + 8) * u * a + (PD_LOG2E / M.eps) * (M.K + 4) * u * b);
+}
+__device__ inline float mfma_bound16(const MapDev &M, int i) {
+  const double *th = M.thc + (size_t)i * M.K;
+  double a = 0.0;
+  for (int k = 0; k < M.K; ++k) a += fabs(th[k]);
+  return (float)(0x1p-17 * a);
 }
 
 // Row coefficients C_a(r, i) = sum_b thc_i(a, b) P_b(x2_r) in FP64 for every
 // evaluated row and grain, stored as three bf16 pieces: T3[rr][piece][Npad][8]
 // (zero for a > d and for padding grains).  For the certified arg-max of a fit
 // (M.cert set) also the FP64 values, C[rr][i][a] (a <= d), and, in the blocks of
-// the first row, the largest logit rounding bound over the grains (block
-// maximum, one atomic per block; the fit clears the slot after each evaluation).
+// the first row, the largest FP64 rounding bound over the grains (block maximum,
+// one atomic per block; the fit clears the slot after each evaluation) and per
+// 32-grain tile the largest matrix-core bound (btile).
 __global__ __launch_bounds__(PD_BLOCK) void k16_prep(const MapDev *__restrict__ maps,
                                                      const int32_t *__restrict__ off, int n_maps) {
   const int m = pd_find_map(off, n_maps, blockIdx.x);
@@ -138,6 +146,12 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_prep(const MapDev *__restrict__ 
   if (M.cert != nullptr && (long long)(blockIdx.x - off[m]) * PD_BLOCK < M.Npad) {
     __shared__ double bred[PD_BLOCK];
     bred[threadIdx.x] = e < M.N ? cert_bound16(M, (int)e) : 0.0;
+    // the tile maximum over 32 consecutive grains (lanes of one wave half; N_pad
+    // is a multiple of 64)
+    float bt = e < M.N ? mfma_bound16(M, (int)e) : 0.f;
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) bt = fmaxf(bt, __shfl_xor(bt, o, PD_WAVE));
+    if (e < M.Npad && (e & 31) == 0) M.btile[e / 32] = bt;
     __syncthreads();
     for (int w = PD_BLOCK / 2; w > 0; w >>= 1) {
       if (threadIdx.x < w) {
@@ -188,14 +202,14 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_prep(const MapDev *__restrict__ 
 // ---------------------------------------------------------------------------
 // With CERT, also the hard assignment of every pixel at this theta, certified
 // against the canonical FP64 arg-min (Section 2.1): each lane keeps, per pixel,
-// the largest maximum of its 16-grain chunks (its chunk) and the largest of the
-// other chunks' maxima, from the matrix-core logits; at the end the best chunk's
-// 16 logits are formed again in FP64 from the FP64 row coefficients.  If the
-// best grain leads the runner-up (the chunk's second, the other half's best, or
-// the other chunks' maxima, which bound theirs within the matrix-core error)
-// by more than twice the rounding bound of cert_bound16, the canonical scores
-// have the same strict minimum there; otherwise the pixel is listed for
-// k_assign_list.  Per-wave counts of certified correct pixels go to part_c.
+// its 16-grain chunk with the largest matrix-core maximum and the largest upper
+// bound of the other chunks' exact logits (chunk maximum plus the tile's
+// matrix-core bound); at the end the best chunk's 16 logits are formed again in
+// FP64 from the FP64 row coefficients.  If the best grain leads the runner-up
+// (the chunk's second, the other half's best, or that upper bound) by more than
+// twice the FP64 rounding bound of cert_bound16, the canonical scores have the
+// same strict minimum there; otherwise the pixel is listed for k_assign_list.
+// Per-wave counts of certified correct pixels go to part_c.
 template <bool CERT>
 __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
   constexpr int TPW = MF_TILES_PER_WAVE;
@@ -210,8 +224,11 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
   bf16x8 xa[TPW], xb[TPW];
   float mrun[TPW], S[TPW];
   int lab[TPW];
-  float bv[TPW], sv[TPW];  // CERT: best chunk maximum, largest other chunk maximum
-  int bi[TPW];             // CERT: grain base of the best chunk
+  // CERT: the two chunks with the largest matrix-core maxima (maximum, upper
+  // bound of the exact logits = maximum plus the tile's matrix-core bound, grain
+  // base) and the largest such upper bound of the other chunks
+  float bv[TPW], bvu[TPW], b2v[TPW], b2u[TPW], sv[TPW];
+  int bi[TPW], b2i[TPW];
   int ntile = 0;  // this wave's tiles that start inside the row (wave-uniform)
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
@@ -224,8 +241,12 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
     mrun[t] = -INFINITY;
     S[t] = 0.f;
     bv[t] = -INFINITY;
+    bvu[t] = -INFINITY;
+    b2v[t] = -INFINITY;
+    b2u[t] = -INFINITY;
     sv[t] = -INFINITY;
-    bi[t] = 0;
+    bi[t] = -1;
+    b2i[t] = -1;
     lab[t] = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
   }
   const bf16x8 *T = (const bf16x8 *)M.T3 + (size_t)rr * 3 * M.Npad;
@@ -245,6 +266,7 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
       const bf16x8 y1 = half ? yh : ym, y2 = half ? yh : yl, y3 = half ? ym : yh;
       const int gbase = g0 + gt;
       const bool partial = gbase + 32 > M.N;
+      const float btl = CERT ? pd_uni(M.btile)[gbase / 32] : 0.f;
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         if (t >= ntile) break;
@@ -266,10 +288,16 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
         // also avoids exp2(-inf - (-inf)) while this lane's maximum is still -inf
         if (cm == -INFINITY) continue;
         if constexpr (CERT) {
-          const bool gt = cm > bv[t];
-          sv[t] = gt ? bv[t] : fmaxf(sv[t], cm);
-          bi[t] = gt ? gbase : bi[t];
-          bv[t] = gt ? cm : bv[t];
+          const float cu = cm + btl;
+          const bool gt1 = cm > bv[t];
+          const bool gt2 = !gt1 && cm > b2v[t];
+          sv[t] = fmaxf(sv[t], (gt1 || gt2) ? b2u[t] : cu);
+          b2v[t] = gt1 ? bv[t] : (gt2 ? cm : b2v[t]);
+          b2u[t] = gt1 ? bvu[t] : (gt2 ? cu : b2u[t]);
+          b2i[t] = gt1 ? bi[t] : (gt2 ? gbase : b2i[t]);
+          bv[t] = gt1 ? cm : bv[t];
+          bvu[t] = gt1 ? cu : bvu[t];
+          bi[t] = gt1 ? gbase : bi[t];
         }
         const float mn = fmaxf(mrun[t], cm);
         float s = S[t] * __builtin_amdgcn_exp2f(mrun[t] - mn);
@@ -299,19 +327,22 @@ __device__ inline void lse16_block(const MapDev &M, int blk, bf16x8 *sT) {
     if constexpr (CERT) {
       const int c = (seg * MF_SEG_TILES + 4 * t + wave) * 32 + col;
       const bool valid = c < M.W;
-      // FP64 logits of this lane's best chunk: grains bi + 8 (j / 4) + 4 half + j % 4
+      // FP64 logits of this lane's two best chunks: grains base + 8 (j / 4) +
+      // 4 half + j % 4; v1 (grain j1) and v2 the largest two of them
       double v1 = -INFINITY, v2 = -INFINITY;
       int j1 = -1;
-      if (valid && bv[t] > -INFINITY) {
+      if (valid) {
         const double *px = M.tx64 + (size_t)c * M.DP;
         double pa[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) pa[a] = a <= M.d ? px[a] : 0.0;
         const double *C = (const double *)M.C + (size_t)rr * M.Npad * M.DP;
 #pragma unroll 1
-        for (int j = 0; j < 16; ++j) {
-          const int g = bi[t] + (j / 4) * 8 + half * 4 + (j % 4);
-          if (g >= M.N) continue;
+        for (int q = 0; q < 32; ++q) {
+          const int base = q < 16 ? bi[t] : b2i[t];
+          const int j = q & 15;
+          const int g = base + (j / 4) * 8 + half * 4 + (j % 4);
+          if (base < 0 || g >= M.N) continue;
           const double *cp = C + (size_t)g * M.DP;
           double v = cp[0];
 #pragma unroll
@@ -711,6 +742,121 @@ __global__ __launch_bounds__(PD_BLOCK) void k16_reduce(const MapDev *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Fallback of the certified arg-max of a BF16 fit.  Late in a fit sum |thc| can
+// grow so large that the matrix-core bound of k16_lse exceeds the logit gaps at
+// most pixels; then every pixel is decided again from the FP64 row coefficients
+// alone (d + 1 FMAs per pair, FP64 bound), so that only the few pixels that
+// this leaves undecided go to the canonical scan.  The flag (bytes 12..15 of the
+// certificate slot) is set by k16_recheck_gate when k16_lse left more than 1/16
+// of the map's pixels undecided; the gate also clears the list for the new pass
+// and zeroes the count slots that neither pass writes.
+__global__ void k16_recheck_gate(const MapDev *__restrict__ maps, int n_maps) {
+  const MapDev &M = maps[blockIdx.x];
+  if ((int)blockIdx.x >= n_maps || PD_GATED(M) || M.cert == nullptr) return;
+  int32_t *flag = (int32_t *)((char *)M.cert + 12);
+  const long long n_px = (long long)M.rows * M.W;
+  const bool redo = (long long)*M.unc_count > (n_px >> 4);
+  __syncthreads();  // every thread has read the count
+  const int c_items = max(M.a_items, 4 * M.a16_items);
+  for (int t = (redo ? M.a_items : 4 * M.a16_items) + threadIdx.x; t < c_items; t += blockDim.x)
+    M.part_c[t] = 0;
+  if (threadIdx.x == 0) {
+    *flag = redo ? 1 : 0;
+    if (redo) *M.unc_count = 0;
+  }
+}
+
+// One wave per 64-pixel row segment (the FP64 objective's work list), lanes =
+// pixels: the logits of grains in chunks of 8 from the FP64 row coefficients
+// (wave-uniform loads), the largest chunk maximum, its chunk and the largest of
+// the others; then the best chunk again, and the gap to the runner-up against
+// twice the FP64 bound of cert_bound16.
+template <int D>
+__device__ inline void recert_item(const MapDev &M, int local, int lane) {
+  constexpr int DP = D + 1;
+  if (local >= M.rows * M.segs) {
+    if (lane == 0) pd_glb(M.part_c)[local] = 0;
+    return;
+  }
+  const int lr = local / M.segs;
+  const int r = M.row0 + lr;
+  const int c = (local - lr * M.segs) * PD_WAVE + lane;
+  const bool valid = c < M.W;
+  const int cc = valid ? c : M.W - 1;
+  double px[DP];
+#pragma unroll
+  for (int a = 0; a < DP; ++a) px[a] = M.tx64[(size_t)cc * DP + a];
+  const auto Crow = pd_uni((const double *)M.C + (size_t)lr * M.Npad * DP);
+  const int g = valid ? pd_glb(M.labels)[(size_t)r * M.W + c] : -1;
+  auto logit = [&](int i) {
+    const auto cp = Crow + (size_t)i * DP;
+    double v = cp[0];
+#pragma unroll
+    for (int a = 1; a < DP; ++a) v = __builtin_fma(cp[a], px[a], v);
+    return v;
+  };
+  double bv = -INFINITY, sv = -INFINITY;
+  int bi = 0;
+  const int nfull = M.N & ~7;
+  for (int i0 = 0; i0 < M.N; i0 += 8) {
+    double cm = -INFINITY;
+    if (i0 < nfull) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cm = fmax(cm, logit(i0 + j));
+    } else {
+      for (int j = 0; i0 + j < M.N; ++j) cm = fmax(cm, logit(i0 + j));
+    }
+    const bool gt = cm > bv;
+    sv = gt ? bv : fmax(sv, cm);
+    bi = gt ? i0 : bi;
+    bv = gt ? cm : bv;
+  }
+  double v1 = -INFINITY, v2 = -INFINITY;
+  int j1 = -1;
+#pragma unroll 1
+  for (int j = 0; j < 8; ++j) {
+    if (bi + j >= M.N) break;
+    const double v = logit(bi + j);
+    if (v > v1) {
+      v2 = v1;
+      v1 = v;
+      j1 = bi + j;
+    } else {
+      v2 = fmax(v2, v);
+    }
+  }
+  const double bound = __longlong_as_double((long long)*pd_uni((const unsigned long long *)M.cert));
+  const bool sure = (v1 - fmax(v2, sv)) > 2.0 * bound;  // false for NaN
+  const long long ok = (valid && sure && j1 == g) ? 1 : 0;
+  const bool unsure = valid && !sure;
+  const unsigned long long um = __ballot(unsure);
+  if (um != 0) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(M.unc_count, __popcll(um));
+    base = __shfl(base, 0, PD_WAVE);
+    const int pos = base + __popcll(um & ((1ull << lane) - 1ull));
+    if (unsure && pos < M.rows * M.W) pd_glb(M.unc_list)[pos] = r * M.W + c;
+  }
+  const long long wc = pd_wave_sum_i64(ok);
+  if (lane == 0) pd_glb(M.part_c)[local] = wc;
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(PD_BLOCK) void k16_recert(const MapDev *__restrict__ maps,
+                                                       const int32_t *__restrict__ off,
+                                                       int n_maps, int total) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / PD_WAVE);
+  const int lane = threadIdx.x % PD_WAVE;
+  const int item = pd_xcd_block(blockIdx.x, gridDim.x) * PD_WAVES_PER_BLOCK + wave;
+  if (item >= total) return;
+  const int m = pd_find_map(off, n_maps, item);
+  const MapDev &M = maps[m];
+  if (PD_GATED(M) || M.cert == nullptr) return;
+  if (*pd_uni((const int32_t *)((const char *)M.cert + 12)) == 0) return;
+  PD_DISPATCH_UPTO(DMAX, M.d, (recert_item<D>(M, item - off[m], lane)));
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
@@ -733,8 +879,22 @@ void pd_bf16_launch(const EvalPlan &P, int stage, hipStream_t s) {
 void pd_bf16_plan_eval(pd_ctx *, const EvalPlan &P, hipStream_t s, bool center) {
   if (center) pd_launch_center(P.d_maps, P.n, P.max_k, s);
   for (int st = 0; st < 4; ++st) pd_bf16_launch(P, st, s);
-  // the pixels that the certified arg-max of k16_lse left undecided
-  if (P.cert) pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
+  if (P.cert) {
+    // the FP64 fallback where k16_lse left many pixels undecided, then the
+    // canonical scan of the pixels still undecided
+    k16_recheck_gate<<<P.n, PD_WAVE, 0, s>>>(P.d_maps, P.n);
+    const int total = P.offA[P.n];
+    if (total > 0)
+    {
+      const int blocks = (total + PD_WAVES_PER_BLOCK - 1) / PD_WAVES_PER_BLOCK;
+      switch (P.dmax) {
+        case 2: k16_recert<2><<<blocks, PD_BLOCK, 0, s>>>(P.d_maps, P.d_offA, P.n, total); break;
+        case 4: k16_recert<4><<<blocks, PD_BLOCK, 0, s>>>(P.d_maps, P.d_offA, P.n, total); break;
+        default: k16_recert<6><<<blocks, PD_BLOCK, 0, s>>>(P.d_maps, P.d_offA, P.n, total); break;
+      }
+    }
+    pd_launch_assign_list(P.dmax, P.d_maps, P.n, s);
+  }
 }
 
 pd_status pd_bf16_objective_grad(pd_ctx *ctx, const pd_problem *probs, int n,

@@ -48,7 +48,7 @@ struct Arena {
 
 struct MapRegions {
   size_t tx64, ty64, txT, tyT, thc, C, lse, rpix, part_l, part_g, part_c, T3, lse32, part_g32, part_d,
-      onehot, cert, unc_list, order, pos, order_sums, nearmask;
+      onehot, cert, unc_list, btile, order, pos, order_sums, nearmask;
   bool sorted, nearmask_on;
 };
 

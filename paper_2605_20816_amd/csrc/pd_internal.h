@@ -90,6 +90,8 @@ struct MapDev {
   // (k_assign_list), whose correct ones are counted in fb_count
   double *cert;
   int32_t *unc_list, *unc_count;    // [rows * W] pixel indices; their number
+  float *btile;                     // BF16 fits: per 32-grain tile, the largest error
+                                    // bound of its grains' matrix-core logits
   int64_t *fb_count;
   // optional gate: when non-null and zero, every kernel skips this map
   const int32_t *gate;

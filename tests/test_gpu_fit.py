@@ -226,6 +226,24 @@ def test_bf16_fit_accuracy_is_the_canonical_one(pd, orc, d, eps, iters):
     assert nc / (gm.H * gm.W) == rep["acc"]
 
 
+def test_bf16_fit_accuracy_with_large_coefficients(pd, orc):
+    """A start with large coefficients (sum |thc| ~ 1e6 at eps = 1e-3): the
+    matrix-core bound then exceeds the logit gaps at most pixels, the FP64 pass
+    over the row coefficients decides them, and the reported accuracy is still
+    exactly the oracle's count at the returned iterate."""
+    pdl, ctx = pd
+    d, eps = 4, 1e-3
+    gm = poly_map(91, 96, 80, 40, d)
+    K = pdl.num_features(d)
+    th0 = np.random.default_rng(92).normal(scale=30.0, size=(gm.N, K))
+    th = dev(th0)
+    rep = ctx.fit([problem(pdl, gm, d, eps)], [th], "bf16", init="given", max_iter=3,
+                  target_acc=2.0)[0]
+    _, nc, _ = orc.assign(th.cpu().numpy(), gm.H, gm.W, d, gm.labels)
+    print(f"large start: {rep['iters']} iterations, accuracy {rep['acc']:.4f}")
+    assert nc / (gm.H * gm.W) == rep["acc"]
+
+
 def test_given_start_is_moved_into_the_gauge(pd, orc):
     """Lemma 4.2: a given start enters the gauge theta_{N-1} = 0 by the common
     shift -theta_{N-1}, which leaves Phi unchanged (not by zeroing the row)."""
